@@ -1,0 +1,220 @@
+/*
+ * cosm.h -- C ABI of libcosm, an MI355X (gfx950) implementation of the sweep of
+ * Cosm ("Collective Switched Motion for Fast and Accurate Sparse Ising
+ * Optimization", Zick, Shukla, Marakov).
+ *
+ * The problem (Eq. (1)): spins s_i in {-1,+1}, i < n; sparse couplings J on m
+ * undirected edges (u_k, v_k); optional bias h.  H(s) = -sum_k J_k s_u s_v -
+ * sum_i h_i s_i.  The Max-Cut form (Appendix A, Eq. (14)) uses w = -J, so
+ * cut(s) = sum over edges with s_u != s_v of (-J_k).
+ *
+ * The method (Algorithm 1): a proper edge colouring splits the edges into C
+ * matchings (Eqs. (9)-(11)); every replica keeps one phase per spin on the
+ * circle; a sweep applies the pair update of Eq. (6) to every edge of class 0,
+ * then class 1, ..., class C-1 (Eqs. (12)-(13)); every dwt_period sweeps the
+ * dual window twist rotates the phases inside two opposing windows centred at
+ * a random angle (Sec. II-D); the step size ramps linearly from alpha0 to 0,
+ * constant within a sweep (Sec. II-B, Appendix B); after the last sweep the
+ * phases are cut by B equally spaced bisectors and the lowest-energy spin
+ * vector is kept.
+ *
+ * Conventions for every function:
+ *   - Return value: COSM_OK (0) or a negative COSM_E* status; no exception or
+ *     abort crosses the ABI.  cosm_last_error() gives a message for the last
+ *     failing call on the calling thread.
+ *   - Host pointers are read during the call only; the caller keeps ownership
+ *     and may free them afterwards.  Output arrays are caller-allocated.
+ *   - A cosm_state is owned by the library, released by cosm_destroy, and must
+ *     not be used from two host threads at once.  Separate states are
+ *     independent.
+ *   - Every GPU operation of a state is enqueued on the hip stream given to
+ *     cosm_init.  Functions that return host values synchronise that stream.
+ *   - Phases live on the device as turns in [0, 1) (1 turn = 360 degrees).
+ */
+#ifndef COSM_H
+#define COSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+enum {
+  COSM_OK = 0,
+  COSM_EINVAL = -1,  /* bad argument: NULL, out of range, self-loop, bad spin value */
+  COSM_EDUP = -2,    /* duplicate undirected edge */
+  COSM_ECOLOR = -3,  /* colouring is not proper or does not cover every edge */
+  COSM_ERANGE = -4,  /* request exceeds a limit (sweeps past S, LDS capacity, sizes) */
+  COSM_ENOMEM = -5,  /* device or host allocation failed, or workspace too small */
+  COSM_EDEVICE = -6, /* HIP runtime error */
+  COSM_ESTATE = -7   /* call not valid in the state's current condition */
+};
+
+/* ---- enumerations ---------------------------------------------------------- */
+enum { COSM_COLOR_GREEDY = 0, COSM_COLOR_MISRA_GRIES = 1, COSM_COLOR_TORUS = 2 };
+enum { COSM_STORE_FP32 = 0, COSM_STORE_FP16 = 1, COSM_STORE_BF16 = 2 };
+/* Where a replica's phases live during a sweep.  LDS: a workgroup holds whole
+ * replicas in LDS for all sweeps of a call.  HBM: phases stay in device memory,
+ * one launch per colour class.  PLAIN: one replica per launch, one launch per
+ * colour class (the unbatched baseline). */
+enum { COSM_RES_AUTO = 0, COSM_RES_LDS = 1, COSM_RES_HBM = 2, COSM_RES_PLAIN = 3 };
+/* GRID: every phase, step and angle is a multiple of 2^-23 turn, so FP32 sweeps
+ * are exact.  CONTINUOUS: the literal ramp alpha0 (S - t + 1) / S in FP32. */
+enum { COSM_SCHED_GRID = 0, COSM_SCHED_CONTINUOUS = 1 };
+/* SCS: Eqs. (12)-(13), classes one after another.  FULL_GRADIENT: Eq. (8), all
+ * edges read the same state (the "without SCS" variant of Table VII). */
+enum { COSM_UPDATE_SCS = 0, COSM_UPDATE_FULL_GRADIENT = 1 };
+/* Readout rule (Algorithm 1, binarization).  BISECTORS: B equally spaced
+ * bisectors.  OPTIMAL: the best of all distinct bisectors (every position where
+ * some spin changes side), the alternative the paper cites from Burer et al. */
+enum { COSM_READOUT_BISECTORS = 0, COSM_READOUT_OPTIMAL = 1 };
+enum { COSM_UNIT_TURNS = 0, COSM_UNIT_DEGREES = 1, COSM_UNIT_RADIANS = 2 };
+
+/* ---- parameters (Tables IX-XI) --------------------------------------------- */
+typedef struct {
+  double alpha0_deg;        /* initial step size, degrees (14 in Table IX) */
+  double dwt_ratio;         /* twist = dwt_ratio * alpha_t (Table X: 0.5 / 1.0 / 1.5) */
+  int32_t dwt_period;       /* twist after sweeps t with t % period == 0; 0 = never */
+  double dwt_window_deg;    /* width of each of the two windows (90 in Table IX) */
+  int32_t n_bisectors;      /* B (100 in Table IX); forced to 1 when h is given */
+  int64_t sweeps_per_trial; /* S: the schedule length */
+  int32_t schedule;         /* COSM_SCHED_* */
+  int32_t storage;          /* COSM_STORE_*: phase storage; arithmetic is FP32 */
+  int32_t residency;        /* COSM_RES_* */
+  int32_t replicas_per_wg;  /* LDS form: replicas per workgroup; 0 = autotune */
+  int32_t threads_per_wg;   /* LDS form: threads per workgroup; 0 = autotune */
+  int32_t update;           /* COSM_UPDATE_* */
+  int32_t readout;          /* COSM_READOUT_* */
+} cosm_params;
+
+/* Fill *p with Table IX/X defaults: alpha0 14, ratio 0.5, period 3, window 90,
+ * B 100, S 1000, GRID, FP32, AUTO, autotuned shape, SCS, BISECTORS. */
+void cosm_default_params(cosm_params *p);
+
+typedef struct cosm_state cosm_state;
+
+/* ---- partitions (Sec. II-B, Eqs. (9)-(11)) -------------------------------- */
+/* Proper edge colouring of the graph with n vertices and m edges (eu[k], ev[k]).
+ *   method GREEDY: edges in input order, each gets the lowest colour free at
+ *     both endpoints (Sec. II-B); at most 2*Delta - 1 colours.
+ *   method MISRA_GRIES: Misra-Gries fan/path recolouring; at most Delta + 1.
+ *   method TORUS: the regular lattice pattern (Sec. II-B); method_args =
+ *     {Lx, Ly}, vertex (r, c) = r*Lx + c; every edge must join lattice
+ *     neighbours.  Horizontal edges with even / odd left column get colours 0 /
+ *     1, vertical edges with even / odd upper row 2 / 3; with an odd side the
+ *     wrap-around edges of that direction get their own colour (4 horizontal,
+ *     5 vertical), the remaining colours are renumbered to stay contiguous.
+ * colour_out[m] (caller-owned) receives the class of every edge; class indices
+ * are also the order in which a sweep applies them.  *num_colours_out = C.
+ * Errors: EINVAL (NULL, n < 1, endpoint out of range, self-loop, TORUS edge that
+ * is not a lattice edge), EDUP (repeated undirected edge). */
+int cosm_build_partitions(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                          int32_t method, const int32_t *method_args, int32_t *colour_out,
+                          int32_t *num_colours_out);
+
+/* ---- state ------------------------------------------------------------------ */
+/* Device bytes cosm_init needs when the caller supplies the workspace. */
+int cosm_workspace_bytes(int32_t n, int64_t m, int32_t num_colours, int32_t replicas,
+                         const cosm_params *p, size_t *bytes_out);
+
+/* Create a solver state: validates the graph and the colouring, copies them to
+ * the device, picks (or takes from p) the sweep kernel's shape, and draws the
+ * initial phases of replicas 0..replicas-1 (Algorithm 1, "Set x_i random"):
+ * Philox4x32-10 with key = seed, counter (i, 0, replica, "INIT").
+ *   J: Ising couplings (Eq. (1) sign), m entries.  h: n entries or NULL (h = 0).
+ *   colour / num_colours: as returned by cosm_build_partitions or any proper
+ *     colouring; classes are applied in index order.
+ *   hip_stream: a hipStream_t or NULL for the default stream.
+ *   device_workspace / workspace_bytes: device memory the state uses for all its
+ *     buffers (at least cosm_workspace_bytes), owned by the caller, kept alive
+ *     until cosm_destroy; NULL makes the library allocate its own.
+ * Errors: EINVAL, EDUP, ECOLOR (not a proper colouring), ERANGE (alpha0*|J|,
+ * dwt_ratio*alpha0 or the window not below a full turn; GRID with 2*dwt_ratio
+ * not an integer or a window off the 2^-23 turn grid; forced LDS residency that
+ * does not fit), ENOMEM, EDEVICE. */
+int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+              const int32_t *J, const int32_t *h, const int32_t *colour, int32_t num_colours,
+              const cosm_params *p, uint64_t seed, int32_t replicas, void *hip_stream,
+              void *device_workspace, size_t workspace_bytes);
+
+/* Release the state and everything the library allocated for it. */
+int cosm_destroy(cosm_state *s);
+
+/* Redraw the initial phases (sweep counter back to 0) for replicas with global
+ * indices replica_offset .. replica_offset+R-1 under a new seed.  Used to run
+ * successive trial batches. */
+int cosm_reset(cosm_state *s, uint64_t seed, int64_t replica_offset);
+
+/* ---- the sweep (Algorithm 1, main loop) ----------------------------------- */
+/* Run sweeps t+1 .. t+n_sweeps on every replica (t = sweeps already done),
+ * asynchronously on the state's stream.  ERANGE if t + n_sweeps > S. */
+int cosm_sweep(cosm_state *s, int64_t n_sweeps);
+
+/* ---- readout and energy (Algorithm 1 binarization; Eq. (1); Eq. (14)) ---- */
+/* spins == NULL: binarize the current phases of every replica (B bisectors
+ * beta_p = p/(2B) turn rounded to the grid, +1 on [beta_p, beta_p + 1/2),
+ * lowest H kept, lowest p on ties; with h a single semicircle centred at 0).
+ * spins != NULL: [R][n] int8 in {-1,+1} supplied by the caller; its energies.
+ * spins_out ([R][n] int8) may be NULL; H_out and cut_out ([R] int64) must not.
+ * Synchronises the stream.  EINVAL on a spin outside {-1,+1}. */
+int cosm_energy(cosm_state *s, const int8_t *spins, int8_t *spins_out, int64_t *H_out,
+                int64_t *cut_out);
+
+/* ---- trials and time to target (Appendix A, Eqs. (15)-(17)) --------------- */
+typedef struct {
+  int64_t trials;      /* replicas run */
+  int64_t successes;   /* replicas whose final H <= target */
+  double ps;           /* successes / trials */
+  double ps_lo, ps_hi; /* Wilson 95% interval of ps */
+  double r99;          /* Eq. (15); 1 for ps = 1, +inf for ps = 0 */
+  double t_trial_s;    /* batch wall time / replicas, init to readout inclusive */
+  double ttt_s;        /* Eq. (17): t_trial * R99 */
+  double stt_sweeps;   /* Eq. (16): S * R99 */
+  int64_t best_H;      /* lowest H seen */
+  int64_t best_cut;    /* its cut */
+} cosm_tts_result;
+
+/* Run batches of R independent trials (each: cosm_reset with the next replica
+ * offset, S sweeps, readout) until max_trials replicas have run, or after the
+ * first batch with a hit when stop_at_first_hit != 0.  best_spins ([n] int8)
+ * may be NULL.  Leaves the state holding the last batch. */
+int cosm_solve_to_target(cosm_state *s, int64_t target_H, int64_t max_trials,
+                         int32_t stop_at_first_hit, cosm_tts_result *out, int8_t *best_spins);
+
+/* ---- phase access ------------------------------------------------------------ */
+/* Copy the phases out as [R][n] doubles in the given unit (COSM_UNIT_*); turns
+ * and degrees are exact.  Synchronises the stream. */
+int cosm_get_phases(cosm_state *s, int32_t unit, double *out);
+/* Overwrite the phases from [R][n] doubles in the given unit (wrapped into one
+ * turn, rounded to the storage format) and set the sweep counter to t. */
+int cosm_set_phases(cosm_state *s, int32_t unit, const double *in, int64_t t);
+
+/* ---- introspection ---------------------------------------------------------- */
+typedef struct {
+  int32_t n, num_colours, replicas;
+  int64_t m, sweeps_done;
+  int32_t residency;       /* resolved COSM_RES_* */
+  int32_t storage;
+  int32_t replicas_per_wg; /* resolved */
+  int32_t threads_per_wg;  /* resolved */
+  int32_t workgroups;
+  int32_t lds_bytes;       /* dynamic LDS per workgroup */
+  int32_t max_class_edges;
+  int64_t sweep_launches;  /* sweep kernels launched so far */
+  double sweep_kernel_ms;  /* their summed duration (HIP events), when timing is on */
+} cosm_info;
+int cosm_get_info(const cosm_state *s, cosm_info *out);
+
+/* Time every sweep kernel with HIP events on the state's stream (on != 0). */
+int cosm_set_timing(cosm_state *s, int32_t on);
+
+const char *cosm_last_error(void);
+const char *cosm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COSM_H */

@@ -1,0 +1,19 @@
+"""MI355X (gfx950) implementation of the Cosm sweep: a thin Python binding over
+the C ABI of ``libcosm.so`` (declared in ``include/cosm.h``).
+
+Every step of the method runs in the library's HIP kernels; this package only
+marshals arguments.  PyTorch supplies device memory (the state's workspace)
+and the HIP stream.  Importing the package does not touch the GPU; creating a
+``State`` does, and fails loudly when the library has not been built.
+"""
+from .cosm import (  # noqa: F401
+    COLOR_GREEDY, COLOR_MISRA_GRIES, COLOR_TORUS,
+    RES_AUTO, RES_HBM, RES_LDS, RES_PLAIN,
+    READOUT_BISECTORS, READOUT_OPTIMAL,
+    SCHED_CONTINUOUS, SCHED_GRID,
+    STORE_BF16, STORE_FP16, STORE_FP32,
+    UNIT_DEGREES, UNIT_RADIANS, UNIT_TURNS,
+    UPDATE_FULL_GRADIENT, UPDATE_SCS,
+    CosmError, Params, State, TTSResult,
+    build_partitions, default_params, exported_symbols, library_path, load_library, version,
+)

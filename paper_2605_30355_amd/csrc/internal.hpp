@@ -1,0 +1,145 @@
+// internal.hpp -- declarations shared by the host side of libcosm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cosm.h"
+
+namespace cosm {
+
+// ---- errors ------------------------------------------------------------------
+// Every entry point returns a status; set_error records the message for
+// cosm_last_error() on the calling thread.
+int set_error(int status, const std::string &msg);
+void clear_error();
+
+#define COSM_HIP_CHECK(expr)                                                              \
+  do {                                                                                    \
+    hipError_t err_ = (expr);                                                             \
+    if (err_ != hipSuccess)                                                               \
+      return ::cosm::set_error(COSM_EDEVICE, std::string(#expr) + ": " +                  \
+                                                 hipGetErrorString(err_));                \
+  } while (0)
+
+// ---- graph checks and colourings (graph.cpp) --------------------------------------
+// EINVAL / EDUP with a message, or COSM_OK.  Fills degree[n] when non-null.
+int validate_graph(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                   std::vector<int32_t> *degree);
+// ECOLOR unless colour[] is a proper colouring with classes 0..C-1.
+int validate_colouring(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                       const int32_t *colour, int32_t C);
+int32_t colour_greedy(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                      int32_t *colour);
+int32_t colour_misra_gries(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                           int32_t *colour);
+// Returns C, or a negative status for a non-lattice edge.
+int32_t colour_torus(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, int32_t Lx,
+                     int32_t Ly, int32_t *colour);
+
+// ---- phase and schedule encoding ----------------------------------------------------
+// Phases are turns.  The grid quantum is 2^-23 turn; step sizes live on the
+// 2^-22 grid so that half a step stays on the 2^-23 grid.
+constexpr double kTwo23 = 8388608.0;
+constexpr double kTwo22 = 4194304.0;
+
+// Scalars a sweep kernel needs to evaluate the schedule of sweep t on the device.
+struct Schedule {
+  int32_t grid;          // COSM_SCHED_GRID ?
+  int64_t S;             // schedule length
+  // grid: alpha_units(t) = floor((a0 * (S - t + 1) + S/2) / S), units of 2^-22 turn
+  int64_t a0_units;
+  int32_t twist_num2;    // 2 * dwt_ratio (grid)
+  // continuous
+  float alpha0_turns;
+  float dwt_ratio;
+  int32_t dwt_period;    // 0: never
+  float window2;         // 2 * window width in turns (membership threshold)
+  float window;          // window width in turns
+};
+
+// ---- the device-side problem description -----------------------------------------
+// Per-class edge descriptors for the LDS kernel: 32-bit word of LDS slots
+// (slot_u | slot_v << 16) and the coupling as a float.
+struct EdgeDesc {
+  uint32_t slots;
+  float J;
+};
+
+struct DeviceBuffers {
+  void *phases = nullptr;       // [n][R] float or 16-bit, replica-major
+  EdgeDesc *desc = nullptr;     // LDS-form descriptors, grouped by class
+  int32_t *class_off = nullptr; // [C+1] offsets into desc
+  int32_t *slot_vertex = nullptr; // [n_slots] vertex held by each LDS slot
+  int32_t *eu = nullptr;        // [m] (original ids)
+  int32_t *ev = nullptr;
+  int32_t *J = nullptr;
+  int32_t *h = nullptr;         // [n] or null
+  int32_t *peu = nullptr;       // [m] edges grouped by class, original ids (plain / HBM forms)
+  int32_t *pev = nullptr;
+  float *pJ = nullptr;
+  int8_t *spins = nullptr;      // [R][n]
+  int64_t *H = nullptr;         // [R]
+  int64_t *cut = nullptr;       // [R]
+  int32_t *best_p = nullptr;    // [R]
+  // full-gradient form: incidence lists and a second phase buffer
+  int32_t *inc_off = nullptr;   // [n+1]
+  uint32_t *inc_nbr = nullptr;  // [2m] neighbour | (1u << 31 when the vertex is the edge's u)
+  float *inc_J = nullptr;       // [2m]
+  void *phases_alt = nullptr;   // [n][R]
+};
+
+struct KernelShape {
+  int32_t residency = COSM_RES_LDS;
+  int32_t rw = 1;          // replicas per workgroup (LDS form)
+  int32_t threads = 256;
+  int32_t blocks = 1;
+  int32_t lds_bytes = 0;
+};
+
+}  // namespace cosm
+
+// The state behind the opaque handle.
+struct cosm_state {
+  int32_t n = 0, C = 0, R = 0;
+  int64_t m = 0;
+  cosm_params p{};
+  uint64_t seed = 0;
+  int64_t rid0 = 0;   // global index of replica 0
+  int64_t t = 0;      // sweeps done
+  hipStream_t stream = nullptr;
+  bool own_memory = false;
+  void *base = nullptr;
+  size_t base_bytes = 0;
+  cosm::DeviceBuffers d;
+  cosm::KernelShape shape;
+  cosm::Schedule sched{};
+  int32_t n_slots = 0;
+  int32_t max_class = 0;
+  bool has_h = false;
+  int64_t sumJ = 0;
+  std::vector<int32_t> h_eu, h_ev, h_J, h_h, h_colour;
+  std::vector<int32_t> class_sizes;  // edges per class
+  std::vector<int32_t> class_begin;  // offset of each class in the grouped edge arrays
+  // timing
+  bool timing = false;
+  int64_t launches = 0;
+  double kernel_ms = 0.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace cosm {
+// ---- kernel launchers (kernels.hip) -------------------------------------------------
+int launch_init(cosm_state *s);
+int launch_sweeps(cosm_state *s, int64_t n_sweeps);
+int launch_readout(cosm_state *s);
+int launch_energy(cosm_state *s);  // spins already in s->d.spins
+// Convert between the storage format and FP32 turns in [0, 1), both [n][R].
+int launch_to_turns(cosm_state *s, float *turns_dev);
+int launch_from_turns(cosm_state *s, const float *turns_dev);
+int lds_capacity_bytes();
+size_t readout_lds_bytes(int32_t n, int32_t B);
+}  // namespace cosm

@@ -1,0 +1,108 @@
+"""Host-side checks of libcosm that need no GPU: the library loads and exports
+every function include/cosm.h declares, the three colourings are proper and
+within their bounds, and bad graphs are rejected with the documented codes."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import cosm_inputs as ci
+import oracle
+import paper_2605_30355_amd as cosm
+from paper_2605_30355_amd.cosm import CosmError
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "cosm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cosm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    declared = header_functions()
+    assert len(declared) >= 10
+    exported = cosm.exported_symbols()
+    assert sorted(exported) == declared
+    assert "gfx950" in cosm.version()
+
+
+def test_default_params_match_tables_ix_x():
+    p = cosm.default_params()
+    assert p.alpha0_deg == 14.0 and p.dwt_window_deg == 90.0 and p.n_bisectors == 100
+    assert p.dwt_ratio == 0.5 and p.dwt_period == 3
+    assert p.schedule == cosm.SCHED_GRID and p.storage == cosm.STORE_FP32
+
+
+INSTANCES = [ci.torus(6, seed=1), ci.torus(7, seed=2), ci.torus(20, seed=1),
+             ci.random_regular(2000, 3, seed=2), ci.random_regular(600, 5, seed=3, weights="pm1"),
+             ci.erdos_renyi_capped(3000, 4, 8, seed=3), ci.small_random(40, 300, seed=4),
+             ci.trap_triangle(), ci.cycle(9)]
+
+
+@pytest.mark.parametrize("inst", INSTANCES, ids=lambda i: i.name)
+def test_greedy_equals_oracle_greedy(inst):
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_GREEDY)
+    ref, Cref = oracle.greedy_colouring(inst.n, inst.eu, inst.ev)
+    assert C == Cref and np.array_equal(colour, ref)
+
+
+@pytest.mark.parametrize("inst", INSTANCES, ids=lambda i: i.name)
+def test_misra_gries_proper_and_at_most_delta_plus_one(inst):
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_MISRA_GRIES)
+    delta = int(inst.degrees().max())
+    assert oracle.is_proper_colouring(inst.n, inst.eu, inst.ev, colour, C)
+    assert C <= delta + 1
+    assert np.all(np.bincount(colour, minlength=C) > 0)
+
+
+def test_misra_gries_many_random_graphs():
+    rng = np.random.default_rng(0)
+    for k in range(60):
+        n = int(rng.integers(3, 40))
+        m = int(rng.integers(0, n * (n - 1) // 2 + 1))
+        inst = ci.small_random(n, m, seed=k)
+        colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_MISRA_GRIES)
+        delta = int(inst.degrees().max()) if m else 0
+        assert oracle.is_proper_colouring(inst.n, inst.eu, inst.ev, colour, C)
+        assert C <= delta + 1
+
+
+@pytest.mark.parametrize("L", [(4, 4), (6, 8), (5, 5), (141, 141), (7, 6), (100, 100)])
+def test_torus_pattern(L):
+    Lx, Ly = L
+    inst = ci.torus(Lx, Ly, seed=3)
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [Lx, Ly])
+    assert oracle.is_proper_colouring(inst.n, inst.eu, inst.ev, colour, C)
+    assert C == 4 + (Lx % 2) + (Ly % 2)
+    sizes = np.bincount(colour)
+    if Lx % 2 == 0 and Ly % 2 == 0:  # regular pattern: N/2 edges per class (Sec. II-B)
+        assert np.all(sizes == inst.n // 2)
+
+
+def test_torus_rejects_non_lattice_edge():
+    inst = ci.torus(6, seed=1)
+    eu = np.append(inst.eu, 0)
+    ev = np.append(inst.ev, 14)
+    with pytest.raises(CosmError) as e:
+        cosm.build_partitions(inst.n, eu, ev, cosm.COLOR_TORUS, [6, 6])
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("eu,ev,status", [
+    ([0, 1], [1, 1], -1),      # self-loop
+    ([0, 1], [1, 5], -1),      # endpoint out of range
+    ([0, 1, 1], [1, 2, 0], -2),  # duplicate undirected edge
+    ([-1], [1], -1),
+])
+def test_bad_graphs_rejected(eu, ev, status):
+    with pytest.raises(CosmError) as e:
+        cosm.build_partitions(3, eu, ev, cosm.COLOR_GREEDY)
+    assert e.value.status == status
+
+
+def test_empty_graph():
+    colour, C = cosm.build_partitions(5, [], [], cosm.COLOR_GREEDY)
+    assert C == 0 and len(colour) == 0

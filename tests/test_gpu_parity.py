@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Grid schedule (every value on the 2^-23 turn grid): phases, spins, energies and
+cuts must be bit-identical to the oracle's for whole trials.  Phases compare as
+turns (GPU) against degrees / 360 (oracle), which is exact on the grid.
+"""
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import cosm_inputs as ci
+import oracle
+import paper_2605_30355_amd as cosm
+from paper_2605_30355_amd.cosm import CosmError
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make(inst, method=cosm.COLOR_GREEDY, sides=None):
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, method, sides)
+    prob = oracle.Problem(inst.n, inst.eu, inst.ev, inst.J, colour=colour, C=C, h=inst.h)
+    return colour, C, prob
+
+
+def oparams(p: cosm.Params):
+    return oracle.Params(alpha0_deg=p.alpha0_deg, dwt_ratio=p.dwt_ratio, dwt_period=p.dwt_period,
+                         dwt_window_deg=p.dwt_window_deg, n_bisectors=p.n_bisectors,
+                         sweeps=p.sweeps_per_trial, schedule=p.schedule, update=p.update)
+
+
+def run_gpu(inst, colour, C, params, seed, R, sweeps, chunks=1):
+    say(f"[gpu] {inst.name} R={R} sweeps={sweeps} res={params.residency} "
+        f"rw={params.replicas_per_wg} store={params.storage} sched={params.schedule}")
+    with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, params, seed=seed, replicas=R,
+                    h=inst.h) as st:
+        done = 0
+        for k in range(chunks):
+            step = sweeps // chunks + (1 if k < sweeps % chunks else 0)
+            st.sweep(step)
+            done += step
+        x = st.get_phases(cosm.UNIT_TURNS)
+        H, cut, spins = st.energy()
+        info = st.info()
+    say(f"[gpu]   done: {info}")
+    return x, H, cut, spins, info
+
+
+# ---------------------------------------------------------------------------
+def test_init_matches_oracle():
+    inst = ci.random_regular(124, 3, seed=5)
+    colour, C, prob = make(inst)
+    for sched in (cosm.SCHED_GRID, cosm.SCHED_CONTINUOUS):
+        p = cosm.Params(schedule=sched, sweeps_per_trial=10)
+        say(f"[gpu] init sched={sched}")
+        with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=77, replicas=37) as st:
+            x = st.get_phases(cosm.UNIT_DEGREES)
+            st.reset(78, 1000)
+            x2 = st.get_phases(cosm.UNIT_DEGREES)
+        assert np.array_equal(x, oracle.init_phases(inst.n, 77, 0, 37, sched))
+        assert np.array_equal(x2, oracle.init_phases(inst.n, 78, 1000, 37, sched))
+
+
+@pytest.mark.parametrize("inst", [ci.torus(20, seed=1), ci.random_regular(2000, 3, seed=2),
+                                  ci.small_random(30, 200, seed=3, weights="pm12"),
+                                  ci.erdos_renyi_capped(1000, 4, 8, seed=4)],
+                         ids=lambda i: i.name)
+def test_energy_of_given_spins(inst):
+    colour, C, prob = make(inst)
+    R = 19
+    rng = np.random.default_rng(1)
+    s = rng.choice(np.array([-1, 1], np.int8), size=(R, inst.n))
+    s[0] = 1
+    s[1] = -1
+    say(f"[gpu] energy {inst.name}")
+    with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, cosm.Params(), replicas=R) as st:
+        H, cut, back = st.energy(s)
+    Hr, cr = oracle.energy(prob, s)
+    assert np.array_equal(H, Hr) and np.array_equal(cut, cr)
+
+
+def test_energy_with_bias_fields():
+    inst = ci.small_random(25, 60, seed=9)
+    inst.h = np.random.default_rng(2).integers(-2, 3, size=inst.n).astype(np.int32)
+    colour, C, prob = make(inst)
+    s = np.random.default_rng(3).choice(np.array([-1, 1], np.int8), size=(5, inst.n))
+    say("[gpu] energy with h")
+    with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, cosm.Params(), replicas=5,
+                    h=inst.h) as st:
+        H, cut, _ = st.energy(s)
+    Hr, cr = oracle.energy(prob, s)
+    assert np.array_equal(H, Hr) and np.array_equal(cut, cr)
+
+
+def test_energy_rejects_bad_spins():
+    inst = ci.torus(4)
+    colour, C, _ = make(inst)
+    with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, cosm.Params(), replicas=2) as st:
+        s = np.ones((2, inst.n), np.int8)
+        s[1, 3] = 0
+        with pytest.raises(CosmError) as e:
+            st.energy(s)
+        assert e.value.status == -1
+
+
+# ---------------------------------------------------------------------------
+# Whole trials in the grid schedule: bit-exact.
+# ---------------------------------------------------------------------------
+def check_trial(inst, colour, C, prob, params, seed, R, sweeps, chunks=1, sample=None):
+    x, H, cut, spins, info = run_gpu(inst, colour, C, params, seed, R, sweeps, chunks)
+    op = oparams(params)
+    rows = list(range(R)) if sample is None else [int(r) for r in sample]
+    say(f"[oracle] {len(rows)} replicas x {sweeps} sweeps")
+
+    def one(r):  # ctypes releases the GIL, so rows run in parallel
+        xr = oracle.init_phases(inst.n, seed, r, 1, params.schedule)
+        oracle.sweeps(prob, op, seed, r, xr, 0, sweeps, n_threads=1)
+        return xr
+
+    with ThreadPoolExecutor(max_workers=8) as pool:
+        ref = list(pool.map(one, rows))
+    for r, xr in zip(rows, ref):
+        sr, Hr, cr, _ = oracle.readout(prob, op, xr)
+        assert np.array_equal(x[r] * 360.0, xr[0]), f"replica {r}: phases differ"
+        assert H[r] == Hr[0] and cut[r] == cr[0], f"replica {r}: energy differs"
+        assert np.array_equal(spins[r], sr[0]), f"replica {r}: spins differ"
+    return info
+
+
+@pytest.mark.parametrize("rw", [1, 2, 4])
+def test_c1_torus20_full_trial_lds(rw):
+    """20x20 +-1 torus, 4 classes, 64 replicas, 2000 sweeps (the small workload)."""
+    inst = ci.torus(20, seed=1)
+    colour, C, prob = make(inst, cosm.COLOR_TORUS, [20, 20])
+    p = cosm.Params(sweeps_per_trial=2000, dwt_ratio=0.5, dwt_period=3, residency=cosm.RES_LDS,
+                    replicas_per_wg=rw)
+    info = check_trial(inst, colour, C, prob, p, seed=42, R=64, sweeps=2000)
+    assert info["residency"] == cosm.RES_LDS and info["replicas_per_wg"] == rw
+
+
+@pytest.mark.parametrize("res", [cosm.RES_HBM, cosm.RES_PLAIN])
+def test_c1_torus20_other_forms(res):
+    inst = ci.torus(20, seed=1)
+    colour, C, prob = make(inst, cosm.COLOR_TORUS, [20, 20])
+    p = cosm.Params(sweeps_per_trial=300, dwt_ratio=0.5, dwt_period=3, residency=res)
+    check_trial(inst, colour, C, prob, p, seed=5, R=8 if res == cosm.RES_PLAIN else 70, sweeps=300)
+
+
+def test_ragged_replicas_and_resume():
+    """R not a multiple of the row width; sweeps split over several calls."""
+    inst = ci.random_regular(300, 3, seed=8, weights="pm1")
+    colour, C, prob = make(inst, cosm.COLOR_MISRA_GRIES)
+    p = cosm.Params(sweeps_per_trial=500, dwt_ratio=1.5, dwt_period=3, residency=cosm.RES_LDS,
+                    replicas_per_wg=4)
+    check_trial(inst, colour, C, prob, p, seed=9, R=37, sweeps=500, chunks=7)
+
+
+def test_c2_full_size_sampled():
+    """3-regular N=2000 Max-Cut (+1 weights), MG colouring, 1024 replicas, 1e4
+    sweeps, in the launch shape the benchmark uses; 6 replicas checked."""
+    inst = ci.random_regular(2000, 3, seed=2, weights="maxcut1")
+    colour, C, prob = make(inst, cosm.COLOR_MISRA_GRIES)
+    p = cosm.Params(sweeps_per_trial=10000, dwt_ratio=1.0, dwt_period=6)
+    info = check_trial(inst, colour, C, prob, p, seed=42, R=1024, sweeps=10000,
+                       sample=[0, 1, 511, 512, 1022, 1023])
+    assert info["residency"] == cosm.RES_LDS
+
+
+def test_large_torus_odd_side_sampled():
+    """141x141 torus (N=19881, 6 classes): the largest LDS-resident replica block."""
+    inst = ci.torus(141, seed=4)
+    colour, C, prob = make(inst, cosm.COLOR_TORUS, [141, 141])
+    p = cosm.Params(sweeps_per_trial=200, dwt_ratio=0.5, dwt_period=3)
+    info = check_trial(inst, colour, C, prob, p, seed=3, R=96, sweeps=200, sample=[0, 95])
+    assert info["residency"] == cosm.RES_LDS
+
+
+def test_five_regular_20000_sampled():
+    inst = ci.random_regular(20000, 5, seed=1000, weights="pm1")
+    colour, C, prob = make(inst, cosm.COLOR_GREEDY)
+    p = cosm.Params(sweeps_per_trial=100, dwt_ratio=1.5, dwt_period=3)
+    check_trial(inst, colour, C, prob, p, seed=6, R=64, sweeps=100, sample=[0, 33, 63])
+
+
+def test_degenerate_instances():
+    # one edge; no edges (twist only); an empty class in the middle
+    one = ci.Instance("one_edge", 2, np.array([0], np.int32), np.array([1], np.int32),
+                      np.array([1], np.int32))
+    c, C, prob = make(one)
+    check_trial(one, c, C, prob, cosm.Params(sweeps_per_trial=50, dwt_period=2), 1, 5, 50)
+    none = ci.Instance("no_edges", 17, np.zeros(0, np.int32), np.zeros(0, np.int32),
+                       np.zeros(0, np.int32))
+    c, C, prob = make(none)
+    check_trial(none, c, C, prob, cosm.Params(sweeps_per_trial=30, dwt_period=1, dwt_ratio=1.0), 2, 9, 30)
+    inst = ci.cycle(10, weights="antiferro")
+    c = np.array([0, 2, 0, 2, 0, 2, 0, 2, 0, 2], np.int32)  # class 1 empty
+    prob = oracle.Problem(inst.n, inst.eu, inst.ev, inst.J, colour=c, C=3)
+    check_trial(inst, c, 3, prob, cosm.Params(sweeps_per_trial=40), 3, 4, 40)
+
+
+def test_trap_triangle_scs_escapes_on_gpu():
+    inst = ci.trap_triangle()
+    colour, C, prob = make(inst)
+    p = cosm.Params(sweeps_per_trial=1000, dwt_period=0)
+    with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, replicas=1) as st:
+        st.set_phases(np.array([[0.0, 15.0, 0.0]]), cosm.UNIT_DEGREES, 0)
+        st.sweep(1)
+        H, _, _ = st.energy()
+    assert H[0] == -3
+
+
+def test_schedule_limits_and_errors():
+    inst = ci.torus(4)
+    colour, C, _ = make(inst)
+    with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C,
+                    cosm.Params(sweeps_per_trial=10), replicas=2) as st:
+        st.sweep(10)
+        with pytest.raises(CosmError) as e:
+            st.sweep(1)
+        assert e.value.status == -4
+    with pytest.raises(CosmError) as e:
+        big = ci.torus(150, seed=1)
+        cb, Cb, _ = make(big, cosm.COLOR_TORUS, [150, 150])
+        cosm.State(big.n, big.eu, big.ev, big.J, cb, Cb,
+                   cosm.Params(residency=cosm.RES_LDS, replicas_per_wg=4), replicas=4)
+    assert e.value.status == -4
+    bad = colour.copy()
+    bad[0] = bad[1] if inst.eu[0] == inst.eu[1] else bad[0]
+    k0, k1 = np.nonzero((inst.eu == 0) | (inst.ev == 0))[0][:2]
+    bad[k1] = bad[k0]
+    with pytest.raises(CosmError) as e:
+        cosm.State(inst.n, inst.eu, inst.ev, inst.J, bad, C, cosm.Params(), replicas=1)
+    assert e.value.status == -3
+
+
+def test_set_get_phases_roundtrip():
+    inst = ci.torus(5)
+    colour, C, _ = make(inst, cosm.COLOR_TORUS, [5, 5])
+    x = oracle.init_phases(inst.n, 3, 0, 3)
+    with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, cosm.Params(), replicas=3) as st:
+        st.set_phases(x, cosm.UNIT_DEGREES, 0)
+        assert np.array_equal(st.get_phases(cosm.UNIT_DEGREES), x)
+
+
+# ---------------------------------------------------------------------------
+# Continuous schedule: within 1e-4 rad for 8 sweeps, away from near-ties.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("inst", [ci.torus(20, seed=1), ci.random_regular(2000, 3, seed=2)],
+                         ids=lambda i: i.name)
+def test_continuous_first_sweeps_within_tolerance(inst):
+    colour, C, prob = make(inst, cosm.COLOR_MISRA_GRIES)
+    p = cosm.Params(sweeps_per_trial=2000, schedule=cosm.SCHED_CONTINUOUS, dwt_period=3)
+    R, seed = 64, 21
+    x, *_ = run_gpu(inst, colour, C, p, seed, R, 8)
+    xr = oracle.init_phases(inst.n, seed, 0, R, oracle.SCHED_CONTINUOUS)
+    margin = oracle.sweeps(prob, oparams(p), seed, 0, xr, 0, 8, diag_sweeps=8)
+    d = np.abs(x * 360.0 - xr) % 360.0
+    err = np.deg2rad(np.minimum(d, 360.0 - d)).max(axis=1)
+    clean = margin > 1e-3  # degrees: replicas with no decision within 1e-3 deg of a threshold
+    say(f"continuous: {clean.sum()} of {R} replicas clear of ties; max err {err[clean].max():.2e} rad")
+    assert clean.sum() >= R // 2
+    assert np.all(err[clean] <= 1e-4)
