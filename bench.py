@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the Cosm sweep on one MI355X.
+
+A step is one whole trial batch of the hot path on the Max-Cut workload (random
+3-regular graph, N = 2000, 3000 edges, +1 weights, Misra-Gries colouring in 4
+classes of equal size, 1024 replicas, 10^4 sweeps): phase init, 10^4 sweeps (SCS sub-sweeps,
+twist, schedule) and the bisector readout with int64 energies.
+
+Prints one JSON line: edge-updates/s of the batched LDS-resident form (value),
+the plain one-replica-per-launch form, replica-sweeps/s, time-to-target at 99%
+for the batched, plain and 16-bit-storage forms, the roofline of the sweep
+kernel, and the CPU oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs at 2.4 GHz; LDS serves 128 B/clk/CU (measured 125 B/clk/CU
+# with conflict-free ds_read_b128 / ds_write_b128).
+LDS_PEAK_GBS = 128 * 256 * 2.4          # 78643 GB/s
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-ops per second, non-packed FP32
+
+WORKLOAD = dict(name="maxcut-3reg-n2000", n=2000, degree=3, seed=2, weights="maxcut1",
+                replicas=1024, sweeps=10000, alpha0_deg=14.0, dwt_ratio=1.0, dwt_period=6,
+                window_deg=90.0, bisectors=100)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_instance():
+    import cosm_inputs as ci
+    return ci.random_regular(WORKLOAD["n"], WORKLOAD["degree"], seed=WORKLOAD["seed"],
+                             weights=WORKLOAD["weights"])
+
+
+def params(cosm, **over):
+    p = cosm.Params(alpha0_deg=WORKLOAD["alpha0_deg"], dwt_ratio=WORKLOAD["dwt_ratio"],
+                    dwt_period=WORKLOAD["dwt_period"], dwt_window_deg=WORKLOAD["window_deg"],
+                    n_bisectors=WORKLOAD["bisectors"], sweeps_per_trial=WORKLOAD["sweeps"])
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def load_target():
+    path = os.path.join(ROOT, "tests", "golden", "targets.json")
+    try:
+        with open(path) as f:
+            return json.load(f)[WORKLOAD["name"]]["target_H"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(inst, colour, C, seconds_goal=10.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    op = oracle.Params(alpha0_deg=WORKLOAD["alpha0_deg"], dwt_ratio=WORKLOAD["dwt_ratio"],
+                       dwt_period=WORKLOAD["dwt_period"], dwt_window_deg=WORKLOAD["window_deg"],
+                       n_bisectors=WORKLOAD["bisectors"], sweeps=WORKLOAD["sweeps"])
+    prob = oracle.Problem(inst.n, inst.eu, inst.ev, inst.J, colour=colour, C=C)
+    # calibrate on one replica per thread for 200 sweeps, then size the sample
+    x = oracle.init_phases(inst.n, 7, 0, threads)
+    t0 = time.perf_counter()
+    oracle.sweeps(prob, op, 7, 0, x, 0, 200, n_threads=threads)
+    rate = threads * 200 * inst.m / (time.perf_counter() - t0)
+    R = max(threads, int(seconds_goal * rate / (inst.m * WORKLOAD["sweeps"])) // threads * threads)
+    x = oracle.init_phases(inst.n, 7, 0, R)
+    t0 = time.perf_counter()
+    oracle.sweeps(prob, op, 7, 0, x, 0, WORKLOAD["sweeps"], n_threads=threads)
+    oracle.readout(prob, op, x)
+    dt = time.perf_counter() - t0
+    return {"value": R * WORKLOAD["sweeps"] * inst.m / dt, "unit": "edge-updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{R} replicas x {WORKLOAD['sweeps']} sweeps of {WORKLOAD['name']} "
+                      f"(init, sweeps, readout), {dt:.1f} s wall",
+            "seconds": round(dt, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device copy (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the method's replicas are independent, so several "
+              "GPUs would each run this same single-GPU job on their own replicas; "
+              "run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2605_30355_amd as cosm
+
+    torch.cuda.set_device(0)
+    inst = make_instance()
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+    R, S, m = WORKLOAD["replicas"], WORKLOAD["sweeps"], inst.m
+    log(f"workload {WORKLOAD['name']}: n={inst.n} m={m} C={C} R={R} S={S}")
+
+    if args.copy_probe:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # ---- batched LDS-resident form: the timed steps --------------------------------
+    st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, params(cosm), seed=1,
+                    replicas=R)
+    info = st.info()
+    log(f"shape: {info}")
+    stream = torch.cuda.current_stream()
+
+    def step(k, ev=None):
+        st.reset(1, k * R)
+        if ev:
+            ev[0].record(stream)
+        st.sweep(S)
+        if ev:
+            ev[1].record(stream)
+        st.energy(return_spins=False)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k, events[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in events]
+    avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    updates = m * S * R * args.steps
+    value = updates / elapsed
+    log(f"batched: {elapsed * 1e3 / args.steps:.2f} ms/step, sweep kernel {avg_kernel_s * 1e3:.2f} ms, "
+        f"{value:.3e} edge-updates/s")
+
+    b = 4  # FP32 phase bytes
+    n_dwt = S // WORKLOAD["dwt_period"]
+    lds_bytes_per_launch = R * (S * 4 * b * m + n_dwt * 2 * b * inst.n)
+    achieved = lds_bytes_per_launch / avg_kernel_s / 1e9
+    roofline = {"bound": "lds", "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
+                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sweep_lds<fp32,4>",
+                "bytes_per_edge_update": 4 * b,
+                "edge_updates_per_s_kernel": round(m * S * R / avg_kernel_s, 1)}
+
+    # ---- plain form: one replica per launch, one launch per colour class ------------
+    plain_sweeps = 500
+    sp = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C,
+                    params(cosm, residency=cosm.RES_PLAIN), seed=1, replicas=1)
+    sp.sweep(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sp.sweep(plain_sweeps)
+    torch.cuda.synchronize()
+    plain_dt = time.perf_counter() - t0
+    plain_rate = m * plain_sweeps / plain_dt
+    plain_t_trial = plain_dt / plain_sweeps * S
+    sp.close()
+    log(f"plain: {plain_rate:.3e} edge-updates/s, t_trial {plain_t_trial:.3f} s")
+
+    # ---- time to target at 99% -------------------------------------------------------
+    ttt = None
+    target = load_target()
+    if not args.no_ttt and target is not None:
+        ttt = {"target_H": target, "target_cut": (int(-inst.J.sum()) - target) // 2}
+        for name, store in (("batched_fp32", cosm.STORE_FP32), ("batched_fp16", cosm.STORE_FP16),
+                            ("batched_bf16", cosm.STORE_BF16)):
+            s2 = st if store == cosm.STORE_FP32 else cosm.State(
+                inst.n, inst.eu, inst.ev, inst.J, colour, C, params(cosm, storage=store), seed=1,
+                replicas=R)
+            res, _ = s2.solve_to_target(target, 8 * R)
+            ttt[name] = {"ps": res.ps, "ps_ci95": [res.ps_lo, res.ps_hi], "trials": res.trials,
+                         "r99": res.r99, "t_trial_s": res.t_trial_s, "ttt_s": res.ttt_s,
+                         "best_H": res.best_H}
+            if s2 is not st:
+                s2.close()
+            log(f"{name}: {ttt[name]}")
+        ps = ttt["batched_fp32"]["ps"]
+        r99 = ttt["batched_fp32"]["r99"]
+        # the plain form runs the same trajectories (bit-exact), so it shares P_s
+        ttt["plain_fp32"] = {"ps": ps, "r99": r99, "t_trial_s": plain_t_trial,
+                             "ttt_s": plain_t_trial * r99 if math.isfinite(r99) else None}
+        for k, v in ttt.items():
+            if isinstance(v, dict) and v.get("ttt_s") is not None and not math.isfinite(v["ttt_s"]):
+                v["ttt_s"] = None
+                v["r99"] = None
+    st.close()
+
+    out = {
+        "metric": "edge-updates/s (batched vs plain) + time-to-target @99% success, 1 MI355X",
+        "value": round(value, 1),
+        "unit": "edge-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD["name"], "n": inst.n, "edges": m, "classes": C,
+                   "colouring": "misra-gries, class sizes equalised", "replicas": R, "sweeps": S,
+                   "alpha0_deg": WORKLOAD["alpha0_deg"], "dwt_ratio": WORKLOAD["dwt_ratio"],
+                   "dwt_period": WORKLOAD["dwt_period"], "bisectors": WORKLOAD["bisectors"],
+                   "schedule": "grid", "storage": "fp32", "residency": "lds",
+                   "replicas_per_wg": info["replicas_per_wg"],
+                   "threads_per_wg": info["threads_per_wg"], "workgroups": info["workgroups"]},
+        "replica_sweeps_per_s": round(S * R * args.steps / elapsed, 1),
+        "plain_edge_updates_per_s": round(plain_rate, 1),
+        "batched_over_plain": round(value / plain_rate, 1),
+        "roofline": roofline,
+        "ttt": ttt,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, colour, C)
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -54,7 +54,8 @@ enum {
 };
 
 /* ---- enumerations ---------------------------------------------------------- */
-enum { COSM_COLOR_GREEDY = 0, COSM_COLOR_MISRA_GRIES = 1, COSM_COLOR_TORUS = 2 };
+enum { COSM_COLOR_GREEDY = 0, COSM_COLOR_MISRA_GRIES = 1, COSM_COLOR_TORUS = 2,
+       COSM_COLOR_BALANCED = 3 };
 enum { COSM_STORE_FP32 = 0, COSM_STORE_FP16 = 1, COSM_STORE_BF16 = 2 };
 /* Where a replica's phases live during a sweep.  LDS: a workgroup holds whole
  * replicas in LDS for all sweeps of a call.  HBM: phases stay in device memory,
@@ -107,6 +108,10 @@ typedef struct cosm_state cosm_state;
  *     1, vertical edges with even / odd upper row 2 / 3; with an odd side the
  *     wrap-around edges of that direction get their own colour (4 horizontal,
  *     5 vertical), the remaining colours are renumbered to stay contiguous.
+ *   method BALANCED: Misra-Gries, then class sizes equalised (largest minus
+ *     smallest <= 1 where Kempe swaps allow) by recolouring alternating
+ *     two-colour paths; same number of colours.  Appendix B notes that
+ *     colourings which balance the edges per colour are admissible.
  * colour_out[m] (caller-owned) receives the class of every edge; class indices
  * are also the order in which a sweep applies them.  *num_colours_out = C.
  * Errors: EINVAL (NULL, n < 1, endpoint out of range, self-loop, TORUS edge that

@@ -13,7 +13,7 @@ _LIB_PATH = os.path.join(_HERE, "libcosm.so")
 COSM_OK = 0
 STATUS_NAMES = {0: "COSM_OK", -1: "COSM_EINVAL", -2: "COSM_EDUP", -3: "COSM_ECOLOR",
                 -4: "COSM_ERANGE", -5: "COSM_ENOMEM", -6: "COSM_EDEVICE", -7: "COSM_ESTATE"}
-COLOR_GREEDY, COLOR_MISRA_GRIES, COLOR_TORUS = 0, 1, 2
+COLOR_GREEDY, COLOR_MISRA_GRIES, COLOR_TORUS, COLOR_BALANCED = 0, 1, 2, 3
 STORE_FP32, STORE_FP16, STORE_BF16 = 0, 1, 2
 RES_AUTO, RES_LDS, RES_HBM, RES_PLAIN = 0, 1, 2, 3
 SCHED_GRID, SCHED_CONTINUOUS = 0, 1
@@ -251,12 +251,12 @@ class State:
         _check(load_library().cosm_reset(self._h_state, int(seed) & ((1 << 64) - 1),
                                          int(replica_offset)))
 
-    def energy(self, spins=None):
+    def energy(self, spins=None, return_spins=True):
         """Readout (spins=None) or energies of given spins [R][n].
-        Returns (H[R], cut[R], spins[R][n])."""
+        Returns (H[R], cut[R], spins[R][n] or None)."""
         H = np.zeros(self.R, dtype=np.int64)
         cut = np.zeros(self.R, dtype=np.int64)
-        out = np.zeros((self.R, self.n), dtype=np.int8)
+        out = np.zeros((self.R, self.n), dtype=np.int8) if return_spins else None
         sp = None
         if spins is not None:
             sp = np.ascontiguousarray(spins, dtype=np.int8).reshape(self.R, self.n)

@@ -42,7 +42,8 @@ MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_param
   };
   const size_t nr = (size_t)n * (size_t)R;
   mp.phases = take(nr * storage_bytes(p.storage));
-  mp.desc = take((size_t)m * sizeof(EdgeDesc));
+  // lane schedule: at most 32 lanes per edge group plus one partial pass per class
+  mp.desc = take(((size_t)32 * m + (size_t)1024 * C + 1024) * sizeof(EdgeDesc));
   mp.class_off = take(((size_t)C + 1) * 4);
   mp.slot_vertex = take(((size_t)n + 1) * 4);
   mp.eu = take((size_t)m * 4);
@@ -122,7 +123,8 @@ int device_cu_count() {
 }
 
 // LDS bytes of the sweep kernel for W words per row.
-size_t lds_sweep_bytes(int32_t n_slots, int W) { return (size_t)n_slots * W * 4 + 16; }
+// (rows, then two buffers of reference angles for up to 8 replicas)
+size_t lds_sweep_bytes(int32_t n_slots, int W) { return (size_t)n_slots * W * 4 + 2 * 8 * 4; }
 
 // Choose residency, replicas per workgroup and threads.  The LDS form is used
 // when a replica block fits; among fitting shapes prefer the widest rows that
@@ -170,9 +172,8 @@ int choose_shape(cosm_state *s) {
       sh.rw = chosen * pw;
       sh.blocks = (s->R + sh.rw - 1) / sh.rw;
       sh.lds_bytes = (int32_t)lds_sweep_bytes(s->n_slots, chosen);
-      int th = p.threads_per_wg;
-      if (th == 0) th = std::min(1024, std::max(64, (s->max_class + 63) / 64 * 64));
-      sh.threads = th;
+      if (int rc = build_lds_schedule(*s, chosen, p.threads_per_wg, &s->lds)) return rc;
+      sh.threads = s->lds.nth;
     }
   }
   if (sh.residency != COSM_RES_LDS) {
@@ -234,6 +235,10 @@ int cosm_build_partitions(int32_t n, int64_t m, const int32_t *eu, const int32_t
   switch (method) {
     case COSM_COLOR_GREEDY: C = colour_greedy(n, m, eu, ev, colour_out); break;
     case COSM_COLOR_MISRA_GRIES: C = colour_misra_gries(n, m, eu, ev, colour_out); break;
+    case COSM_COLOR_BALANCED:
+      C = colour_misra_gries(n, m, eu, ev, colour_out);
+      equalise_classes(n, m, eu, ev, C, colour_out);
+      break;
     case COSM_COLOR_TORUS:
       if (method_args == nullptr) return set_error(COSM_EINVAL, "TORUS needs {Lx, Ly}");
       C = colour_torus(n, m, eu, ev, method_args[0], method_args[1], colour_out);
@@ -321,7 +326,6 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   s->max_class = num_colours ? *std::max_element(s->class_sizes.begin(), s->class_sizes.end()) : 0;
   std::vector<int32_t> peu((size_t)m), pev((size_t)m);
   std::vector<float> pJ((size_t)m);
-  std::vector<EdgeDesc> desc((size_t)m);
   {
     std::vector<int32_t> fill(s->class_begin);
     for (int64_t k = 0; k < m; k++) {
@@ -331,16 +335,7 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
       pJ[(size_t)pos] = (float)J[k];
     }
   }
-  // LDS slots: slot i holds vertex i.
   s->n_slots = n;
-  std::vector<int32_t> slot_vertex((size_t)n);
-  for (int32_t i = 0; i < n; i++) slot_vertex[(size_t)i] = i;
-  for (int64_t k = 0; k < m; k++)
-    desc[(size_t)k] = EdgeDesc{(uint32_t)peu[(size_t)k] | ((uint32_t)pev[(size_t)k] << 16),
-                               pJ[(size_t)k]};
-  std::vector<int32_t> class_off((size_t)num_colours + 1, 0);
-  for (int32_t c = 0; c < num_colours; c++)
-    class_off[(size_t)c + 1] = class_off[(size_t)c] + s->class_sizes[(size_t)c];
 
   // incidence lists (full-gradient form)
   std::vector<int32_t> inc_off;
@@ -419,9 +414,11 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
     return COSM_OK;
   };
   int rc = COSM_OK;
-  rc = rc ? rc : up(d.desc, desc.data(), desc.size() * sizeof(EdgeDesc));
-  rc = rc ? rc : up(d.class_off, class_off.data(), class_off.size() * 4);
-  rc = rc ? rc : up(d.slot_vertex, slot_vertex.data(), slot_vertex.size() * 4);
+  if (s->shape.residency == COSM_RES_LDS) {
+    rc = rc ? rc : up(d.desc, s->lds.desc.data(), s->lds.desc.size() * sizeof(EdgeDesc));
+    rc = rc ? rc : up(d.class_off, s->lds.K.data(), s->lds.K.size() * 4);
+    rc = rc ? rc : up(d.slot_vertex, s->lds.slot_vertex.data(), s->lds.slot_vertex.size() * 4);
+  }
   rc = rc ? rc : up(d.eu, eu, (size_t)m * 4);
   rc = rc ? rc : up(d.ev, ev, (size_t)m * 4);
   rc = rc ? rc : up(d.J, J, (size_t)m * 4);

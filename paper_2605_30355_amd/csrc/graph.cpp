@@ -226,6 +226,63 @@ int32_t colour_misra_gries(int32_t n, int64_t m, const int32_t *eu, const int32_
   return C;
 }
 
+// Equalise class sizes of a proper colouring without adding colours: while the
+// largest class a exceeds the smallest b by more than one edge, swap a <-> b on
+// a maximal a/b alternating path that holds one more a-edge than b-edges (one
+// exists whenever |a| > |b|).  Every swap keeps the colouring proper.
+void equalise_classes(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, int32_t C,
+                      int32_t *colour) {
+  if (C < 2 || m == 0) return;
+  std::vector<int64_t> size((size_t)C, 0);
+  for (int64_t k = 0; k < m; k++) size[(size_t)colour[k]]++;
+  // edge of colour c at vertex v
+  std::vector<int64_t> at((size_t)n * C, -1);
+  for (int64_t k = 0; k < m; k++) {
+    at[(size_t)eu[k] * C + colour[k]] = k;
+    at[(size_t)ev[k] * C + colour[k]] = k;
+  }
+  auto other = [&](int64_t e, int32_t v) { return eu[e] == v ? ev[e] : eu[e]; };
+  std::vector<int64_t> path;
+  for (int64_t guard = 0; guard < 4 * m + 16; guard++) {
+    int32_t a = 0, b = 0;
+    for (int32_t c = 1; c < C; c++) {
+      if (size[(size_t)c] > size[(size_t)a]) a = c;
+      if (size[(size_t)c] < size[(size_t)b]) b = c;
+    }
+    if (size[(size_t)a] - size[(size_t)b] <= 1) break;
+    bool swapped = false;
+    // a path with more a- than b-edges starts at a vertex with an a-edge and no b-edge
+    for (int32_t v0 = 0; v0 < n && !swapped; v0++) {
+      if (at[(size_t)v0 * C + a] < 0 || at[(size_t)v0 * C + b] >= 0) continue;
+      path.clear();
+      int32_t v = v0, want = a;
+      int64_t na = 0, nb = 0;
+      while (true) {
+        const int64_t e = at[(size_t)v * C + want];
+        if (e < 0) break;
+        path.push_back(e);
+        (want == a ? na : nb)++;
+        v = other(e, v);
+        want = (want == a) ? b : a;
+      }
+      if (na <= nb) continue;
+      for (int64_t e : path) {
+        at[(size_t)eu[e] * C + colour[e]] = -1;
+        at[(size_t)ev[e] * C + colour[e]] = -1;
+      }
+      for (int64_t e : path) {
+        colour[e] = colour[e] == a ? b : a;
+        at[(size_t)eu[e] * C + colour[e]] = e;
+        at[(size_t)ev[e] * C + colour[e]] = e;
+      }
+      size[(size_t)a]--;
+      size[(size_t)b]++;
+      swapped = true;
+    }
+    if (!swapped) break;
+  }
+}
+
 // Regular lattice pattern for an Lx x Ly torus (vertex r*Lx + c).
 int32_t colour_torus(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, int32_t Lx,
                      int32_t Ly, int32_t *colour) {

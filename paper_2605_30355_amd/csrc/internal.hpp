@@ -36,6 +36,8 @@ int32_t colour_greedy(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev
                       int32_t *colour);
 int32_t colour_misra_gries(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
                            int32_t *colour);
+void equalise_classes(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, int32_t C,
+                      int32_t *colour);
 // Returns C, or a negative status for a non-lattice edge.
 int32_t colour_torus(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, int32_t Lx,
                      int32_t Ly, int32_t *colour);
@@ -67,6 +69,22 @@ struct Schedule {
 struct EdgeDesc {
   uint32_t slots;
   float J;
+};
+constexpr uint32_t kEmptySlot = 0xffffffffu;  // masked lane
+
+// Lane schedule of the LDS-resident sweep (schedule.cpp).  Entry (j, t) of
+// desc is thread t's edge in its j-th slot; slots run class by class, K[c]
+// per class, and a workgroup barrier follows the last slot of every class.
+struct LdsSchedule {
+  int32_t G = 0;                   // lanes per LDS cycle for the row width
+  int32_t n_rows = 0;              // LDS rows (slots)
+  int32_t nth = 0;                 // threads per workgroup
+  int32_t total_slots = 0;
+  int64_t pad_entries = 0;         // masked lanes added by the schedule
+  std::vector<int32_t> slot_vertex;  // [n_rows] vertex of each slot
+  std::vector<int32_t> K;          // [C] slots per thread for each class
+  std::vector<int32_t> padded;     // [C] padded list length of each class
+  std::vector<EdgeDesc> desc;      // [total_slots * nth]
 };
 
 struct DeviceBuffers {
@@ -119,6 +137,7 @@ struct cosm_state {
   cosm::Schedule sched{};
   int32_t n_slots = 0;
   int32_t max_class = 0;
+  cosm::LdsSchedule lds;  // resolved lane schedule of the LDS form
   bool has_h = false;
   int64_t sumJ = 0;
   std::vector<int32_t> h_eu, h_ev, h_J, h_h, h_colour;
@@ -141,5 +160,7 @@ int launch_energy(cosm_state *s);  // spins already in s->d.spins
 int launch_to_turns(cosm_state *s, float *turns_dev);
 int launch_from_turns(cosm_state *s, const float *turns_dev);
 int lds_capacity_bytes();
+int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out);
+
 size_t readout_lds_bytes(int32_t n, int32_t B);
 }  // namespace cosm

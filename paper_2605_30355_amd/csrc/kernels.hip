@@ -185,13 +185,14 @@ struct SweepSchedule {
 
 struct LdsArgs {
   void *phases;
-  const EdgeDesc *desc;
-  const int32_t *class_off;
-  const int32_t *slot_vertex;
-  int32_t R, n_slots, C;
+  const EdgeDesc *desc;       // [total_slots * nth] lane schedule
+  const int32_t *Kc;          // [C] slots per thread of each class
+  const int32_t *slot_vertex; // [n_rows]
+  int32_t R, n_rows, C, total_slots;
   int64_t t0, nsw;
   SweepSchedule sch;
   uint32_t k0, k1, rid0;
+  uint32_t bar_mask;          // register-resident schedule: barrier after slot j
 };
 
 // ---------------------------------------------------------------------------
@@ -211,19 +212,67 @@ __global__ void __launch_bounds__(256) k_init(void *phases, int32_t n, int32_t R
 // ---------------------------------------------------------------------------
 // The batched LDS-resident sweep: one workgroup owns RW = W * kPerWord whole
 // replicas, stored as LDS rows of W 32-bit words (one row per slot), and runs
-// every sweep of the call with workgroup barriers only.
+// every sweep of the call with workgroup barriers only.  Thread t handles the
+// t-th entry of each slot of the lane schedule (consecutive lanes touch rows in
+// distinct LDS bank groups).  EMAX > 0: the schedule (at most EMAX slots) is
+// loaded into registers once; EMAX == 0: it streams from memory, one slot ahead.
 // ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ void lds_load_at(const uint32_t *base, uint32_t byte, uint32_t (&w)[W]) {
+  const char *p = reinterpret_cast<const char *>(base) + byte;
+  if constexpr (W == 4) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(p);
+    w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+  } else if constexpr (W == 2) {
+    const uint2 q = *reinterpret_cast<const uint2 *>(p);
+    w[0] = q.x; w[1] = q.y;
+  } else {
+    w[0] = *reinterpret_cast<const uint32_t *>(p);
+  }
+}
+template <int W>
+__device__ __forceinline__ void lds_store_at(uint32_t *base, uint32_t byte, const uint32_t (&w)[W]) {
+  char *p = reinterpret_cast<char *>(base) + byte;
+  if constexpr (W == 4) {
+    *reinterpret_cast<uint4 *>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else if constexpr (W == 2) {
+    *reinterpret_cast<uint2 *>(p) = make_uint2(w[0], w[1]);
+  } else {
+    *reinterpret_cast<uint32_t *>(p) = w[0];
+  }
+}
+
+// Eq. (6) on every replica of one edge: rows at byte offsets bu, bv.
 template <int ST, int W>
+__device__ __forceinline__ void edge_rows(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ) {
+  using F = Fmt<ST>;
+  constexpr int RW = W * F::kPerWord;
+  uint32_t wu[W], wv[W];
+  lds_load_at<W>(lds, bu, wu);
+  lds_load_at<W>(lds, bv, wv);
+  float xu[RW], xv[RW];
+  F::template unpack<W>(wu, xu);
+  F::template unpack<W>(wv, xv);
+#pragma unroll
+  for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
+  F::template pack<W>(xu, wu);
+  F::template pack<W>(xv, wv);
+  lds_store_at<W>(lds, bu, wu);
+  lds_store_at<W>(lds, bv, wv);
+}
+
+template <int ST, int W, int EMAX>
 __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
+  constexpr uint32_t ROWB = 4 * W;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int32_t r0 = blockIdx.x * RW;
   const int32_t nvalid = min(RW, a.R - r0);
 
   // HBM [n][R] -> LDS rows
-  for (int s = tid; s < a.n_slots; s += nth) {
+  for (int s = tid; s < a.n_rows; s += nth) {
     const size_t base = (size_t)a.slot_vertex[s] * a.R + r0;
     float v[RW];
 #pragma unroll
@@ -231,6 +280,29 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     uint32_t w[W];
     F::template pack<W>(v, w);
     lds_store<W>(lds, s, w);
+  }
+
+  // reference angles of the first twist of this call
+  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)a.n_rows * W);  // [2][RW]
+  int tbuf = 0;
+  if (a.sch.period > 0 && tid < RW) {
+    const int64_t first = a.t0 + (a.sch.period - a.sch.phase);  // next t with t % period == 0
+    theta_buf[tid] = 2.0f * theta_turns((uint32_t)first, a.rid0 + (uint32_t)(r0 + tid), a.k0,
+                                        a.k1) - a.sch.win;
+  }
+
+  // register-resident lane schedule
+  uint32_t ua[EMAX > 0 ? EMAX : 1], va[EMAX > 0 ? EMAX : 1];
+  float jr[EMAX > 0 ? EMAX : 1];
+  if constexpr (EMAX > 0) {
+#pragma unroll
+    for (int j = 0; j < EMAX; j++) {
+      EdgeDesc d{kEmptySlot, 0.0f};
+      if (j < a.total_slots) d = a.desc[(size_t)j * nth + tid];
+      ua[j] = d.slots == kEmptySlot ? kEmptySlot : (d.slots & 0xffffu) * ROWB;
+      va[j] = (d.slots >> 16) * ROWB;
+      jr[j] = d.J;
+    }
   }
   __syncthreads();
 
@@ -251,40 +323,46 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       twist = sc.ratio * alpha;
     }
     // Sequential conflict-free search: classes in order, a barrier after each.
-    for (int c = 0; c < a.C; c++) {
-      const int beg = a.class_off[c], end = a.class_off[c + 1];
-      for (int e = beg + tid; e < end; e += nth) {
-        const EdgeDesc d = a.desc[e];
-        const int su = (int)(d.slots & 0xffffu), sv = (int)(d.slots >> 16);
-        const float aJ = alpha * d.J;
-        uint32_t wu[W], wv[W];
-        lds_load<W>(lds, su, wu);
-        lds_load<W>(lds, sv, wv);
-        float xu[RW], xv[RW];
-        F::template unpack<W>(wu, xu);
-        F::template unpack<W>(wv, xv);
+    if constexpr (EMAX > 0) {
 #pragma unroll
-        for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
-        F::template pack<W>(xu, wu);
-        F::template pack<W>(xv, wv);
-        lds_store<W>(lds, su, wu);
-        lds_store<W>(lds, sv, wv);
+      for (int j = 0; j < EMAX; j++) {
+        if (j < a.total_slots) {
+          if (ua[j] != kEmptySlot) edge_rows<ST, W>(lds, ua[j], va[j], alpha * jr[j]);
+          if ((a.bar_mask >> j) & 1u) __syncthreads();
+        }
       }
-      __syncthreads();
+    } else {
+      int j = 0;
+      EdgeDesc cur{kEmptySlot, 0.0f};
+      if (a.total_slots > 0) cur = a.desc[tid];
+      for (int c = 0; c < a.C; c++) {
+        const int kc = a.Kc[c];
+        for (int k = 0; k < kc; k++, j++) {
+          const int jn = (j + 1 < a.total_slots) ? j + 1 : 0;
+          const EdgeDesc nxt = a.desc[(size_t)jn * nth + tid];
+          if (cur.slots != kEmptySlot)
+            edge_rows<ST, W>(lds, (cur.slots & 0xffffu) * ROWB, (cur.slots >> 16) * ROWB,
+                             alpha * cur.J);
+          cur = nxt;
+        }
+        if (kc > 0) __syncthreads();
+      }
     }
-    // Dual window twist every `period` sweeps.
+    // Dual window twist every `period` sweeps.  The reference angles of this
+    // twist were drawn during the previous one (or at the start) by the first
+    // RW lanes of the workgroup; those lanes now draw the next twist's angles
+    // into the other buffer, read only after the barrier that ends this twist.
     if (sc.period > 0 && ++sc.phase == sc.period) {
       sc.phase = 0;
-      // lanes 0..RW-1 of each wave draw the replicas' reference angles
-      const int lane = __lane_id();
-      float cl = 0.0f;
-      if (lane < RW)
-        cl = 2.0f * theta_turns((uint32_t)t, a.rid0 + (uint32_t)(r0 + lane), a.k0, a.k1) - sc.win;
       float cth[RW];
 #pragma unroll
-      for (int k = 0; k < RW; k++)
-        cth[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cl), k));
-      for (int s = tid; s < a.n_slots; s += nth) {
+      for (int k = 0; k < RW; k++) cth[k] = theta_buf[tbuf * RW + k];
+      if (tid < RW)
+        theta_buf[(tbuf ^ 1) * RW + tid] =
+            2.0f * theta_turns((uint32_t)(t + sc.period), a.rid0 + (uint32_t)(r0 + tid), a.k0,
+                               a.k1) - sc.win;
+      tbuf ^= 1;
+      for (int s = tid; s < a.n_rows; s += nth) {
         uint32_t w[W];
         lds_load<W>(lds, s, w);
         float v[RW];
@@ -300,7 +378,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   }
 
   // LDS rows -> HBM
-  for (int s = tid; s < a.n_slots; s += nth) {
+  for (int s = tid; s < a.n_rows; s += nth) {
     const size_t base = (size_t)a.slot_vertex[s] * a.R + r0;
     uint32_t w[W];
     lds_load<W>(lds, s, w);
@@ -621,18 +699,47 @@ float host_twist(const Schedule &sc, int64_t t) {
   return sc.dwt_ratio * host_alpha(sc, t);
 }
 
+template <int ST, int W, int EMAX>
+int launch_lds(cosm_state *s, const LdsArgs &a) {
+  const size_t lds = s->shape.lds_bytes;
+  (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, W, EMAX>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_sweep_lds<ST, W, EMAX>), dim3(s->shape.blocks), dim3(s->shape.threads), lds,
+                     s->stream, a);
+  return launch_check("k_sweep_lds");
+}
+
+template <int ST, int W>
+int launch_lds_w(cosm_state *s, const LdsArgs &a) {
+  const int slots = a.total_slots;
+  if (slots <= 4) return launch_lds<ST, W, 4>(s, a);
+  if (slots <= 8) return launch_lds<ST, W, 8>(s, a);
+  if (slots <= 16) return launch_lds<ST, W, 16>(s, a);
+  return launch_lds<ST, W, 0>(s, a);
+}
+
 template <int ST>
 int sweeps_lds_st(cosm_state *s, int64_t n_sweeps) {
   LdsArgs a{};
   a.phases = s->d.phases;
   a.desc = s->d.desc;
-  a.class_off = s->d.class_off;
+  a.Kc = s->d.class_off;
   a.slot_vertex = s->d.slot_vertex;
   a.R = s->R;
-  a.n_slots = s->n_slots;
+  a.n_rows = s->lds.n_rows;
   a.C = s->C;
+  a.total_slots = s->lds.total_slots;
   a.t0 = s->t;
   a.nsw = n_sweeps;
+  uint32_t mask = 0;
+  {
+    int j = 0;
+    for (int c = 0; c < s->C; c++) {
+      j += s->lds.K[(size_t)c];
+      if (s->lds.K[(size_t)c] > 0 && j - 1 < 32) mask |= 1u << (j - 1);
+    }
+  }
+  a.bar_mask = mask;
   const Schedule &sc = s->sched;
   SweepSchedule &w = a.sch;
   w.grid = sc.grid;
@@ -652,25 +759,11 @@ int sweeps_lds_st(cosm_state *s, int64_t n_sweeps) {
   a.k0 = (uint32_t)(s->seed & 0xffffffffu);
   a.k1 = (uint32_t)(s->seed >> 32);
   a.rid0 = (uint32_t)s->rid0;
-  const dim3 grid(s->shape.blocks), block(s->shape.threads);
-  const size_t lds = s->shape.lds_bytes;
   const int W = s->shape.rw / Fmt<ST>::kPerWord;
-  if (W == 4) {
-    (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, 4>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_sweep_lds<ST, 4>), grid, block, lds, s->stream, a);
-  } else if (W == 2) {
-    (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, 2>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_sweep_lds<ST, 2>), grid, block, lds, s->stream, a);
-  } else if (W == 1) {
-    (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, 1>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_sweep_lds<ST, 1>), grid, block, lds, s->stream, a);
-  } else {
-    return set_error(COSM_EINVAL, "unsupported replicas per workgroup");
-  }
-  return launch_check("k_sweep_lds");
+  if (W == 4) return launch_lds_w<ST, 4>(s, a);
+  if (W == 2) return launch_lds_w<ST, 2>(s, a);
+  if (W == 1) return launch_lds_w<ST, 1>(s, a);
+  return set_error(COSM_EINVAL, "unsupported replicas per workgroup");
 }
 
 template <int ST>

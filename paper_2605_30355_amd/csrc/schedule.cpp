@@ -1,0 +1,197 @@
+// schedule.cpp -- LDS layout and lane schedule of the LDS-resident sweep.
+//
+// The sweep kernel keeps a replica block as LDS rows (one row per slot) and
+// lets consecutive lanes take consecutive entries of a class's edge list.  LDS
+// serves 128 bytes per clock: a row access of 4 W bytes by G = 32 / W
+// consecutive lanes is conflict-free when the G rows touched lie in distinct
+// residues (slot mod G).  Within a colour class the edges are a matching, so
+// their order is free; this file picks
+//   1. a vertex -> slot map that spreads every class's u-endpoints, and its
+//      v-endpoints, evenly over the G residues;
+//   2. per class, an order made of aligned groups of G entries in which the
+//      u-residues are distinct and the v-residues are distinct: a proper edge
+//      colouring of the bipartite multigraph (u-residue, v-residue), which
+//      König's theorem gives with as many colours as its maximum degree;
+//      unused lanes of a group are masked off.
+// None of this changes the dynamics: each class is still applied in full, in
+// the class order given by the caller.
+#include <algorithm>
+#include <numeric>
+#include <random>
+
+#include "internal.hpp"
+
+namespace cosm {
+
+namespace {
+
+// Edge colouring of a bipartite multigraph with Delta colours (alternating-path
+// recolouring).  left/right in [0, G); returns colour per edge and the count.
+int32_t bipartite_edge_colouring(int32_t G, const std::vector<int32_t> &left,
+                                 const std::vector<int32_t> &right, std::vector<int32_t> *col) {
+  const size_t E = left.size();
+  std::vector<int32_t> degL((size_t)G, 0), degR((size_t)G, 0);
+  for (size_t e = 0; e < E; e++) {
+    degL[(size_t)left[e]]++;
+    degR[(size_t)right[e]]++;
+  }
+  int32_t D = 0;
+  for (int32_t g = 0; g < G; g++) D = std::max({D, degL[(size_t)g], degR[(size_t)g]});
+  // atL[a*D + c] = edge coloured c at left node a (or -1); same for atR
+  std::vector<int32_t> atL((size_t)G * D, -1), atR((size_t)G * D, -1);
+  col->assign(E, -1);
+  auto freeL = [&](int32_t a) {
+    for (int32_t c = 0; c < D; c++)
+      if (atL[(size_t)a * D + c] < 0) return c;
+    return -1;
+  };
+  auto freeR = [&](int32_t b) {
+    for (int32_t c = 0; c < D; c++)
+      if (atR[(size_t)b * D + c] < 0) return c;
+    return -1;
+  };
+  std::vector<int32_t> path;
+  for (size_t e = 0; e < E; e++) {
+    const int32_t a = left[e], b = right[e];
+    const int32_t al = freeL(a), be = freeR(b);
+    if (atR[(size_t)b * D + al] >= 0) {
+      // swap al <-> be along the path from b that starts with b's al-edge
+      path.clear();
+      int32_t node = b, c = al;
+      bool on_right = true;
+      while (true) {
+        const int32_t f = on_right ? atR[(size_t)node * D + c] : atL[(size_t)node * D + c];
+        if (f < 0) break;
+        path.push_back(f);
+        node = on_right ? left[(size_t)f] : right[(size_t)f];
+        on_right = !on_right;
+        c = (c == al) ? be : al;
+      }
+      for (int32_t f : path) {
+        atL[(size_t)left[(size_t)f] * D + (*col)[(size_t)f]] = -1;
+        atR[(size_t)right[(size_t)f] * D + (*col)[(size_t)f]] = -1;
+      }
+      for (int32_t f : path) {
+        const int32_t nc = (*col)[(size_t)f] == al ? be : al;
+        (*col)[(size_t)f] = nc;
+        atL[(size_t)left[(size_t)f] * D + nc] = f;
+        atR[(size_t)right[(size_t)f] * D + nc] = f;
+      }
+    }
+    (*col)[e] = al;
+    atL[(size_t)a * D + al] = (int32_t)e;
+    atR[(size_t)b * D + al] = (int32_t)e;
+  }
+  return D;
+}
+
+}  // namespace
+
+int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out) {
+  const int32_t n = s.n, C = s.C, G = 32 / W;
+  const int64_t m = s.m;
+  LdsSchedule &L = *out;
+  L.G = G;
+  L.n_rows = n;
+  if (n > 65536) return set_error(COSM_ERANGE, "too many LDS rows");
+
+  // 1. residue of every vertex: greedy balancing of the per-class, per-side
+  // residue counts; residue g owns the slots g, g + G, ... below n.
+  // inc[i] lists (class, side) pairs of vertex i.
+  std::vector<std::vector<int32_t>> inc((size_t)n);
+  for (int64_t k = 0; k < m; k++) {
+    inc[(size_t)s.h_eu[(size_t)k]].push_back(2 * s.h_colour[(size_t)k]);
+    inc[(size_t)s.h_ev[(size_t)k]].push_back(2 * s.h_colour[(size_t)k] + 1);
+  }
+  std::vector<int32_t> cnt((size_t)2 * C * G, 0), cap((size_t)G, 0), res((size_t)n, 0);
+  for (int32_t g = 0; g < G; g++) cap[(size_t)g] = (n - g + G - 1) / G;
+  std::vector<int32_t> order((size_t)n);
+  std::iota(order.begin(), order.end(), 0);
+  std::mt19937 rng(12345u);
+  std::shuffle(order.begin(), order.end(), rng);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return inc[(size_t)a].size() > inc[(size_t)b].size();
+  });
+  for (int32_t i : order) {
+    int32_t best = -1;
+    int64_t best_cost = 0;
+    for (int32_t g = 0; g < G; g++) {
+      if (cap[(size_t)g] == 0) continue;
+      int64_t cost = 0;  // sum of squares of the counts this choice raises
+      for (int32_t cs : inc[(size_t)i]) {
+        const int64_t v = cnt[(size_t)cs * G + g];
+        cost += 2 * v + 1;
+      }
+      if (best < 0 || cost < best_cost) {
+        best = g;
+        best_cost = cost;
+      }
+    }
+    res[(size_t)i] = best;
+    cap[(size_t)best]--;
+    for (int32_t cs : inc[(size_t)i]) cnt[(size_t)cs * G + best]++;
+  }
+  // slots: residue g holds slots g, g + G, g + 2G, ... in vertex order
+  L.slot_vertex.assign((size_t)L.n_rows, -1);
+  std::vector<int32_t> slot((size_t)n), next_in_res((size_t)G, 0);
+  for (int32_t i = 0; i < n; i++) {
+    const int32_t g = res[(size_t)i];
+    slot[(size_t)i] = g + G * next_in_res[(size_t)g]++;
+    L.slot_vertex[(size_t)slot[(size_t)i]] = i;
+  }
+
+  // 2. per class: bipartite colouring of (u residue, v residue) -> groups of G
+  std::vector<std::vector<int64_t>> by_class((size_t)C);
+  for (int64_t k = 0; k < m; k++) by_class[(size_t)s.h_colour[(size_t)k]].push_back(k);
+  L.K.assign((size_t)C, 0);
+  L.padded.assign((size_t)C, 0);
+  std::vector<std::vector<EdgeDesc>> lists((size_t)C);
+  for (int32_t c = 0; c < C; c++) {
+    const auto &E = by_class[(size_t)c];
+    if (E.empty()) continue;
+    std::vector<int32_t> lft(E.size()), rgt(E.size()), col;
+    for (size_t a = 0; a < E.size(); a++) {
+      lft[a] = slot[(size_t)s.h_eu[(size_t)E[a]]] % G;
+      rgt[a] = slot[(size_t)s.h_ev[(size_t)E[a]]] % G;
+    }
+    const int32_t D = bipartite_edge_colouring(G, lft, rgt, &col);
+    auto &lst = lists[(size_t)c];
+    lst.assign((size_t)D * G, EdgeDesc{kEmptySlot, 0.0f});  // unfilled lanes stay masked
+    std::vector<int32_t> fill((size_t)D, 0);
+    for (size_t a = 0; a < E.size(); a++) {
+      const int32_t g = col[a];
+      const int64_t k = E[a];
+      const uint32_t su = (uint32_t)slot[(size_t)s.h_eu[(size_t)k]];
+      const uint32_t sv = (uint32_t)slot[(size_t)s.h_ev[(size_t)k]];
+      lst[(size_t)g * G + fill[(size_t)g]++] = EdgeDesc{su | (sv << 16), (float)s.h_J[(size_t)k]};
+    }
+    L.padded[(size_t)c] = (int32_t)lst.size();
+  }
+  // threads: enough for the largest class in one pass, a multiple of 64, <= 1024
+  int32_t maxp = 0;
+  for (int32_t c = 0; c < C; c++) maxp = std::max(maxp, L.padded[(size_t)c]);
+  int32_t nth = nth_request;
+  if (nth <= 0) nth = std::min(1024, std::max(64, (maxp + 63) / 64 * 64));
+  L.nth = nth;
+  for (int32_t c = 0; c < C; c++) L.K[(size_t)c] = (L.padded[(size_t)c] + nth - 1) / nth;
+  // 3. flatten: entry (j, tid) of the per-thread slot list, j running over
+  // classes in order and K[c] slots per class.
+  L.total_slots = 0;
+  for (int32_t c = 0; c < C; c++) L.total_slots += L.K[(size_t)c];
+  L.desc.assign((size_t)L.total_slots * nth, EdgeDesc{kEmptySlot, 0.0f});
+  int32_t j = 0;
+  for (int32_t c = 0; c < C; c++) {
+    const auto &lst = lists[(size_t)c];
+    for (int32_t k = 0; k < L.K[(size_t)c]; k++, j++)
+      for (int32_t t = 0; t < nth; t++) {
+        const size_t pos = (size_t)k * nth + t;
+        if (pos < lst.size()) L.desc[(size_t)j * nth + t] = lst[pos];
+      }
+  }
+  int64_t pad = 0;
+  for (int32_t c = 0; c < C; c++) pad += L.padded[(size_t)c] - (int64_t)by_class[(size_t)c].size();
+  L.pad_entries = pad;
+  return COSM_OK;
+}
+
+}  // namespace cosm

@@ -1,0 +1,49 @@
+// Host-only check of the LDS lane schedule built by schedule.cpp.
+// Input on stdin: "n m C" then m lines "u v J colour".  Prints a summary line;
+// exit status 0 only if the slot map is a permutation.  The caller checks
+// "conflicts=0" (distinct bank groups per aligned lane group, u-rows and
+// v-rows separately) and "equal=1" (every edge exactly once).
+#include "internal.hpp"
+#include <cstdio>
+#include <set>
+#include <fstream>
+#include <vector>
+int cosm::set_error(int st, const std::string& m){ fprintf(stderr,"err %s\n",m.c_str()); return st; }
+void cosm::clear_error(){}
+int main(int argc, char** argv) {
+  // reads n m C then m lines u v J colour from stdin
+  int n; long m; int C; int W = atoi(argv[1]);
+  if (scanf("%d %ld %d", &n, &m, &C) != 3) return 1;
+  cosm_state s; s.n = n; s.m = m; s.C = C;
+  for (long k = 0; k < m; k++) { int u, v, J, c; if (scanf("%d %d %d %d", &u, &v, &J, &c) != 4) return 1;
+    s.h_eu.push_back(u); s.h_ev.push_back(v); s.h_J.push_back(J); s.h_colour.push_back(c); }
+  cosm::LdsSchedule L;
+  if (cosm::build_lds_schedule(s, W, 0, &L)) return 2;
+  // permutation
+  std::vector<int> seen(n, 0); for (int sl = 0; sl < L.n_rows; sl++) { if (L.slot_vertex[sl] < 0 || L.slot_vertex[sl] >= n) { puts("BAD slot map"); return 3; } seen[L.slot_vertex[sl]]++; }
+  for (int i = 0; i < n; i++) if (seen[i] != 1) { puts("BAD perm"); return 3; }
+  std::vector<int> vslot(n); for (int sl = 0; sl < n; sl++) vslot[L.slot_vertex[sl]] = sl;
+  // each edge once, in its class, conflict-free groups
+  // (class, slot_u, slot_v, J) of every edge, expected and scheduled
+  std::multiset<std::tuple<int,int,int,float>> want, got;
+  for (long k = 0; k < m; k++) want.insert({s.h_colour[k], vslot[s.h_eu[k]] , vslot[s.h_ev[k]], (float)s.h_J[k]});
+  int j = 0; long conflicts = 0, active = 0;
+  for (int c = 0; c < C; c++) {
+    for (int k = 0; k < L.K[c]; k++, j++) {
+      for (int g0 = 0; g0 < L.nth; g0 += L.G) {
+        std::set<int> ru, rv; int act = 0;
+        for (int t = g0; t < g0 + L.G; t++) {
+          auto d = L.desc[(size_t)j * L.nth + t];
+          if (d.slots == cosm::kEmptySlot) continue;
+          act++; active++;
+          int su = d.slots & 0xffff, sv = d.slots >> 16;
+          got.insert({c, su, sv, d.J});
+          ru.insert(su % L.G); rv.insert(sv % L.G);
+        }
+        conflicts += (act - (long)ru.size()) + (act - (long)rv.size());
+      }
+    }
+  }
+  printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got));
+  return 0;
+}

@@ -58,6 +58,17 @@ def test_misra_gries_proper_and_at_most_delta_plus_one(inst):
     assert np.all(np.bincount(colour, minlength=C) > 0)
 
 
+@pytest.mark.parametrize("inst", INSTANCES, ids=lambda i: i.name)
+def test_balanced_is_proper_equalised_and_same_count(inst):
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+    _, Cmg = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_MISRA_GRIES)
+    assert C == Cmg
+    assert oracle.is_proper_colouring(inst.n, inst.eu, inst.ev, colour, C)
+    sizes = np.bincount(colour, minlength=C)
+    if inst.m >= 100:
+        assert sizes.max() - sizes.min() <= 1
+
+
 def test_misra_gries_many_random_graphs():
     rng = np.random.default_rng(0)
     for k in range(60):

@@ -162,10 +162,11 @@ def test_ragged_replicas_and_resume():
 
 
 def test_c2_full_size_sampled():
-    """3-regular N=2000 Max-Cut (+1 weights), MG colouring, 1024 replicas, 1e4
-    sweeps, in the launch shape the benchmark uses; 6 replicas checked."""
+    """3-regular N=2000 Max-Cut (+1 weights), equalised Misra-Gries colouring,
+    1024 replicas, 1e4 sweeps, in the launch shape the benchmark uses; 6
+    replicas checked."""
     inst = ci.random_regular(2000, 3, seed=2, weights="maxcut1")
-    colour, C, prob = make(inst, cosm.COLOR_MISRA_GRIES)
+    colour, C, prob = make(inst, cosm.COLOR_BALANCED)
     p = cosm.Params(sweeps_per_trial=10000, dwt_ratio=1.0, dwt_period=6)
     info = check_trial(inst, colour, C, prob, p, seed=42, R=1024, sweeps=10000,
                        sample=[0, 1, 511, 512, 1022, 1023])
