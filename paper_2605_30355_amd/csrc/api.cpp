@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -122,9 +123,6 @@ int device_cu_count() {
   return v > 0 ? v : 256;
 }
 
-// LDS bytes of the sweep kernel for W words per row.
-// (rows, then two buffers of reference angles for up to 8 replicas)
-size_t lds_sweep_bytes(int32_t n_slots, int W) { return (size_t)n_slots * W * 4 + 2 * 8 * 4; }
 
 // Choose residency, replicas per workgroup and threads.  The LDS form is used
 // when a replica block fits; among fitting shapes prefer the widest rows that
@@ -157,6 +155,7 @@ int choose_shape(cosm_state *s) {
       int best_full = 0, smallest_fit = 0;
       for (int W : {4, 2, 1}) {
         if (lds_sweep_bytes(s->n_slots, W) > cap) continue;
+        s->lds_widths.push_back(W);
         const int64_t blocks = (s->R + W * pw - 1) / (W * pw);
         if (blocks >= cus && best_full == 0) best_full = W;
         smallest_fit = W;
@@ -365,6 +364,10 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
     delete s;
     return rc;
   }
+  const char *tune_env = std::getenv("COSM_AUTOTUNE");
+  const bool autotune = s->shape.residency == COSM_RES_LDS && p->replicas_per_wg == 0 &&
+                        p->threads_per_wg == 0 && s->lds_widths.size() > 0 &&
+                        !(tune_env && tune_env[0] == '0');
   if (readout_lds_bytes(n, s->p.n_bisectors) > (size_t)lds_capacity_bytes()) {
     delete s;
     return set_error(COSM_ERANGE, "the readout of one replica does not fit in LDS");
@@ -435,6 +438,8 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   if (rc == COSM_OK && hipEventCreate(&s->ev1) != hipSuccess) rc = set_error(COSM_EDEVICE, "hipEventCreate");
   rc = rc ? rc : launch_init(s);
   rc = rc ? rc : sync(s);  // the host vectors above must outlive the copies
+  if (rc == COSM_OK && autotune) rc = autotune_lds_shape(s, s->lds_widths);
+  rc = rc ? rc : sync(s);
   if (rc) {
     cosm_destroy(s);
     return rc;

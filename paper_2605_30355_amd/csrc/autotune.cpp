@@ -1,0 +1,131 @@
+// autotune.cpp -- picks the LDS sweep kernel's shape by measurement.
+//
+// Candidates: every LDS row width that fits (1, 2 or 4 words per row, i.e. 1-4
+// FP32 or 2-8 16-bit replicas per workgroup) crossed with a few thread counts.
+// Each candidate runs a short timed probe on the state's own phases (which are
+// re-drawn afterwards, so the probe leaves no trace in the trajectory), and the
+// fastest shape is kept.  Results are cached per process, keyed by the
+// instance's size signature.  None of the candidates changes the dynamics: they
+// differ only in how the same class-by-class updates are laid out on the GPU.
+#include <algorithm>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "internal.hpp"
+
+namespace cosm {
+
+namespace {
+
+using Key = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t, int32_t, int64_t>;
+std::mutex g_cache_mu;
+std::map<Key, std::pair<int32_t, int32_t>> g_cache;  // -> (W, threads)
+
+Key make_key(const cosm_state &s) {
+  int64_t h = 1469598103934665603LL;  // FNV-1a over the class sizes
+  for (int32_t c : s.class_sizes) h = (h ^ c) * 1099511628211LL;
+  int32_t delta = 0;
+  {
+    std::vector<int32_t> deg((size_t)s.n, 0);
+    for (int64_t k = 0; k < s.m; k++) {
+      deg[(size_t)s.h_eu[(size_t)k]]++;
+      deg[(size_t)s.h_ev[(size_t)k]]++;
+    }
+    for (int32_t d : deg) delta = std::max(delta, d);
+  }
+  return Key{s.n, s.m, s.C, delta, s.R, s.p.storage, h};
+}
+
+int upload_schedule(cosm_state *s) {
+  const LdsSchedule &L = s->lds;
+  COSM_HIP_CHECK(hipMemcpyAsync(s->d.desc, L.desc.data(), L.desc.size() * sizeof(EdgeDesc),
+                                hipMemcpyHostToDevice, s->stream));
+  if (!L.K.empty())
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.class_off, L.K.data(), L.K.size() * 4,
+                                  hipMemcpyHostToDevice, s->stream));
+  COSM_HIP_CHECK(hipMemcpyAsync(s->d.slot_vertex, L.slot_vertex.data(),
+                                L.slot_vertex.size() * 4, hipMemcpyHostToDevice, s->stream));
+  COSM_HIP_CHECK(hipStreamSynchronize(s->stream));  // host vectors may change next
+  return COSM_OK;
+}
+
+int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw) {
+  if (int rc = build_lds_schedule(*s, W, nth, &s->lds)) return rc;
+  s->shape.residency = COSM_RES_LDS;
+  s->shape.rw = W * pw;
+  s->shape.blocks = (s->R + s->shape.rw - 1) / s->shape.rw;
+  s->shape.lds_bytes = (int32_t)lds_sweep_bytes(s->n_slots, W);
+  s->shape.threads = s->lds.nth;
+  return upload_schedule(s);
+}
+
+}  // namespace
+
+int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
+  const int32_t pw = s->p.storage == COSM_STORE_FP32 ? 1 : 2;
+  const Key key = make_key(*s);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) return apply_shape(s, it->second.first, it->second.second, pw);
+  }
+  const int64_t probe = std::min<int64_t>(64, s->p.sweeps_per_trial);
+  hipEvent_t e0, e1;
+  COSM_HIP_CHECK(hipEventCreate(&e0));
+  COSM_HIP_CHECK(hipEventCreate(&e1));
+  float best_ms = 0.0f;
+  int32_t best_W = 0, best_nth = 0;
+  int rc = COSM_OK;
+  const bool timing = s->timing;
+  s->timing = false;
+  std::vector<std::pair<int32_t, int32_t>> tried;
+  for (int32_t W : widths) {
+    int32_t auto_nth = 0;
+    for (int32_t req : {0, 512, 768, 1024}) {
+      if (req > 0 && req < auto_nth / 2) continue;  // far too few threads for one pass
+      rc = apply_shape(s, W, req, pw);
+      if (rc) break;
+      if (req == 0) auto_nth = s->lds.nth;
+      if (std::find(tried.begin(), tried.end(), std::make_pair(W, s->lds.nth)) != tried.end())
+        continue;
+      tried.emplace_back(W, s->lds.nth);
+      const int64_t t_saved = s->t;
+      rc = launch_sweeps(s, probe);  // warm-up
+      s->t = t_saved;
+      if (rc) break;
+      if (hipEventRecord(e0, s->stream) != hipSuccess) { rc = set_error(COSM_EDEVICE, "event"); break; }
+      rc = launch_sweeps(s, probe);
+      s->t = t_saved;
+      if (rc) break;
+      if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = set_error(COSM_EDEVICE, "event");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best_W == 0 || ms < best_ms) {
+        best_ms = ms;
+        best_W = W;
+        best_nth = s->lds.nth;
+      }
+    }
+    if (rc) break;
+  }
+  s->timing = timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  s->launches = 0;
+  s->kernel_ms = 0.0;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache[key] = {best_W, best_nth};
+  }
+  rc = apply_shape(s, best_W, best_nth, pw);
+  if (rc) return rc;
+  return launch_init(s);  // the probes moved the phases: draw them again
+}
+
+}  // namespace cosm

@@ -138,6 +138,7 @@ struct cosm_state {
   int32_t n_slots = 0;
   int32_t max_class = 0;
   cosm::LdsSchedule lds;  // resolved lane schedule of the LDS form
+  std::vector<int32_t> lds_widths;  // row widths (words) that fit, for the autotuner
   bool has_h = false;
   int64_t sumJ = 0;
   std::vector<int32_t> h_eu, h_ev, h_J, h_h, h_colour;
@@ -161,6 +162,11 @@ int launch_to_turns(cosm_state *s, float *turns_dev);
 int launch_from_turns(cosm_state *s, const float *turns_dev);
 int lds_capacity_bytes();
 int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out);
+// Measure candidate LDS shapes (row widths in words) and keep the fastest.
+int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths);
+// LDS bytes of the sweep kernel: the rows, then two buffers of reference
+// angles for up to 8 replicas.
+inline size_t lds_sweep_bytes(int32_t n_rows, int W) { return (size_t)n_rows * W * 4 + 2 * 8 * 4; }
 
 size_t readout_lds_bytes(int32_t n, int32_t B);
 }  // namespace cosm
