@@ -88,6 +88,92 @@ def cpu_baseline(inst, colour, C, seconds_goal=10.0):
             "seconds": round(dt, 2)}
 
 
+STREAM = dict(name="mixed-stream-256", requests=256, n_min=400, n_max=20000, seed=5,
+              replicas=256, sweeps=10000, load=0.7)
+FAMILY_PARAMS = {"torus": dict(dwt_ratio=0.5, dwt_period=3),
+                 "3-regular": dict(dwt_ratio=1.0, dwt_period=6),
+                 "5-regular": dict(dwt_ratio=1.5, dwt_period=3)}
+
+
+def stream_bench():
+    """Mixed request stream: 256 solve requests (N uniform in [400, 20000]; torus,
+    3-regular Max-Cut and 5-regular +-1 graphs), each a whole trial of 256
+    replicas x 10^4 sweeps, served by one batch (one persistent sweep launch per
+    micro-batch, replayed from a hipGraph).  First all requests at t = 0 (the
+    burst gives the capacity), then Poisson arrivals at 70 % of that capacity."""
+    import numpy as np
+    import torch
+
+    import cosm_inputs as ci
+    import paper_2605_30355_amd as cosm
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    reqs = ci.request_stream(STREAM["requests"], STREAM["n_min"], STREAM["n_max"], STREAM["seed"])
+    b = cosm.Batch(max_graphs=STREAM["requests"], max_n=STREAM["n_max"] + 1)
+    ids, updates = [], 0
+    for k, (_, inst) in enumerate(reqs):
+        fam = inst.meta["family"]
+        if fam == "torus":
+            L = inst.meta["Lx"]
+            colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [L, L])
+        else:
+            colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+        p = cosm.Params(sweeps_per_trial=STREAM["sweeps"], **FAMILY_PARAMS[fam])
+        ids.append(b.add(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=k,
+                         replicas=STREAM["replicas"]))
+        updates += inst.m * STREAM["sweeps"] * STREAM["replicas"]
+    log(f"stream: {len(ids)} requests prepared in {time.perf_counter() - t0:.1f} s")
+    b.run(ids[:4])  # warm-up (captures the graph)
+    b.wait()
+    # burst: every request at t = 0, one launch
+    t0 = time.perf_counter()
+    b.run(ids)
+    dev_ms = b.wait()
+    burst_s = time.perf_counter() - t0
+    capacity = len(ids) / burst_s
+    log(f"stream burst: {burst_s:.2f} s ({dev_ms:.0f} ms device), {capacity:.1f} requests/s")
+    # Poisson arrivals at STREAM["load"] x capacity, micro-batched when the GPU is idle
+    rng = np.random.default_rng(STREAM["seed"])
+    arrivals = np.cumsum(rng.exponential(1.0 / (STREAM["load"] * capacity), size=len(ids)))
+    done = np.zeros(len(ids))
+    nxt, launches = 0, 0
+    start = time.perf_counter()
+    while nxt < len(ids):
+        now = time.perf_counter() - start
+        if arrivals[nxt] > now:
+            time.sleep(min(arrivals[nxt] - now, 0.002))
+            continue
+        batch = []
+        while nxt < len(ids) and arrivals[nxt] <= now:
+            batch.append(nxt)
+            nxt += 1
+        for k in batch:
+            b.set_seed(ids[k], 1000 + k, 0)
+        b.run([ids[k] for k in batch])
+        b.wait()
+        launches += 1
+        done[batch] = time.perf_counter() - start
+    lat = (done - arrivals) * 1e3
+    span = done.max() - arrivals[0]
+    b.close()
+    return {
+        "metric": "mixed request stream on one MI355X (latency and throughput)",
+        "workload": STREAM["name"], "requests": len(ids), "replicas_per_request": STREAM["replicas"],
+        "sweeps_per_request": STREAM["sweeps"], "n_range": [STREAM["n_min"], STREAM["n_max"]],
+        "families": list(FAMILY_PARAMS), "total_edge_updates": updates,
+        "burst": {"seconds": round(burst_s, 3), "device_ms": round(dev_ms, 1),
+                  "requests_per_s": round(capacity, 2),
+                  "edge_updates_per_s": round(updates / burst_s, 1)},
+        "poisson": {"rate_per_s": round(STREAM["load"] * capacity, 2), "launches": launches,
+                    "p50_ms": round(float(np.percentile(lat, 50)), 1),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 1),
+                    "mean_ms": round(float(lat.mean()), 1),
+                    "requests_per_s": round(len(ids) / span, 2),
+                    "edge_updates_per_s": round(updates / span, 1)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,12 +183,17 @@ def main():
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--stream", action="store_true",
+                    help="measure the mixed request stream instead (prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's replicas are independent, so several "
               "GPUs would each run this same single-GPU job on their own replicas; "
               "run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.stream:
+        print(json.dumps(stream_bench()), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -116,13 +207,16 @@ def main():
     log(f"workload {WORKLOAD['name']}: n={inst.n} m={m} C={C} R={R} S={S}")
 
     if args.copy_probe:
+        # 256 MiB source, then 1 GiB of other writes so that the copy reads HBM
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
+        evict = torch.empty(256 << 20, dtype=torch.float32, device="cuda")
         a.fill_(1.0)
+        evict.fill_(2.0)
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        del a, b
+        del a, b, evict
 
     # ---- batched LDS-resident form: the timed steps --------------------------------
     st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, params(cosm), seed=1,

@@ -189,6 +189,42 @@ typedef struct {
 int cosm_solve_to_target(cosm_state *s, int64_t target_H, int64_t max_trials,
                          int32_t stop_at_first_hit, cosm_tts_result *out, int8_t *best_spins);
 
+/* ---- many instances in one persistent launch ------------------------------- */
+/* A batch holds instances of uneven sizes (each with its own couplings,
+ * colouring, parameters, seed and replica count) and runs whole trials of any
+ * subset of them with one persistent sweep launch: work items (instance, first
+ * replica, replica sets) are taken from a device counter by one workgroup per
+ * CU; a small instance packs several replica sets into one workgroup's LDS.
+ * Init, sweeps and readout are captured once into a hipGraph and replayed by
+ * every run.  Trajectories are the same as cosm_init / cosm_sweep / cosm_energy
+ * with the same seed and replica offset.  Storage is fixed per batch; the SCS
+ * update only; no bias fields. */
+typedef struct cosm_batch cosm_batch;
+/* max_graphs: instances the batch can hold; max_n: largest instance (<= 65536);
+ * max_bisectors: largest B; hip_stream: NULL makes the batch use a stream of its
+ * own (a graph cannot be captured on the legacy default stream).  ERANGE if a
+ * readout of max_n spins does not fit in LDS. */
+int cosm_batch_create(cosm_batch **out, int32_t storage, int32_t max_graphs, int32_t max_n,
+                      int32_t max_bisectors, void *hip_stream);
+int cosm_batch_destroy(cosm_batch *b);
+/* Add an instance (arguments as cosm_init; p->storage must match the batch).
+ * Uploads it, builds its lane schedule, and returns its id (0, 1, ...). */
+int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
+                         const int32_t *ev, const int32_t *J, const int32_t *colour,
+                         int32_t num_colours, const cosm_params *p, uint64_t seed,
+                         int32_t replicas, int32_t *graph_id_out);
+/* Seed and global index of replica 0 used by the next run of that instance. */
+int cosm_batch_set_seed(cosm_batch *b, int32_t graph_id, uint64_t seed, int64_t replica_offset);
+/* Enqueue one whole trial (init, S sweeps, readout) of every listed instance.
+ * Asynchronous; host tables are copied before returning. */
+int cosm_batch_run(cosm_batch *b, const int32_t *graph_ids, int32_t count);
+/* Wait for the last run; *device_ms_out (may be NULL) = its device time. */
+int cosm_batch_wait(cosm_batch *b, double *device_ms_out);
+/* Results of an instance's last run: H, cut ([R] int64) and spins ([R][n]); any
+ * output may be NULL.  Synchronises the batch's stream. */
+int cosm_batch_results(cosm_batch *b, int32_t graph_id, int64_t *H_out, int64_t *cut_out,
+                       int8_t *spins_out);
+
 /* ---- phase access ------------------------------------------------------------ */
 /* Copy the phases out as [R][n] doubles in the given unit (COSM_UNIT_*); turns
  * and degrees are exact.  Synchronises the stream. */

@@ -14,6 +14,6 @@ from .cosm import (  # noqa: F401
     STORE_BF16, STORE_FP16, STORE_FP32,
     UNIT_DEGREES, UNIT_RADIANS, UNIT_TURNS,
     UPDATE_FULL_GRADIENT, UPDATE_SCS,
-    CosmError, Params, State, TTSResult,
+    Batch, CosmError, Params, State, TTSResult,
     build_partitions, default_params, exported_symbols, library_path, load_library, version,
 )

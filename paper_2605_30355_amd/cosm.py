@@ -27,6 +27,8 @@ ABI_FUNCTIONS = (
     "cosm_destroy", "cosm_reset", "cosm_sweep", "cosm_energy", "cosm_solve_to_target",
     "cosm_get_phases", "cosm_set_phases", "cosm_get_info", "cosm_set_timing",
     "cosm_last_error", "cosm_version",
+    "cosm_batch_create", "cosm_batch_destroy", "cosm_batch_add_graph", "cosm_batch_set_seed",
+    "cosm_batch_run", "cosm_batch_wait", "cosm_batch_results",
 )
 
 
@@ -98,6 +100,14 @@ def load_library():
         "cosm_get_info": (I32, [P, ctypes.POINTER(_CInfo)]),
         "cosm_set_timing": (I32, [P, I32]),
         "cosm_last_error": (ctypes.c_char_p, []),
+        "cosm_batch_create": (I32, [ctypes.POINTER(P), I32, I32, I32, I32, P]),
+        "cosm_batch_destroy": (I32, [P]),
+        "cosm_batch_add_graph": (I32, [P, I32, I64, P, P, P, P, I32, PS, U64, I32,
+                                       ctypes.POINTER(I32)]),
+        "cosm_batch_set_seed": (I32, [P, I32, U64, I64]),
+        "cosm_batch_run": (I32, [P, P, I32]),
+        "cosm_batch_wait": (I32, [P, ctypes.POINTER(ctypes.c_double)]),
+        "cosm_batch_results": (I32, [P, I32, P, P, P]),
         "cosm_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -287,3 +297,73 @@ class State:
 
     def set_timing(self, on: bool):
         _check(load_library().cosm_set_timing(self._h_state, int(bool(on))))
+
+
+class Batch:
+    """A cosm_batch: instances of uneven sizes run as whole trials by one
+    persistent sweep launch (init, sweeps and readout replayed from a hipGraph).
+    Runs on a torch stream of its own (graphs cannot be captured on the default
+    stream)."""
+
+    def __init__(self, storage=STORE_FP32, max_graphs=256, max_n=20000, max_bisectors=100):
+        import torch
+        L = load_library()
+        if not torch.cuda.is_available():
+            raise CosmError(-6, "no HIP device is visible")
+        self._stream = torch.cuda.Stream()
+        self.storage = storage
+        h = ctypes.c_void_p()
+        _check(L.cosm_batch_create(ctypes.byref(h), int(storage), int(max_graphs), int(max_n),
+                                   int(max_bisectors), ctypes.c_void_p(self._stream.cuda_stream)))
+        self._b = h
+        self._sizes = []
+        self._keep = []
+
+    def add(self, n, eu, ev, J, colour, num_colours, params: Params, seed=0, replicas=1):
+        eu, ev, J, colour = _i32(eu), _i32(ev), _i32(J), _i32(colour)
+        gid = ctypes.c_int32(0)
+        cp = params._c()
+        _check(load_library().cosm_batch_add_graph(
+            self._b, int(n), len(eu), _ptr(eu), _ptr(ev), _ptr(J), _ptr(colour), int(num_colours),
+            ctypes.byref(cp), int(seed) & ((1 << 64) - 1), int(replicas), ctypes.byref(gid)))
+        self._sizes.append((int(n), int(replicas)))
+        return int(gid.value)
+
+    def set_seed(self, graph_id, seed, replica_offset=0):
+        _check(load_library().cosm_batch_set_seed(self._b, int(graph_id),
+                                                  int(seed) & ((1 << 64) - 1), int(replica_offset)))
+
+    def run(self, graph_ids):
+        ids = _i32(graph_ids)
+        _check(load_library().cosm_batch_run(self._b, _ptr(ids), len(ids)))
+
+    def wait(self):
+        ms = ctypes.c_double(0.0)
+        _check(load_library().cosm_batch_wait(self._b, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def results(self, graph_id, return_spins=False):
+        n, R = self._sizes[graph_id]
+        H = np.zeros(R, dtype=np.int64)
+        cut = np.zeros(R, dtype=np.int64)
+        sp = np.zeros((R, n), dtype=np.int8) if return_spins else None
+        _check(load_library().cosm_batch_results(self._b, int(graph_id), _ptr(H), _ptr(cut),
+                                                 _ptr(sp)))
+        return H, cut, sp
+
+    def close(self):
+        if getattr(self, "_b", None):
+            load_library().cosm_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -67,6 +67,12 @@ MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_param
   return mp;
 }
 
+}  // namespace
+
+int check_params_public(const cosm_params *p);
+
+namespace {
+
 int check_params(const cosm_params *p) {
   if (p == nullptr) return set_error(COSM_EINVAL, "params must not be NULL");
   auto bad = [](const char *m) { return set_error(COSM_EINVAL, m); };
@@ -88,6 +94,8 @@ int check_params(const cosm_params *p) {
     return bad("bad workgroup shape");
   return COSM_OK;
 }
+
+}  // namespace
 
 // Schedule constants shared by every sweep form; the grid reading of the step
 // ramp and of the twist (see the header of kernels.hip).
@@ -115,6 +123,14 @@ int make_schedule(const cosm_params &p, int32_t max_abs_J, Schedule *sc) {
   sc->window2 = 2.0f * sc->window;
   return COSM_OK;
 }
+
+namespace {
+
+}  // namespace
+
+int check_params_public(const cosm_params *p) { return check_params(p); }
+
+namespace {
 
 int device_cu_count() {
   int dev = 0, v = 0;
@@ -147,14 +163,14 @@ int choose_shape(cosm_state *s) {
       const int W = p.replicas_per_wg / pw;
       if (W != 1 && W != 2 && W != 4)
         return set_error(COSM_EINVAL, "replicas_per_wg must be 1, 2 or 4 words per row");
-      if (slots_ok && lds_sweep_bytes(s->n_slots, W) <= cap) chosen = W;
+      if (slots_ok && lds_sweep_bytes(s->n_slots, W, s->C) <= cap) chosen = W;
       else if (sh.residency == COSM_RES_LDS)
         return set_error(COSM_ERANGE, "requested replicas per workgroup do not fit in LDS");
     } else if (slots_ok) {
       const int cus = device_cu_count();
       int best_full = 0, smallest_fit = 0;
       for (int W : {4, 2, 1}) {
-        if (lds_sweep_bytes(s->n_slots, W) > cap) continue;
+        if (lds_sweep_bytes(s->n_slots, W, s->C) > cap) continue;
         s->lds_widths.push_back(W);
         const int64_t blocks = (s->R + W * pw - 1) / (W * pw);
         if (blocks >= cus && best_full == 0) best_full = W;
@@ -170,7 +186,7 @@ int choose_shape(cosm_state *s) {
       sh.residency = COSM_RES_LDS;
       sh.rw = chosen * pw;
       sh.blocks = (s->R + sh.rw - 1) / sh.rw;
-      sh.lds_bytes = (int32_t)lds_sweep_bytes(s->n_slots, chosen);
+      sh.lds_bytes = (int32_t)lds_sweep_bytes(s->n_slots, chosen, s->C);
       if (int rc = build_lds_schedule(*s, chosen, p.threads_per_wg, &s->lds)) return rc;
       sh.threads = s->lds.nth;
     }

@@ -56,7 +56,7 @@ int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw) {
   s->shape.residency = COSM_RES_LDS;
   s->shape.rw = W * pw;
   s->shape.blocks = (s->R + s->shape.rw - 1) / s->shape.rw;
-  s->shape.lds_bytes = (int32_t)lds_sweep_bytes(s->n_slots, W);
+  s->shape.lds_bytes = (int32_t)lds_sweep_bytes(s->n_slots, W, s->C);
   s->shape.threads = s->lds.nth;
   return upload_schedule(s);
 }

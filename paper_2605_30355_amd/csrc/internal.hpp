@@ -63,6 +63,11 @@ struct Schedule {
   float window;          // window width in turns
 };
 
+// EINVAL unless every field of *p is in range.
+int check_params_public(const cosm_params *p);
+// Validates the schedule parameters against the couplings and fills *sc.
+int make_schedule(const cosm_params &p, int32_t max_abs_J, Schedule *sc);
+
 // ---- the device-side problem description -----------------------------------------
 // Per-class edge descriptors for the LDS kernel: 32-bit word of LDS slots
 // (slot_u | slot_v << 16) and the coupling as a float.
@@ -164,9 +169,11 @@ int lds_capacity_bytes();
 int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out);
 // Measure candidate LDS shapes (row widths in words) and keep the fastest.
 int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths);
-// LDS bytes of the sweep kernel: the rows, then two buffers of reference
-// angles for up to 8 replicas.
-inline size_t lds_sweep_bytes(int32_t n_rows, int W) { return (size_t)n_rows * W * 4 + 2 * 8 * 4; }
+// LDS bytes of the sweep kernel: the rows, two buffers of reference angles for
+// up to 8 replicas, and the slot count of each of the C classes.
+inline size_t lds_sweep_bytes(int32_t n_rows, int W, int32_t C) {
+  return (size_t)n_rows * W * 4 + 2 * 8 * 4 + (size_t)C * 4;
+}
 
 size_t readout_lds_bytes(int32_t n, int32_t B);
 }  // namespace cosm

@@ -12,176 +12,11 @@
 // (fract(d) < 1/2 is exactly "the difference wrapped to [-1/2, 1/2) is >= 0".)
 #include <hip/hip_runtime.h>
 
+#include "device_common.hpp"
 #include "internal.hpp"
 
 namespace cosm {
 namespace {
-
-constexpr uint32_t kTagInit = 0x494E4954u;  // "INIT"
-constexpr uint32_t kTagDwt = 0x44575420u;   // "DWT "
-constexpr float kQ23 = 1.0f / 8388608.0f;   // 2^-23
-constexpr float kQ22 = 1.0f / 4194304.0f;   // 2^-22
-constexpr float kQ24 = 1.0f / 16777216.0f;  // 2^-24
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products,
-// Weyl key schedule; only output word 0 is used here.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t philox_first_word(uint32_t c0, uint32_t c1, uint32_t c2,
-                                                      uint32_t c3, uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int i = 0; i < 10; i++) {
-    const uint32_t ka = k0 + (uint32_t)i * 0x9E3779B9u;
-    const uint32_t kb = k1 + (uint32_t)i * 0xBB67AE85u;
-    const uint32_t p0lo = 0xD2511F53u * c0, p0hi = __umulhi(0xD2511F53u, c0);
-    const uint32_t p1lo = 0xCD9E8D57u * c2, p1hi = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = p1hi ^ c1 ^ ka;
-    const uint32_t n2 = p0hi ^ c3 ^ kb;
-    c0 = n0;
-    c1 = p1lo;
-    c2 = n2;
-    c3 = p0lo;
-  }
-  return c0;
-}
-
-__device__ __forceinline__ float fract1(float v) { return __builtin_amdgcn_fractf(v); }
-
-// ---------------------------------------------------------------------------
-// Storage formats.  "value" is x in [0,1) for FP32 and y = x - 1/2 otherwise.
-// ---------------------------------------------------------------------------
-template <int ST>
-struct Fmt;
-
-template <>
-struct Fmt<COSM_STORE_FP32> {
-  using elem_t = float;
-  static constexpr int kPerWord = 1;
-  __device__ __forceinline__ static float wrap(float v) { return fract1(v); }
-  __device__ __forceinline__ static float from_turn(float x) { return x; }
-  __device__ __forceinline__ static float to_turn(float v) { return v; }
-  __device__ __forceinline__ static float load_elem(const void *p, size_t i) {
-    return static_cast<const float *>(p)[i];
-  }
-  __device__ __forceinline__ static void store_elem(void *p, size_t i, float v) {
-    static_cast<float *>(p)[i] = v;
-  }
-  template <int W>
-  __device__ __forceinline__ static void unpack(const uint32_t (&w)[W], float (&v)[W]) {
-#pragma unroll
-    for (int k = 0; k < W; k++) v[k] = __uint_as_float(w[k]);
-  }
-  template <int W>
-  __device__ __forceinline__ static void pack(const float (&v)[W], uint32_t (&w)[W]) {
-#pragma unroll
-    for (int k = 0; k < W; k++) w[k] = __float_as_uint(v[k]);
-  }
-};
-
-template <int ST>
-struct Fmt16 {
-  static constexpr int kPerWord = 2;
-  __device__ __forceinline__ static float wrap(float v) { return v - __builtin_rintf(v); }
-  __device__ __forceinline__ static float from_turn(float x) { return x - 0.5f; }
-  __device__ __forceinline__ static float to_turn(float v) { return fract1(v + 0.5f); }
-  __device__ __forceinline__ static float dec(uint32_t bits16) {
-    if constexpr (ST == COSM_STORE_FP16) {
-      return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
-    } else {
-      return __uint_as_float(bits16 << 16);
-    }
-  }
-  __device__ __forceinline__ static uint32_t enc(float v) {
-    if constexpr (ST == COSM_STORE_FP16) {
-      return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);
-    } else {
-      return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v);
-    }
-  }
-  __device__ __forceinline__ static float load_elem(const void *p, size_t i) {
-    return dec(static_cast<const uint16_t *>(p)[i]);
-  }
-  __device__ __forceinline__ static void store_elem(void *p, size_t i, float v) {
-    static_cast<uint16_t *>(p)[i] = (uint16_t)enc(v);
-  }
-  template <int W>
-  __device__ __forceinline__ static void unpack(const uint32_t (&w)[W], float (&v)[2 * W]) {
-#pragma unroll
-    for (int k = 0; k < W; k++) {
-      if constexpr (ST == COSM_STORE_FP16) {
-        v[2 * k] = dec(w[k] & 0xffffu);
-        v[2 * k + 1] = dec(w[k] >> 16);
-      } else {
-        v[2 * k] = __uint_as_float(w[k] << 16);
-        v[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
-      }
-    }
-  }
-  template <int W>
-  __device__ __forceinline__ static void pack(const float (&v)[2 * W], uint32_t (&w)[W]) {
-#pragma unroll
-    for (int k = 0; k < W; k++) w[k] = enc(v[2 * k]) | (enc(v[2 * k + 1]) << 16);
-  }
-};
-template <>
-struct Fmt<COSM_STORE_FP16> : Fmt16<COSM_STORE_FP16> {};
-template <>
-struct Fmt<COSM_STORE_BF16> : Fmt16<COSM_STORE_BF16> {};
-
-// LDS row access with the widest ds_read / ds_write for W words.
-template <int W>
-__device__ __forceinline__ void lds_load(const uint32_t *base, int slot, uint32_t (&w)[W]) {
-  if constexpr (W == 4) {
-    const uint4 q = reinterpret_cast<const uint4 *>(base)[slot];
-    w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
-  } else if constexpr (W == 2) {
-    const uint2 q = reinterpret_cast<const uint2 *>(base)[slot];
-    w[0] = q.x; w[1] = q.y;
-  } else {
-    w[0] = base[slot];
-  }
-}
-template <int W>
-__device__ __forceinline__ void lds_store(uint32_t *base, int slot, const uint32_t (&w)[W]) {
-  if constexpr (W == 4) {
-    reinterpret_cast<uint4 *>(base)[slot] = make_uint4(w[0], w[1], w[2], w[3]);
-  } else if constexpr (W == 2) {
-    reinterpret_cast<uint2 *>(base)[slot] = make_uint2(w[0], w[1]);
-  } else {
-    base[slot] = w[0];
-  }
-}
-
-// Eq. (6) for one (edge, replica): values in the storage's convention.
-template <int ST>
-__device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ) {
-  const float f = fract1(xu - xv);
-  const float dl = (f < 0.5f) ? aJ : -aJ;
-  xu = Fmt<ST>::wrap(xu - dl);
-  xv = Fmt<ST>::wrap(xv + dl);
-}
-
-// Dual window twist membership: mod_{1/2}(x - theta + w/2) < w, evaluated as
-// fract(2x - c) < 2w with c = 2 theta - w (valid for x and for y = x - 1/2).
-__device__ __forceinline__ bool in_windows(float v, float c, float win2) {
-  return fract1(__builtin_fmaf(2.0f, v, -c)) < win2;
-}
-
-__device__ __forceinline__ float theta_turns(uint32_t t, uint32_t rid, uint32_t k0, uint32_t k1) {
-  return (float)(philox_first_word(0u, t, rid, kTagDwt, k0, k1) >> 9) * kQ23;
-}
-
-// Per-sweep schedule evaluated on the device.  Grid: alpha = q * 2^-22 with
-// q = floor(num / S), num = a0 (S - t + 1) + S/2, stepped by subtraction.
-struct SweepSchedule {
-  int32_t grid;
-  int64_t S, q, r, aq, ar;
-  float alpha_cont_per;  // alpha0 / S in turns (continuous)
-  int32_t twist2;        // 2 * ratio (grid)
-  float ratio;           // continuous
-  int32_t period, phase; // twist when ++phase == period
-  float win, win2;
-};
 
 struct LdsArgs {
   void *phases;
@@ -217,50 +52,6 @@ __global__ void __launch_bounds__(256) k_init(void *phases, int32_t n, int32_t R
 // distinct LDS bank groups).  EMAX > 0: the schedule (at most EMAX slots) is
 // loaded into registers once; EMAX == 0: it streams from memory, one slot ahead.
 // ---------------------------------------------------------------------------
-template <int W>
-__device__ __forceinline__ void lds_load_at(const uint32_t *base, uint32_t byte, uint32_t (&w)[W]) {
-  const char *p = reinterpret_cast<const char *>(base) + byte;
-  if constexpr (W == 4) {
-    const uint4 q = *reinterpret_cast<const uint4 *>(p);
-    w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
-  } else if constexpr (W == 2) {
-    const uint2 q = *reinterpret_cast<const uint2 *>(p);
-    w[0] = q.x; w[1] = q.y;
-  } else {
-    w[0] = *reinterpret_cast<const uint32_t *>(p);
-  }
-}
-template <int W>
-__device__ __forceinline__ void lds_store_at(uint32_t *base, uint32_t byte, const uint32_t (&w)[W]) {
-  char *p = reinterpret_cast<char *>(base) + byte;
-  if constexpr (W == 4) {
-    *reinterpret_cast<uint4 *>(p) = make_uint4(w[0], w[1], w[2], w[3]);
-  } else if constexpr (W == 2) {
-    *reinterpret_cast<uint2 *>(p) = make_uint2(w[0], w[1]);
-  } else {
-    *reinterpret_cast<uint32_t *>(p) = w[0];
-  }
-}
-
-// Eq. (6) on every replica of one edge: rows at byte offsets bu, bv.
-template <int ST, int W>
-__device__ __forceinline__ void edge_rows(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ) {
-  using F = Fmt<ST>;
-  constexpr int RW = W * F::kPerWord;
-  uint32_t wu[W], wv[W];
-  lds_load_at<W>(lds, bu, wu);
-  lds_load_at<W>(lds, bv, wv);
-  float xu[RW], xv[RW];
-  F::template unpack<W>(wu, xu);
-  F::template unpack<W>(wv, xv);
-#pragma unroll
-  for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
-  F::template pack<W>(xu, wu);
-  F::template pack<W>(xv, wv);
-  lds_store_at<W>(lds, bu, wu);
-  lds_store_at<W>(lds, bv, wv);
-}
-
 template <int ST, int W, int EMAX>
 __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   extern __shared__ uint32_t lds[];
@@ -282,8 +73,11 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     lds_store<W>(lds, s, w);
   }
 
-  // reference angles of the first twist of this call
-  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)a.n_rows * W);  // [2][RW]
+  // reference angles of the first twist of this call, then the slots per class
+  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)a.n_rows * W);  // [2][8]
+  int32_t *Ks = reinterpret_cast<int32_t *>(theta_buf + 16);                  // [C]
+  if constexpr (EMAX == 0)
+    for (int c = tid; c < a.C; c += nth) Ks[c] = a.Kc[c];
   int tbuf = 0;
   if (a.sch.period > 0 && tid < RW) {
     const int64_t first = a.t0 + (a.sch.period - a.sch.phase);  // next t with t % period == 0
@@ -303,6 +97,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       va[j] = (d.slots >> 16) * ROWB;
       jr[j] = d.J;
     }
+  }
+  // streamed schedule: the first two slots in flight
+  EdgeDesc dA{kEmptySlot, 0.0f}, dB{kEmptySlot, 0.0f};
+  int jslot = 0;
+  if (EMAX == 0 && a.total_slots > 0) {
+    dA = a.desc[tid];
+    dB = a.desc[(size_t)(1 % a.total_slots) * nth + tid];
   }
   __syncthreads();
 
@@ -331,22 +132,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
           if ((a.bar_mask >> j) & 1u) __syncthreads();
         }
       }
-    } else {
-      int j = 0;
-      EdgeDesc cur{kEmptySlot, 0.0f};
-      if (a.total_slots > 0) cur = a.desc[tid];
-      for (int c = 0; c < a.C; c++) {
-        const int kc = a.Kc[c];
-        for (int k = 0; k < kc; k++, j++) {
-          const int jn = (j + 1 < a.total_slots) ? j + 1 : 0;
-          const EdgeDesc nxt = a.desc[(size_t)jn * nth + tid];
-          if (cur.slots != kEmptySlot)
-            edge_rows<ST, W>(lds, (cur.slots & 0xffffu) * ROWB, (cur.slots >> 16) * ROWB,
-                             alpha * cur.J);
-          cur = nxt;
-        }
-        if (kc > 0) __syncthreads();
-      }
+    } else if (a.total_slots > 0) {
+      stream_classes(a.desc, Ks, a.C, a.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
+        edge_rows<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha * d.J);
+      });
     }
     // Dual window twist every `period` sweeps.  The reference angles of this
     // twist were drawn during the previous one (or at the start) by the first
@@ -486,154 +275,11 @@ __global__ void __launch_bounds__(256) k_full_gradient(const void *src, void *ds
   F::store_elem(dst, (size_t)idx, F::wrap(xi + acc));
 }
 
-// ---------------------------------------------------------------------------
-// Block reductions (wave64 shuffles, then one LDS slot per wave).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t wave_sum(int64_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ int64_t block_sum(int64_t v, int64_t *scratch /* >= 16 */) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) scratch[wv] = v;
-  __syncthreads();
-  int64_t total = 0;
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int k = 0; k < nw; k++) total += scratch[k];
-  __syncthreads();
-  return total;
-}
-
-// ---------------------------------------------------------------------------
-// Readout, Algorithm 1 binarization: one workgroup per replica.  Bisector p is
-// beta_p (increasing, beta_0 = 0); spin i is +1 on [beta_p, beta_p + 1/2).
-// With x in [0,1): s_i(0) = +1 iff x < 1/2, and spin i flips exactly once, at
-// q_i = #{p : beta_p <= y_i}, y_i = x_i mod 1/2.  An edge's term -J s_u s_v thus
-// changes sign at min(q_u, q_v) and back at max(q_u, q_v): a difference array
-// over p gives every H_p in O(n + m + B).
-// ---------------------------------------------------------------------------
-struct ReadoutArgs {
-  const void *phases;
-  const int32_t *eu, *ev, *J, *h;
-  int8_t *spins;
-  int64_t *H, *cut;
-  int32_t *best_p;
-  int32_t n, R, B, grid;
-  int64_t m;
-};
 
 template <int ST>
 __global__ void __launch_bounds__(256) k_readout(const ReadoutArgs a) {
-  using F = Fmt<ST>;
   extern __shared__ int64_t sm64[];
-  int64_t *red = sm64;            // 16
-  int64_t *bins = sm64 + 16;      // B + 1
-  float *beta = reinterpret_cast<float *>(bins + a.B + 1);  // B
-  uint16_t *code = reinterpret_cast<uint16_t *>(beta + a.B); // n
-  const int r = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
-  const int B = a.B;
-  __shared__ int32_t s_bp;
-  __shared__ int64_t s_best;
-
-  if (a.h != nullptr) {
-    // bias fields: fixed semicircles, +1 on the half centred at 0
-    int64_t e = 0;
-    for (int i = tid; i < a.n; i += nth) {
-      const float x = F::to_turn(F::load_elem(a.phases, (size_t)i * a.R + r));
-      const int s = fract1(x + 0.25f) < 0.5f ? 1 : -1;
-      a.spins[(size_t)r * a.n + i] = (int8_t)s;
-      e -= (int64_t)a.h[i] * s;
-    }
-    __syncthreads();
-    int64_t c = 0;
-    for (int64_t k = tid; k < a.m; k += nth) {
-      const int su = a.spins[(size_t)r * a.n + a.eu[k]], sv = a.spins[(size_t)r * a.n + a.ev[k]];
-      e -= (int64_t)a.J[k] * su * sv;
-      if (su != sv) c -= a.J[k];
-    }
-    e = block_sum(e, red);
-    c = block_sum(c, red);
-    if (tid == 0) {
-      a.H[r] = e;
-      a.cut[r] = c;
-      a.best_p[r] = 0;
-    }
-    return;
-  }
-
-  for (int p = tid; p <= B; p += nth) bins[p] = 0;
-  for (int p = tid; p < B; p += nth) {
-    if (a.grid) {
-      const int64_t units = (((int64_t)p << 23) + B) / (2 * (int64_t)B);
-      beta[p] = (float)units * kQ23;
-    } else {
-      beta[p] = (float)p / (float)(2 * B);
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i < a.n; i += nth) {
-    const float x = F::to_turn(F::load_elem(a.phases, (size_t)i * a.R + r));
-    const bool neg = !(x < 0.5f);
-    const float y = neg ? x - 0.5f : x;
-    int lo = 0, hi = B;  // count of beta <= y
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (beta[mid] <= y) lo = mid + 1; else hi = mid;
-    }
-    code[i] = (uint16_t)(lo | (neg ? 0x8000 : 0));
-  }
-  __syncthreads();
-  int64_t h0 = 0;
-  for (int64_t k = tid; k < a.m; k += nth) {
-    const uint32_t cu = code[a.eu[k]], cv = code[a.ev[k]];
-    const int su = (cu & 0x8000) ? -1 : 1, sv = (cv & 0x8000) ? -1 : 1;
-    const int64_t e0 = -(int64_t)a.J[k] * su * sv;
-    h0 += e0;
-    const int qu = cu & 0x7fff, qv = cv & 0x7fff;
-    const int lo = min(qu, qv), hi = max(qu, qv);
-    if (lo != hi) {
-      if (lo < B) atomicAdd((unsigned long long *)&bins[lo], (unsigned long long)(-2 * e0));
-      if (hi < B) atomicAdd((unsigned long long *)&bins[hi], (unsigned long long)(2 * e0));
-    }
-  }
-  h0 = block_sum(h0, red);
-  if (tid == 0) {
-    int64_t run = h0, best = h0;
-    int bp = 0;
-    for (int p = 1; p < B; p++) {
-      run += bins[p];
-      if (run < best) {
-        best = run;
-        bp = p;
-      }
-    }
-    s_bp = bp;
-    s_best = best;
-  }
-  __syncthreads();
-  const int bp = s_bp;
-  for (int i = tid; i < a.n; i += nth) {
-    const uint32_t ci = code[i];
-    const int s0 = (ci & 0x8000) ? -1 : 1;
-    a.spins[(size_t)r * a.n + i] = (int8_t)((bp < (int)(ci & 0x7fff)) ? s0 : -s0);
-  }
-  int64_t c = 0;
-  for (int64_t k = tid; k < a.m; k += nth) {
-    const uint32_t cu = code[a.eu[k]], cv = code[a.ev[k]];
-    const int su = ((cu & 0x8000) ? -1 : 1) * ((bp < (int)(cu & 0x7fff)) ? 1 : -1);
-    const int sv = ((cv & 0x8000) ? -1 : 1) * ((bp < (int)(cv & 0x7fff)) ? 1 : -1);
-    if (su != sv) c -= a.J[k];
-  }
-  c = block_sum(c, red);
-  if (tid == 0) {
-    a.H[r] = s_best;
-    a.cut[r] = c;
-    a.best_p[r] = bp;
-  }
+  readout_block<ST>(a, blockIdx.x, sm64);
 }
 
 // Energy (Eq. (1)) and cut (Eq. (14), w = -J) of caller-supplied spins [R][n].

@@ -1,0 +1,90 @@
+"""The multi-instance persistent launch (cosm_batch_*) against single-instance
+states and the oracle: instances of uneven sizes, families and parameters run
+in one launch must give exactly the trajectories, energies and spins they give
+alone (grid schedule), including on replays of the captured hipGraph with new
+seeds and subsets of the instances."""
+import sys
+
+import numpy as np
+import pytest
+
+import cosm_inputs as ci
+import oracle
+import paper_2605_30355_amd as cosm
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def graphs():
+    out = []
+    t = ci.torus(20, seed=1)
+    c, C = cosm.build_partitions(t.n, t.eu, t.ev, cosm.COLOR_TORUS, [20, 20])
+    out.append((t, c, C, cosm.Params(sweeps_per_trial=300, dwt_ratio=0.5, dwt_period=3), 11, 64))
+    g = ci.random_regular(2000, 3, seed=2)
+    c, C = cosm.build_partitions(g.n, g.eu, g.ev, cosm.COLOR_BALANCED)
+    out.append((g, c, C, cosm.Params(sweeps_per_trial=200, dwt_ratio=1.0, dwt_period=6), 12, 100))
+    g = ci.random_regular(600, 5, seed=3, weights="pm1")
+    c, C = cosm.build_partitions(g.n, g.eu, g.ev, cosm.COLOR_GREEDY)
+    out.append((g, c, C, cosm.Params(sweeps_per_trial=150, dwt_ratio=1.5, dwt_period=3), 13, 37))
+    g = ci.small_random(30, 90, seed=4, weights="pm12")
+    c, C = cosm.build_partitions(g.n, g.eu, g.ev, cosm.COLOR_MISRA_GRIES)
+    out.append((g, c, C, cosm.Params(sweeps_per_trial=500, dwt_ratio=0.5, dwt_period=2), 14, 5))
+    t = ci.torus(141, seed=4)
+    c, C = cosm.build_partitions(t.n, t.eu, t.ev, cosm.COLOR_TORUS, [141, 141])
+    out.append((t, c, C, cosm.Params(sweeps_per_trial=20, dwt_ratio=0.5, dwt_period=3), 15, 3))
+    return out
+
+
+def single(inst, c, C, p, seed, R, rid0=0):
+    with cosm.State(inst.n, inst.eu, inst.ev, inst.J, c, C, p, seed=seed, replicas=R) as st:
+        st.reset(seed, rid0)
+        st.sweep(p.sweeps_per_trial)
+        return st.energy()
+
+
+@pytest.mark.parametrize("storage", [cosm.STORE_FP32, cosm.STORE_BF16])
+def test_batch_equals_single_states(storage):
+    gs = graphs()
+    with cosm.Batch(storage=storage, max_graphs=16, max_n=20000) as b:
+        ids = []
+        for inst, c, C, p, seed, R in gs:
+            p.storage = storage
+            ids.append(b.add(inst.n, inst.eu, inst.ev, inst.J, c, C, p, seed=seed, replicas=R))
+        say(f"[gpu] batch run of {len(ids)} graphs, storage {storage}")
+        b.run(ids)
+        ms = b.wait()
+        say(f"[gpu] batch took {ms:.2f} ms")
+        for gid, (inst, c, C, p, seed, R) in zip(ids, gs):
+            H, cut, sp = b.results(gid, return_spins=True)
+            Hs, cs, ss = single(inst, c, C, p, seed, R)
+            assert np.array_equal(H, Hs) and np.array_equal(cut, cs), inst.name
+            assert np.array_equal(sp, ss), inst.name
+        # replay the captured graph on a subset with new seeds and replica offsets
+        sub = [ids[1], ids[3]]
+        b.set_seed(ids[1], 99, 1000)
+        b.set_seed(ids[3], 98, 7)
+        b.run(sub)
+        b.wait()
+        for gid, rid0, seed in ((ids[1], 1000, 99), (ids[3], 7, 98)):
+            inst, c, C, p, _, R = gs[gid]
+            H, cut, _ = b.results(gid)
+            Hs, cs, _ = single(inst, c, C, p, seed, R, rid0)
+            assert np.array_equal(H, Hs) and np.array_equal(cut, cs), inst.name
+
+
+def test_batch_matches_oracle_sample():
+    inst, c, C, p, seed, R = graphs()[0]
+    with cosm.Batch(max_graphs=4, max_n=400) as b:
+        gid = b.add(inst.n, inst.eu, inst.ev, inst.J, c, C, p, seed=seed, replicas=R)
+        b.run([gid])
+        b.wait()
+        H, cut, sp = b.results(gid, return_spins=True)
+    prob = oracle.Problem(inst.n, inst.eu, inst.ev, inst.J, colour=c, C=C)
+    op = oracle.Params(sweeps=p.sweeps_per_trial, dwt_ratio=p.dwt_ratio, dwt_period=p.dwt_period)
+    _, so, Ho, co = oracle.solve(prob, op, seed, 0, R)
+    assert np.array_equal(H, Ho) and np.array_equal(cut, co) and np.array_equal(sp, so)
