@@ -97,8 +97,11 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
   const int nsets = it.nsets;
   const uint32_t set_bytes = (uint32_t)g.n * ROWB;
   const int nreps = nsets * RW;
-  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)nsets * g.n * W);  // [2][nreps]
-  int32_t *Ks = reinterpret_cast<int32_t *>(theta_buf + 2 * nreps);            // [C]
+  // reference angles of nch twists for the nreps replicas, then slots per class
+  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)nsets * g.n * W);  // [nch][nreps]
+  int32_t *Ks = reinterpret_cast<int32_t *>(theta_buf + 2 * kMaxSetReplicas);  // [C]
+  const int nch = max(1, min(kThetaChunk, 2 * kMaxSetReplicas / nreps));
+  int tw = 0;
   for (int c = tid; c < g.C; c += nth) Ks[c] = as_global(g.Kc)[c];
 
   for (int s = tid; s < g.n * nsets; s += nth) {
@@ -122,27 +125,11 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
     dB = EdgeDesc{d1->slots, d1->J};
   }
   SweepSchedule sc = g.sch;
-  int tbuf = 0;
-  if (sc.period > 0 && tid < nreps)
-    theta_buf[tid] = 2.0f * theta_turns((uint32_t)sc.period, g.rid0 + (uint32_t)(it.r0 + tid),
-                                        g.k0, g.k1) - sc.win;
   __syncthreads();
 
   for (int64_t t = 1; t <= g.S; t++) {
     float alpha, twist;
-    if (sc.grid) {
-      alpha = (float)sc.q * kQ22;
-      twist = (float)(sc.twist2 * sc.q) * kQ23;
-      sc.q -= sc.aq;
-      sc.r -= sc.ar;
-      if (sc.r < 0) {
-        sc.r += sc.S;
-        sc.q -= 1;
-      }
-    } else {
-      alpha = (float)(sc.S - t + 1) * sc.alpha_cont_per;
-      twist = sc.ratio * alpha;
-    }
+    schedule_step(sc, t, alpha, twist);
     if (g.total_slots > 0)
       stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
         edge_rows_sets<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, set_bytes,
@@ -150,24 +137,34 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
       });
     if (sc.period > 0 && ++sc.phase == sc.period) {
       sc.phase = 0;
-      if (tid < nreps)
-        theta_buf[(tbuf ^ 1) * nreps + tid] =
-            2.0f * theta_turns((uint32_t)(t + sc.period), g.rid0 + (uint32_t)(it.r0 + tid), g.k0,
-                               g.k1) - sc.win;
-      for (int s = tid; s < g.n * nsets; s += nth) {
-        const int k = s / g.n;
-        uint32_t w[W];
-        lds_load<W>(lds, s, w);
-        float v[RW];
-        F::template unpack<W>(w, v);
-#pragma unroll
-        for (int q = 0; q < RW; q++)
-          if (in_windows(v[q], theta_buf[tbuf * nreps + k * RW + q], sc.win2))
-            v[q] = F::wrap(v[q] + twist);
-        F::template pack<W>(v, w);
-        lds_store<W>(lds, s, w);
+      const int slot = tw % nch;
+      if (slot == 0) {
+        theta_fill(theta_buf, nch, nreps, t, sc.period, g.rid0 + (uint32_t)it.r0, g.k0, g.k1,
+                   sc.win);
+        __syncthreads();
       }
-      tbuf ^= 1;
+      tw++;
+      const float *cth = theta_buf + slot * nreps;
+      for (int s0 = tid; s0 < g.n * nsets; s0 += 2 * nth) {
+        uint32_t w[2][W];
+#pragma unroll
+        for (int q = 0; q < 2; q++)
+          if (s0 + q * nth < g.n * nsets) lds_load<W>(lds, s0 + q * nth, w[q]);
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+          const int s = s0 + q * nth;
+          if (s < g.n * nsets) {
+            const int k = s / g.n;
+            float v[RW];
+            F::template unpack<W>(w[q], v);
+#pragma unroll
+            for (int r = 0; r < RW; r++)
+              if (in_windows(v[r], cth[k * RW + r], sc.win2)) v[r] = F::wrap(v[r] + twist);
+            F::template pack<W>(v, w[q]);
+            lds_store<W>(lds, s, w[q]);
+          }
+        }
+      }
       __syncthreads();
     }
   }
@@ -471,9 +468,9 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
   const int64_t num = sc.a0_units * sc.S + sc.S / 2;
   d.sch.grid = sc.grid;
   d.sch.S = sc.S;
-  d.sch.q = num / sc.S;
+  d.sch.q = (int32_t)(num / sc.S);
   d.sch.r = num % sc.S;
-  d.sch.aq = sc.a0_units / sc.S;
+  d.sch.aq = (int32_t)(sc.a0_units / sc.S);
   d.sch.ar = sc.a0_units % sc.S;
   d.sch.alpha_cont_per = sc.alpha0_turns / (float)sc.S;
   d.sch.twist2 = sc.twist_num2;

@@ -186,16 +186,50 @@ __device__ __forceinline__ float theta_turns(uint32_t t, uint32_t rid, uint32_t 
 }
 
 // Per-sweep schedule evaluated on the device.  Grid: alpha = q * 2^-22 with
-// q = floor(num / S), num = a0 (S - t + 1) + S/2, stepped by subtraction.
+// q = floor(num / S), num = a0 (S - t + 1) + S/2, stepped by subtraction
+// (q < 2^22 and 2 rho q < 2^23, so the int32 products and conversions are exact).
 struct SweepSchedule {
   int32_t grid;
-  int64_t S, q, r, aq, ar;
+  int64_t S, r, ar;
+  int32_t q, aq;
   float alpha_cont_per;  // alpha0 / S in turns (continuous)
   int32_t twist2;        // 2 * ratio (grid)
   float ratio;           // continuous
   int32_t period, phase; // twist when ++phase == period
   float win, win2;
 };
+
+// alpha_t and the twist angle rho * alpha_t of sweep t (Algorithm 1's ramp);
+// advances the grid numerator to sweep t + 1.  S - t + 1 <= 2^31 fits uint32.
+__device__ __forceinline__ void schedule_step(SweepSchedule &sc, int64_t t, float &alpha,
+                                              float &twist) {
+  if (sc.grid) {
+    alpha = (float)sc.q * kQ22;
+    twist = (float)(sc.twist2 * sc.q) * kQ23;
+    sc.q -= sc.aq;
+    sc.r -= sc.ar;
+    if (sc.r < 0) {
+      sc.r += sc.S;
+      sc.q -= 1;
+    }
+  } else {
+    alpha = (float)(uint32_t)(sc.S - t + 1) * sc.alpha_cont_per;
+    twist = sc.ratio * alpha;
+  }
+}
+
+// Fills table[q * nrep + k] with c = 2 theta - w for the twist at sweep
+// t_first + q * period (q < nch) and replica rid_base + k (k < nrep).  Every
+// thread of the workgroup takes part; the caller synchronises.
+__device__ __forceinline__ void theta_fill(float *table, int nch, int nrep, int64_t t_first,
+                                           int32_t period, uint32_t rid_base, uint32_t k0,
+                                           uint32_t k1, float win) {
+  for (int i = threadIdx.x; i < nch * nrep; i += blockDim.x) {
+    const int q = i / nrep, k = i - q * nrep;
+    table[i] = 2.0f * theta_turns((uint32_t)(t_first + (int64_t)q * period), rid_base + (uint32_t)k,
+                                  k0, k1) - win;
+  }
+}
 
 template <int W>
 __device__ __forceinline__ void lds_load_at(const uint32_t *base, uint32_t byte, uint32_t (&w)[W]) {

@@ -169,10 +169,15 @@ int lds_capacity_bytes();
 int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out);
 // Measure candidate LDS shapes (row widths in words) and keep the fastest.
 int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths);
-// LDS bytes of the sweep kernel: the rows, two buffers of reference angles for
-// up to 8 replicas, and the slot count of each of the C classes.
+// Reference angles of the dual window twist are drawn kThetaChunk twists at a
+// time into an LDS table of kThetaChunk x (at most 8) floats.
+constexpr int kThetaChunk = 32;
+constexpr int kThetaFloats = kThetaChunk * 8;
+
+// LDS bytes of the sweep kernel: the rows, the table of reference angles and
+// the slot count of each of the C classes.
 inline size_t lds_sweep_bytes(int32_t n_rows, int W, int32_t C) {
-  return (size_t)n_rows * W * 4 + 2 * 8 * 4 + (size_t)C * 4;
+  return (size_t)n_rows * W * 4 + (size_t)kThetaFloats * 4 + (size_t)C * 4;
 }
 
 size_t readout_lds_bytes(int32_t n, int32_t B);

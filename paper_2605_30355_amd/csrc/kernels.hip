@@ -73,17 +73,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     lds_store<W>(lds, s, w);
   }
 
-  // reference angles of the first twist of this call, then the slots per class
-  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)a.n_rows * W);  // [2][8]
-  int32_t *Ks = reinterpret_cast<int32_t *>(theta_buf + 16);                  // [C]
+  // table of reference angles (filled at the first twist of every chunk), then
+  // the slots per class
+  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)a.n_rows * W);  // [kThetaChunk][RW]
+  int32_t *Ks = reinterpret_cast<int32_t *>(theta_buf + kThetaFloats);         // [C]
   if constexpr (EMAX == 0)
     for (int c = tid; c < a.C; c += nth) Ks[c] = a.Kc[c];
-  int tbuf = 0;
-  if (a.sch.period > 0 && tid < RW) {
-    const int64_t first = a.t0 + (a.sch.period - a.sch.phase);  // next t with t % period == 0
-    theta_buf[tid] = 2.0f * theta_turns((uint32_t)first, a.rid0 + (uint32_t)(r0 + tid), a.k0,
-                                        a.k1) - a.sch.win;
-  }
+  int tw = 0;  // twists done in this call
 
   // register-resident lane schedule
   uint32_t ua[EMAX > 0 ? EMAX : 1], va[EMAX > 0 ? EMAX : 1];
@@ -110,19 +106,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   SweepSchedule sc = a.sch;
   for (int64_t t = a.t0 + 1; t <= a.t0 + a.nsw; t++) {
     float alpha, twist;
-    if (sc.grid) {
-      alpha = (float)sc.q * kQ22;
-      twist = (float)(sc.twist2 * sc.q) * kQ23;
-      sc.q -= sc.aq;
-      sc.r -= sc.ar;
-      if (sc.r < 0) {
-        sc.r += sc.S;
-        sc.q -= 1;
-      }
-    } else {
-      alpha = (float)(sc.S - t + 1) * sc.alpha_cont_per;
-      twist = sc.ratio * alpha;
-    }
+    schedule_step(sc, t, alpha, twist);
     // Sequential conflict-free search: classes in order, a barrier after each.
     if constexpr (EMAX > 0) {
 #pragma unroll
@@ -137,30 +121,38 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         edge_rows<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha * d.J);
       });
     }
-    // Dual window twist every `period` sweeps.  The reference angles of this
-    // twist were drawn during the previous one (or at the start) by the first
-    // RW lanes of the workgroup; those lanes now draw the next twist's angles
-    // into the other buffer, read only after the barrier that ends this twist.
+    // Dual window twist every `period` sweeps, on the phases after the last
+    // class (a barrier ended it).  Reference angles come from the LDS table,
+    // refilled by the whole workgroup every kThetaChunk twists.
     if (sc.period > 0 && ++sc.phase == sc.period) {
       sc.phase = 0;
+      const int slot = tw % kThetaChunk;
+      if (slot == 0) {
+        theta_fill(theta_buf, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0, a.k0, a.k1, sc.win);
+        __syncthreads();
+      }
+      tw++;
       float cth[RW];
 #pragma unroll
-      for (int k = 0; k < RW; k++) cth[k] = theta_buf[tbuf * RW + k];
-      if (tid < RW)
-        theta_buf[(tbuf ^ 1) * RW + tid] =
-            2.0f * theta_turns((uint32_t)(t + sc.period), a.rid0 + (uint32_t)(r0 + tid), a.k0,
-                               a.k1) - sc.win;
-      tbuf ^= 1;
-      for (int s = tid; s < a.n_rows; s += nth) {
-        uint32_t w[W];
-        lds_load<W>(lds, s, w);
-        float v[RW];
-        F::template unpack<W>(w, v);
+      for (int k = 0; k < RW; k++) cth[k] = theta_buf[slot * RW + k];
+      // four rows per thread in flight: all loads, then the updates and stores
+      for (int s0 = tid; s0 < a.n_rows; s0 += 4 * nth) {
+        uint32_t w[4][W];
 #pragma unroll
-        for (int k = 0; k < RW; k++)
-          if (in_windows(v[k], cth[k], sc.win2)) v[k] = F::wrap(v[k] + twist);
-        F::template pack<W>(v, w);
-        lds_store<W>(lds, s, w);
+        for (int q = 0; q < 4; q++)
+          if (s0 + q * nth < a.n_rows) lds_load<W>(lds, s0 + q * nth, w[q]);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          if (s0 + q * nth < a.n_rows) {
+            float v[RW];
+            F::template unpack<W>(w[q], v);
+#pragma unroll
+            for (int k = 0; k < RW; k++)
+              if (in_windows(v[k], cth[k], sc.win2)) v[k] = F::wrap(v[k] + twist);
+            F::template pack<W>(v, w[q]);
+            lds_store<W>(lds, s0 + q * nth, w[q]);
+          }
+        }
       }
       __syncthreads();
     }
@@ -391,9 +383,9 @@ int sweeps_lds_st(cosm_state *s, int64_t n_sweeps) {
   w.grid = sc.grid;
   w.S = sc.S;
   const int64_t num = sc.a0_units * (sc.S - s->t) + sc.S / 2;  // numerator at t0 + 1
-  w.q = num / sc.S;
+  w.q = (int32_t)(num / sc.S);
   w.r = num % sc.S;
-  w.aq = sc.a0_units / sc.S;
+  w.aq = (int32_t)(sc.a0_units / sc.S);
   w.ar = sc.a0_units % sc.S;
   w.alpha_cont_per = sc.alpha0_turns / (float)sc.S;
   w.twist2 = sc.twist_num2;

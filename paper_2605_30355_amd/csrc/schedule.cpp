@@ -1,10 +1,15 @@
 // schedule.cpp -- LDS layout and lane schedule of the LDS-resident sweep.
 //
 // The sweep kernel keeps a replica block as LDS rows (one row per slot) and
-// lets consecutive lanes take consecutive entries of a class's edge list.  LDS
-// serves 128 bytes per clock: a row access of 4 W bytes by G = 32 / W
-// consecutive lanes is conflict-free when the G rows touched lie in distinct
-// residues (slot mod G).  Within a colour class the edges are a matching, so
+// lets consecutive lanes take consecutive entries of a class's edge list.  The
+// gfx950 LDS has 64 banks of 4 bytes.  Measured on the part: a wave's reads
+// are served in groups of 256 bytes of lanes (16 lanes of ds_read_b128, 32 of
+// _b64, 32 of _b32) and its writes in groups of 128 bytes (8 lanes of
+// ds_write_b128, 16 of _b64, 32 of _b32); an access runs at full speed when
+// the rows of every group lie in distinct banks.  With rows of 4 W bytes that
+// means distinct residues slot mod G within each aligned group of G = 64 / W
+// lanes (32 for W = 1), and distinct residues mod H = 32 / W within each
+// aligned half of H lanes.  Within a colour class the edges are a matching, so
 // their order is free; this file picks
 //   1. a vertex -> slot map that spreads every class's u-endpoints, and its
 //      v-endpoints, evenly over the G residues;
@@ -12,7 +17,11 @@
 //      u-residues are distinct and the v-residues are distinct: a proper edge
 //      colouring of the bipartite multigraph (u-residue, v-residue), which
 //      König's theorem gives with as many colours as its maximum degree;
-//      unused lanes of a group are masked off.
+//      unused lanes of a group are masked off;
+//   3. within each group, the split into two halves of H lanes: two entries
+//      whose u-residues (or v-residues) agree mod H must go to different
+//      halves.  Each entry has at most one such partner of each kind, so the
+//      constraints form paths and even cycles and a 2-colouring exists.
 // None of this changes the dynamics: each class is still applied in full, in
 // the class order given by the caller.
 #include <algorithm>
@@ -88,7 +97,7 @@ int32_t bipartite_edge_colouring(int32_t G, const std::vector<int32_t> &left,
 }  // namespace
 
 int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out) {
-  const int32_t n = s.n, C = s.C, G = 32 / W;
+  const int32_t n = s.n, C = s.C, G = W == 1 ? 32 : 64 / W, H = 32 / W;
   const int64_t m = s.m;
   LdsSchedule &L = *out;
   L.G = G;
@@ -131,6 +140,52 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
     cap[(size_t)best]--;
     for (int32_t cs : inc[(size_t)i]) cnt[(size_t)cs * G + best]++;
   }
+  // 1b. local search: exchange the residues of two vertices when that lowers
+  // sum(cnt^2) + 64 sum(max(0, cnt - T)^2), T = ceil(class-side total / G), the
+  // least maximum a class-side can have.  Stops once no count exceeds its T.
+  {
+    std::vector<int32_t> T((size_t)2 * C, 0);
+    for (int32_t cs = 0; cs < 2 * C; cs++) {
+      int64_t tot = 0;
+      for (int32_t g = 0; g < G; g++) tot += cnt[(size_t)cs * G + g];
+      T[(size_t)cs] = (int32_t)((tot + G - 1) / G);
+    }
+    auto cell = [&](int32_t cs, int32_t c) {
+      const int64_t e = std::max(0, c - T[(size_t)cs]);
+      return (int64_t)c * c + 64 * e * e;
+    };
+    int64_t excess = 0;
+    for (int32_t cs = 0; cs < 2 * C; cs++)
+      for (int32_t g = 0; g < G; g++) excess += std::max(0, cnt[(size_t)cs * G + g] - T[(size_t)cs]);
+    // move vertex i from residue a to b; returns the change of the objective
+    auto move = [&](int32_t i, int32_t a, int32_t b) {
+      int64_t d = 0;
+      for (int32_t cs : inc[(size_t)i]) {
+        int32_t &ca = cnt[(size_t)cs * G + a], &cb = cnt[(size_t)cs * G + b];
+        d += cell(cs, ca - 1) - cell(cs, ca) + cell(cs, cb + 1) - cell(cs, cb);
+        excess += std::max(0, ca - 1 - T[(size_t)cs]) - std::max(0, ca - T[(size_t)cs]);
+        excess += std::max(0, cb + 1 - T[(size_t)cs]) - std::max(0, cb - T[(size_t)cs]);
+        ca--;
+        cb++;
+      }
+      return d;
+    };
+    std::uniform_int_distribution<int32_t> pick(0, n - 1);
+    const int64_t tries = 60 * (int64_t)n;
+    for (int64_t it = 0; it < tries && excess > 0; it++) {
+      const int32_t x = pick(rng), y = pick(rng);
+      const int32_t gx = res[(size_t)x], gy = res[(size_t)y];
+      if (gx == gy) continue;
+      const int64_t d = move(x, gx, gy) + move(y, gy, gx);
+      if (d < 0) {
+        res[(size_t)x] = gy;
+        res[(size_t)y] = gx;
+      } else {
+        move(y, gx, gy);
+        move(x, gy, gx);
+      }
+    }
+  }
   // slots: residue g holds slots g, g + G, g + 2G, ... in vertex order
   L.slot_vertex.assign((size_t)L.n_rows, -1);
   std::vector<int32_t> slot((size_t)n), next_in_res((size_t)G, 0);
@@ -157,13 +212,53 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
     const int32_t D = bipartite_edge_colouring(G, lft, rgt, &col);
     auto &lst = lists[(size_t)c];
     lst.assign((size_t)D * G, EdgeDesc{kEmptySlot, 0.0f});  // unfilled lanes stay masked
-    std::vector<int32_t> fill((size_t)D, 0);
-    for (size_t a = 0; a < E.size(); a++) {
-      const int32_t g = col[a];
-      const int64_t k = E[a];
-      const uint32_t su = (uint32_t)slot[(size_t)s.h_eu[(size_t)k]];
-      const uint32_t sv = (uint32_t)slot[(size_t)s.h_ev[(size_t)k]];
-      lst[(size_t)g * G + fill[(size_t)g]++] = EdgeDesc{su | (sv << 16), (float)s.h_J[(size_t)k]};
+    std::vector<std::vector<int32_t>> group((size_t)D);
+    for (size_t a = 0; a < E.size(); a++) group[(size_t)col[a]].push_back((int32_t)a);
+    std::vector<int32_t> half(E.size(), -1), uo((size_t)H), vo((size_t)H), stack;
+    for (int32_t g = 0; g < D; g++) {
+      const auto &grp = group[(size_t)g];
+      int32_t fill[2] = {0, 0};
+      if (H < G) {
+        // partner of each entry through a shared u- or v-residue mod H
+        std::fill(uo.begin(), uo.end(), -1);
+        std::fill(vo.begin(), vo.end(), -1);
+        std::vector<int32_t> pu(grp.size(), -1), pv(grp.size(), -1);
+        for (size_t q = 0; q < grp.size(); q++) {
+          const int32_t ru = lft[(size_t)grp[q]] % H, rv = rgt[(size_t)grp[q]] % H;
+          if (uo[(size_t)ru] >= 0) {
+            pu[q] = uo[(size_t)ru];
+            pu[(size_t)uo[(size_t)ru]] = (int32_t)q;
+          }
+          uo[(size_t)ru] = (int32_t)q;
+          if (vo[(size_t)rv] >= 0) {
+            pv[q] = vo[(size_t)rv];
+            pv[(size_t)vo[(size_t)rv]] = (int32_t)q;
+          }
+          vo[(size_t)rv] = (int32_t)q;
+        }
+        for (size_t q0 = 0; q0 < grp.size(); q0++) {
+          if (half[(size_t)grp[q0]] >= 0) continue;
+          half[(size_t)grp[q0]] = 0;
+          stack.assign(1, (int32_t)q0);
+          while (!stack.empty()) {
+            const int32_t q = stack.back();
+            stack.pop_back();
+            for (int32_t r : {pu[(size_t)q], pv[(size_t)q]}) {
+              if (r < 0 || half[(size_t)grp[(size_t)r]] >= 0) continue;
+              half[(size_t)grp[(size_t)r]] = 1 - half[(size_t)grp[(size_t)q]];
+              stack.push_back(r);
+            }
+          }
+        }
+      }
+      for (int32_t a : grp) {
+        const int32_t hf = H < G ? half[(size_t)a] : 0;
+        const int64_t k = E[(size_t)a];
+        const uint32_t su = (uint32_t)slot[(size_t)s.h_eu[(size_t)k]];
+        const uint32_t sv = (uint32_t)slot[(size_t)s.h_ev[(size_t)k]];
+        lst[(size_t)g * G + (size_t)hf * H + fill[hf]++] =
+            EdgeDesc{su | (sv << 16), (float)s.h_J[(size_t)k]};
+      }
     }
     L.padded[(size_t)c] = (int32_t)lst.size();
   }

@@ -1,8 +1,12 @@
 // Host-only check of the LDS lane schedule built by schedule.cpp.
 // Input on stdin: "n m C" then m lines "u v J colour".  Prints a summary line;
 // exit status 0 only if the slot map is a permutation.  The caller checks
-// "conflicts=0" (distinct bank groups per aligned lane group, u-rows and
-// v-rows separately) and "equal=1" (every edge exactly once).
+// "conflicts=0" and "equal=1" (every edge exactly once).  Conflicts are counted
+// on a model of the gfx950 LDS written out here, not on the schedule's own
+// group size: 64 banks of 4 bytes; a read of 4 W bytes per lane is served in
+// groups of 256 bytes of lanes (W >= 2) or 32 lanes (W = 1), a write in groups
+// of 128 bytes of lanes, and every bank touched twice within a group is one
+// conflict (u-rows and v-rows separately, reads and writes separately).
 #include "internal.hpp"
 #include <cstdio>
 #include <set>
@@ -27,23 +31,29 @@ int main(int argc, char** argv) {
   // (class, slot_u, slot_v, J) of every edge, expected and scheduled
   std::multiset<std::tuple<int,int,int,float>> want, got;
   for (long k = 0; k < m; k++) want.insert({s.h_colour[k], vslot[s.h_eu[k]] , vslot[s.h_ev[k]], (float)s.h_J[k]});
+  const int rlanes = W == 1 ? 32 : 256 / (4 * W), wlanes = 128 / (4 * W);
   int j = 0; long conflicts = 0, active = 0;
+  auto count = [&](int jj, int g0, int lanes, bool record) {
+    int bu[64] = {0}, bv[64] = {0};
+    for (int t = g0; t < g0 + lanes && t < L.nth; t++) {
+      auto d = L.desc[(size_t)jj * L.nth + t];
+      if (d.slots == cosm::kEmptySlot) continue;
+      int su = d.slots & 0xffff, sv = d.slots >> 16;
+      if (record) { active++; got.insert({0, su, sv, d.J}); }
+      for (int w = 0; w < W; w++) { bu[(su * W + w) % 64]++; bv[(sv * W + w) % 64]++; }
+    }
+    for (int b = 0; b < 64; b++) conflicts += (bu[b] > 1 ? bu[b] - 1 : 0) + (bv[b] > 1 ? bv[b] - 1 : 0);
+  };
+  std::multiset<std::tuple<int,int,int,float>> got_c;
   for (int c = 0; c < C; c++) {
     for (int k = 0; k < L.K[c]; k++, j++) {
-      for (int g0 = 0; g0 < L.nth; g0 += L.G) {
-        std::set<int> ru, rv; int act = 0;
-        for (int t = g0; t < g0 + L.G; t++) {
-          auto d = L.desc[(size_t)j * L.nth + t];
-          if (d.slots == cosm::kEmptySlot) continue;
-          act++; active++;
-          int su = d.slots & 0xffff, sv = d.slots >> 16;
-          got.insert({c, su, sv, d.J});
-          ru.insert(su % L.G); rv.insert(sv % L.G);
-        }
-        conflicts += (act - (long)ru.size()) + (act - (long)rv.size());
-      }
+      got.clear();
+      for (int g0 = 0; g0 < L.nth; g0 += rlanes) count(j, g0, rlanes, true);
+      for (int g0 = 0; g0 < L.nth; g0 += wlanes) count(j, g0, wlanes, false);
+      for (auto &e : got) got_c.insert({c, std::get<1>(e), std::get<2>(e), std::get<3>(e)});
     }
   }
+  got = got_c;
   printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got));
   return 0;
 }

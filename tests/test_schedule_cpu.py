@@ -1,7 +1,9 @@
 """Host checks of the LDS lane schedule (schedule.cpp), compiled with g++ and
-run on the CPU: every edge appears once, in its own class, and every aligned
-group of G lanes touches G distinct LDS bank groups (slot mod G) for its
-u-rows and for its v-rows."""
+run on the CPU: every edge appears once, in its own class, and no LDS bank is
+touched twice by the u-rows, or by the v-rows, of one group of lanes that the
+gfx950 LDS serves together (reads: 256 bytes of lanes, 32 lanes for 4-byte
+rows; writes: 128 bytes of lanes; the model is written out in
+sched_check.cpp)."""
 import os
 import subprocess
 
