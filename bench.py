@@ -23,11 +23,41 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs at 2.4 GHz; LDS serves 128 B/clk/CU (measured 125 B/clk/CU
-# with conflict-free ds_read_b128 / ds_write_b128).
+# MI355X: 256 CUs at 2.4 GHz.  LDS peak taken as 128 B/clk/CU (the CDNA figure;
+# 78.6 TB/s).  On gfx950 conflict-free reads measure up to ~190 B/clk/CU and
+# writes ~72-78 B/clk/CU, so the sweep's 50/50 read/write mix has a lower
+# measured ceiling, which the run also reports (cosm_lds_probe).
 LDS_PEAK_GBS = 128 * 256 * 2.4          # 78643 GB/s
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-ops per second, non-packed FP32
+
+# HBM bytes per launch of the sweep kernel at this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the counter
+# reads for a 256 MiB device copy (FETCH_SIZE 131087 KiB -> x2.0; WRITE_SIZE
+# 262144 KiB -> x1.0).  Valid only for the kernel sources they were taken on.
+TRAFFIC = dict(fetch_kib=4162.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
+               sources_sha256="72daaba8cf803c1974997309e213be5c37a94c18d1bb47ad574c653c30a4a9c2")
+TRAFFIC_SOURCES = ("paper_2605_30355_amd/csrc/kernels.hip",
+                   "paper_2605_30355_amd/csrc/device_common.hpp")
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    """HBM bytes per sweep launch from the recorded counters, or None when the
+    kernel sources changed since they were taken."""
+    if sources_sha256() != TRAFFIC["sources_sha256"]:
+        return None
+    return round(1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"]
+                         + TRAFFIC["write_kib"] * TRAFFIC["write_factor"]))
+
 
 WORKLOAD = dict(name="maxcut-3reg-n2000", n=2000, degree=3, seed=2, weights="maxcut1",
                 replicas=1024, sweeps=10000, alpha0_deg=14.0, dwt_ratio=1.0, dwt_period=6,
@@ -255,9 +285,16 @@ def main():
     n_dwt = S // WORKLOAD["dwt_period"]
     lds_bytes_per_launch = R * (S * 4 * b * m + n_dwt * 2 * b * inst.n)
     achieved = lds_bytes_per_launch / avg_kernel_s / 1e9
+    row_words = info["replicas_per_wg"]  # FP32: one word per replica
+    measured = max(cosm.lds_probe(row_words, bpc) for bpc in (1, 2))
     roofline = {"bound": "lds", "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
-                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sweep_lds<fp32,4>",
+                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
+                "traffic": traffic_bytes(), "traffic_unit": "HBM bytes per launch",
+                "measured_peak": round(measured, 1),
+                "measured_peak_note": "cosm_lds_probe: 2 reads + 2 writes per lane of "
+                                      f"{4 * row_words}-byte rows, no arithmetic or barriers",
+                "frac_of_measured": round(achieved / measured, 4),
+                "kernel": f"k_sweep_lds<fp32, {row_words} words/row>",
                 "bytes_per_edge_update": 4 * b,
                 "edge_updates_per_s_kernel": round(m * S * R / avg_kernel_s, 1)}
 

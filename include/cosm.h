@@ -252,6 +252,17 @@ int cosm_get_info(const cosm_state *s, cosm_info *out);
 /* Time every sweep kernel with HIP events on the state's stream (on != 0). */
 int cosm_set_timing(cosm_state *s, int32_t on);
 
+/* LDS bandwidth ceiling of the current device for the sweep's access mix,
+ * measured with the library's own kernel: every lane reads two rows of
+ * row_words (1, 2 or 4) 32-bit words, adds one to each word and writes both
+ * back (2 reads + 2 writes, as per edge of a sweep, without the arithmetic), rows
+ * of consecutive lanes in distinct banks, blocks_per_cu (1 or 2) workgroups of
+ * 768 threads per compute unit, no barriers.  Writes the aggregate LDS bytes
+ * (reads + writes) per second over all compute units, in GB/s, to *gbs_out.
+ * Runs on hip_stream (NULL: the default stream) and synchronises it.
+ * EINVAL for other row_words / blocks_per_cu, EDEVICE on a HIP error. */
+int cosm_lds_probe(int32_t row_words, int32_t blocks_per_cu, void *hip_stream, double *gbs_out);
+
 const char *cosm_last_error(void);
 const char *cosm_version(void);
 

@@ -15,5 +15,6 @@ from .cosm import (  # noqa: F401
     UNIT_DEGREES, UNIT_RADIANS, UNIT_TURNS,
     UPDATE_FULL_GRADIENT, UPDATE_SCS,
     Batch, CosmError, Params, State, TTSResult,
-    build_partitions, default_params, exported_symbols, library_path, load_library, version,
+    build_partitions, default_params, exported_symbols, lds_probe, library_path, load_library,
+    version,
 )

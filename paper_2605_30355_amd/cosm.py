@@ -26,7 +26,7 @@ ABI_FUNCTIONS = (
     "cosm_default_params", "cosm_build_partitions", "cosm_workspace_bytes", "cosm_init",
     "cosm_destroy", "cosm_reset", "cosm_sweep", "cosm_energy", "cosm_solve_to_target",
     "cosm_get_phases", "cosm_set_phases", "cosm_get_info", "cosm_set_timing",
-    "cosm_last_error", "cosm_version",
+    "cosm_last_error", "cosm_version", "cosm_lds_probe",
     "cosm_batch_create", "cosm_batch_destroy", "cosm_batch_add_graph", "cosm_batch_set_seed",
     "cosm_batch_run", "cosm_batch_wait", "cosm_batch_results",
 )
@@ -109,6 +109,7 @@ def load_library():
         "cosm_batch_wait": (I32, [P, ctypes.POINTER(ctypes.c_double)]),
         "cosm_batch_results": (I32, [P, I32, P, P, P]),
         "cosm_version": (ctypes.c_char_p, []),
+        "cosm_lds_probe": (I32, [I32, I32, P, ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -126,6 +127,17 @@ def exported_symbols():
 
 def version() -> str:
     return load_library().cosm_version().decode()
+
+
+def lds_probe(row_words: int = 2, blocks_per_cu: int = 2) -> float:
+    """LDS ceiling of the device for the sweep's read/update/write mix, GB/s
+    (cosm_lds_probe), on torch's current stream."""
+    import torch
+    out = ctypes.c_double(0.0)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(load_library().cosm_lds_probe(int(row_words), int(blocks_per_cu), stream,
+                                         ctypes.byref(out)))
+    return out.value
 
 
 def _check(status: int):

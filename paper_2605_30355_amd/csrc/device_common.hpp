@@ -59,6 +59,14 @@ __device__ __forceinline__ uint32_t philox_first_word(uint32_t c0, uint32_t c1, 
   return c0;
 }
 
+// Logical index of workgroup b of nb when consecutive workgroups are dealt to
+// the 8 XCDs in turn: XCD x runs logical indices [x q, x q + q), q = nb / 8
+// (the nb % 8 workgroups past 8 q keep their own index).
+__device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb) {
+  const int32_t q = nb >> 3;
+  return b < 8 * q ? (b & 7) * q + (b >> 3) : b;
+}
+
 __device__ __forceinline__ float fract1(float v) { return __builtin_amdgcn_fractf(v); }
 
 // ---------------------------------------------------------------------------
@@ -131,10 +139,21 @@ struct Fmt16 {
       }
     }
   }
+  // two values per word with one round-to-nearest-even packed conversion
   template <int W>
   __device__ __forceinline__ static void pack(const float (&v)[2 * W], uint32_t (&w)[W]) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int k = 0; k < W; k++) w[k] = enc(v[2 * k]) | (enc(v[2 * k + 1]) << 16);
+    for (int k = 0; k < W; k++) {
+      const f32x2 p = {v[2 * k], v[2 * k + 1]};
+      if constexpr (ST == COSM_STORE_FP16) {
+        w[k] = __builtin_bit_cast(uint32_t, __builtin_convertvector(p, f16x2));
+      } else {
+        w[k] = __builtin_bit_cast(uint32_t, __builtin_convertvector(p, bf16x2));
+      }
+    }
   }
 };
 template <>

@@ -174,10 +174,13 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths);
 constexpr int kThetaChunk = 32;
 constexpr int kThetaFloats = kThetaChunk * 8;
 
-// LDS bytes of the sweep kernel: the rows, the table of reference angles and
-// the slot count of each of the C classes.
+// Rows after the n_rows vertex rows that masked lanes of the single-instance
+// sweep read and write instead of branching around their update (J = 0).
+constexpr int kDummyRows = 64;
+// LDS bytes of the sweep kernel: the vertex and dummy rows, the table of
+// reference angles and the slot count of each of the C classes.
 inline size_t lds_sweep_bytes(int32_t n_rows, int W, int32_t C) {
-  return (size_t)n_rows * W * 4 + (size_t)kThetaFloats * 4 + (size_t)C * 4;
+  return (size_t)(n_rows + kDummyRows) * W * 4 + (size_t)kThetaFloats * 4 + (size_t)C * 4;
 }
 
 size_t readout_lds_bytes(int32_t n, int32_t B);

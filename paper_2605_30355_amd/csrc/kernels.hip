@@ -52,14 +52,17 @@ __global__ void __launch_bounds__(256) k_init(void *phases, int32_t n, int32_t R
 // distinct LDS bank groups).  EMAX > 0: the schedule (at most EMAX slots) is
 // loaded into registers once; EMAX == 0: it streams from memory, one slot ahead.
 // ---------------------------------------------------------------------------
-template <int ST, int W, int EMAX>
+template <int ST, int W, int EMAX, bool EXACT>
 __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
   constexpr uint32_t ROWB = 4 * W;
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int32_t r0 = blockIdx.x * RW;
+  // Workgroups go to the 8 XCDs round-robin; give each XCD a contiguous range
+  // of replica blocks so that the workgroups sharing a cache line of a vertex
+  // row ([n][R] layout) share one L2.
+  const int32_t r0 = xcd_block(blockIdx.x, gridDim.x) * RW;
   const int32_t nvalid = min(RW, a.R - r0);
 
   // HBM [n][R] -> LDS rows
@@ -73,25 +76,34 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     lds_store<W>(lds, s, w);
   }
 
-  // table of reference angles (filled at the first twist of every chunk), then
-  // the slots per class
-  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)a.n_rows * W);  // [kThetaChunk][RW]
+  // dummy rows for masked lanes (zero, never stored back), the table of
+  // reference angles (filled at the first twist of every chunk), then the slots
+  // per class
+  for (int s = tid; s < kDummyRows; s += nth) {
+    const uint32_t z[W] = {};
+    lds_store<W>(lds, a.n_rows + s, z);
+  }
+  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)(a.n_rows + kDummyRows) * W);  // [kThetaChunk][RW]
   int32_t *Ks = reinterpret_cast<int32_t *>(theta_buf + kThetaFloats);         // [C]
   if constexpr (EMAX == 0)
     for (int c = tid; c < a.C; c += nth) Ks[c] = a.Kc[c];
   int tw = 0;  // twists done in this call
 
-  // register-resident lane schedule
+  // register-resident lane schedule; a masked lane updates two dummy rows
+  // with J = 0 (a no-op), so the slots need no branches
   uint32_t ua[EMAX > 0 ? EMAX : 1], va[EMAX > 0 ? EMAX : 1];
   float jr[EMAX > 0 ? EMAX : 1];
   if constexpr (EMAX > 0) {
+    const uint32_t du = (uint32_t)(a.n_rows + (tid & 31)) * ROWB;
+    const uint32_t dv = (uint32_t)(a.n_rows + 32 + (tid & 31)) * ROWB;
 #pragma unroll
     for (int j = 0; j < EMAX; j++) {
       EdgeDesc d{kEmptySlot, 0.0f};
-      if (j < a.total_slots) d = a.desc[(size_t)j * nth + tid];
-      ua[j] = d.slots == kEmptySlot ? kEmptySlot : (d.slots & 0xffffu) * ROWB;
-      va[j] = (d.slots >> 16) * ROWB;
-      jr[j] = d.J;
+      if (EXACT || j < a.total_slots) d = a.desc[(size_t)j * nth + tid];
+      const bool empty = d.slots == kEmptySlot;
+      ua[j] = empty ? du : (d.slots & 0xffffu) * ROWB;
+      va[j] = empty ? dv : (d.slots >> 16) * ROWB;
+      jr[j] = empty ? 0.0f : d.J;
     }
   }
   // streamed schedule: the first two slots in flight
@@ -108,11 +120,18 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     float alpha, twist;
     schedule_step(sc, t, alpha, twist);
     // Sequential conflict-free search: classes in order, a barrier after each.
-    if constexpr (EMAX > 0) {
+    if constexpr (EXACT) {
+      // EMAX slots, one class each
+#pragma unroll
+      for (int j = 0; j < EMAX; j++) {
+        edge_rows<ST, W>(lds, ua[j], va[j], alpha * jr[j]);
+        __syncthreads();
+      }
+    } else if constexpr (EMAX > 0) {
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
         if (j < a.total_slots) {
-          if (ua[j] != kEmptySlot) edge_rows<ST, W>(lds, ua[j], va[j], alpha * jr[j]);
+          edge_rows<ST, W>(lds, ua[j], va[j], alpha * jr[j]);
           if ((a.bar_mask >> j) & 1u) __syncthreads();
         }
       }
@@ -271,7 +290,8 @@ __global__ void __launch_bounds__(256) k_full_gradient(const void *src, void *ds
 template <int ST>
 __global__ void __launch_bounds__(256) k_readout(const ReadoutArgs a) {
   extern __shared__ int64_t sm64[];
-  readout_block<ST>(a, blockIdx.x, sm64);
+  // one replica per workgroup; replicas sharing a cache line on one XCD
+  readout_block<ST>(a, xcd_block(blockIdx.x, gridDim.x), sm64);
 }
 
 // Energy (Eq. (1)) and cut (Eq. (14), w = -J) of caller-supplied spins [R][n].
@@ -337,23 +357,27 @@ float host_twist(const Schedule &sc, int64_t t) {
   return sc.dwt_ratio * host_alpha(sc, t);
 }
 
-template <int ST, int W, int EMAX>
+template <int ST, int W, int EMAX, bool EXACT>
 int launch_lds(cosm_state *s, const LdsArgs &a) {
   const size_t lds = s->shape.lds_bytes;
-  (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, W, EMAX>,
+  (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, W, EMAX, EXACT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_sweep_lds<ST, W, EMAX>), dim3(s->shape.blocks), dim3(s->shape.threads), lds,
-                     s->stream, a);
+  hipLaunchKernelGGL((k_sweep_lds<ST, W, EMAX, EXACT>), dim3(s->shape.blocks),
+                     dim3(s->shape.threads), lds, s->stream, a);
   return launch_check("k_sweep_lds");
 }
 
 template <int ST, int W>
 int launch_lds_w(cosm_state *s, const LdsArgs &a) {
   const int slots = a.total_slots;
-  if (slots <= 4) return launch_lds<ST, W, 4>(s, a);
-  if (slots <= 8) return launch_lds<ST, W, 8>(s, a);
-  if (slots <= 16) return launch_lds<ST, W, 16>(s, a);
-  return launch_lds<ST, W, 0>(s, a);
+  // one slot per class and exactly 4 / 8 slots: the unconditional form
+  const bool one_each = slots == a.C && slots <= 32 && a.bar_mask == (uint32_t)((1ull << slots) - 1);
+  if (one_each && slots == 4) return launch_lds<ST, W, 4, true>(s, a);
+  if (one_each && slots == 8) return launch_lds<ST, W, 8, true>(s, a);
+  if (slots <= 4) return launch_lds<ST, W, 4, false>(s, a);
+  if (slots <= 8) return launch_lds<ST, W, 8, false>(s, a);
+  if (slots <= 16) return launch_lds<ST, W, 16, false>(s, a);
+  return launch_lds<ST, W, 0, false>(s, a);
 }
 
 template <int ST>
