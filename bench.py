@@ -125,6 +125,85 @@ FAMILY_PARAMS = {"torus": dict(dwt_ratio=0.5, dwt_period=3),
                  "5-regular": dict(dwt_ratio=1.5, dwt_period=3)}
 
 
+ABLATION = dict(replicas=1024, batches=2, sweeps=10000, seed=11)
+
+
+def wilson(k, n, z=1.959964):
+    if n == 0:
+        return (0.0, 1.0)
+    p = k / n
+    d = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / d
+    h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / d
+    return (max(0.0, c - h), min(1.0, c + h))
+
+
+def ablation_bench():
+    """Table VII's ablation on synthetic stand-ins: the full method against the
+    same sweeps without SCS (Eq. (8) full-gradient update, all edges reading
+    the phases of the previous sweep), without the dual window twist (T = 0)
+    and without both.  Per variant: energies of R x batches trials at S sweeps,
+    P_s at the oracle's best energy and at 0.5 % above it (Wilson CI), R99 and
+    TTT with t_trial from HIP events around each batch (init, sweeps, readout)."""
+    import numpy as np
+    import torch
+
+    import cosm_inputs as ci
+    import paper_2605_30355_amd as cosm
+
+    torch.cuda.set_device(0)
+    with open(os.path.join(ROOT, "tests", "golden", "targets.json")) as f:
+        targets = json.load(f)
+    work = [("maxcut-3reg-n2000", make_instance(), dict(dwt_ratio=1.0, dwt_period=6)),
+            ("maxcut-er-n10000", ci.erdos_renyi_capped(10000, 2.0, 9, seed=70, weights="maxcut1"),
+             dict(dwt_ratio=1.0, dwt_period=6))]
+    R, nb, S = ABLATION["replicas"], ABLATION["batches"], ABLATION["sweeps"]
+    out = {"metric": "ablation (Table VII): P_s and TTT @99% without SCS / without DWT",
+           "replicas_per_batch": R, "batches": nb, "sweeps": S, "instances": {}}
+    stream = torch.cuda.current_stream()
+    for name, inst, kw in work:
+        colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+        tH = targets[name]["target_H"]
+        relaxed = int(math.floor(tH * 0.995))  # H < 0: 0.5 % above the best energy
+        rec = {"n": inst.n, "m": inst.m, "classes": C, "target_H": tH, "relaxed_target_H": relaxed,
+               "variants": {}}
+        for vname, over in (("full", {}), ("without_dwt", {"dwt_period": 0}),
+                            ("without_scs", {"update": cosm.UPDATE_FULL_GRADIENT}),
+                            ("without_both", {"update": cosm.UPDATE_FULL_GRADIENT, "dwt_period": 0})):
+            p = cosm.Params(sweeps_per_trial=S, **kw)
+            for k, v in over.items():
+                setattr(p, k, v)
+            st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=ABLATION["seed"],
+                            replicas=R)
+            Hs, ms = [], 0.0
+            for k in range(nb):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                st.reset(ABLATION["seed"], k * R)
+                st.sweep(S)
+                H, _, _ = st.energy(return_spins=False)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms += e0.elapsed_time(e1)
+                Hs.append(H.copy())
+            info = st.info()
+            st.close()
+            H = np.concatenate(Hs)
+            t_trial = ms * 1e-3 / (R * nb)
+            v = {"form": {cosm.RES_LDS: "lds", cosm.RES_HBM: "hbm"}.get(info["residency"], "plain"),
+                 "mean_H": float(H.mean()), "best_H": int(H.min()), "t_trial_s": t_trial}
+            for label, thr in (("target", tH), ("relaxed", relaxed)):
+                k = int((H <= thr).sum())
+                ps = k / len(H)
+                r99 = (1.0 if ps >= 1.0 else math.log(0.01) / math.log(1.0 - ps)) if ps > 0 else None
+                v[label] = {"hits": k, "ps": ps, "ps_ci95": list(wilson(k, len(H))), "r99": r99,
+                            "ttt_s": t_trial * r99 if r99 is not None else None}
+            rec["variants"][vname] = v
+            log(f"ablation {name} {vname}: {v}")
+        out["instances"][name] = rec
+    return out
+
+
 def stream_bench():
     """Mixed request stream: 256 solve requests (N uniform in [400, 20000]; torus,
     3-regular Max-Cut and 5-regular +-1 graphs), each a whole trial of 256
@@ -215,6 +294,8 @@ def main():
                     help="also run one 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--stream", action="store_true",
                     help="measure the mixed request stream instead (prints its own JSON line)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="run the Table VII ablation instead (prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's replicas are independent, so several "
@@ -223,6 +304,9 @@ def main():
         sys.exit(2)
     if args.stream:
         print(json.dumps(stream_bench()), flush=True)
+        return
+    if args.ablation:
+        print(json.dumps(ablation_bench()), flush=True)
         return
 
     import numpy as np

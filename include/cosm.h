@@ -130,6 +130,13 @@ int cosm_workspace_bytes(int32_t n, int64_t m, int32_t num_colours, int32_t repl
  * initial phases of replicas 0..replicas-1 (Algorithm 1, "Set x_i random"):
  * Philox4x32-10 with key = seed, counter (i, 0, replica, "INIT").
  *   J: Ising couplings (Eq. (1) sign), m entries.  h: n entries or NULL (h = 0).
+ *     With h the sweep couples every x_i with h_i != 0 to a fixed virtual
+ *     spin at phase 0 (coupling h_i), applied by Eq. (6) as one more
+ *     conflict-free sub-sweep after the C classes; each twist then rotates in
+ *     a direction drawn per (replica, twist) from word 1 of the reference
+ *     angle's Philox draw; the readout uses the single semicircle centred at
+ *     0 (B is forced to 1).  The paper leaves h out of the dynamics (Eq. (7));
+ *     this is the library's reading.  |alpha0 * h_i| is bounded like |J|.
  *   colour / num_colours: as returned by cosm_build_partitions or any proper
  *     colouring; classes are applied in index order.
  *   hip_stream: a hipStream_t or NULL for the default stream.

@@ -78,6 +78,8 @@ def lib():
                                       ctypes.c_int32, ctypes.c_int32, P]
         L.orc_theta_ref.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
         L.orc_theta_ref.restype = ctypes.c_double
+        L.orc_twist_direction.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
+        L.orc_twist_direction.restype = ctypes.c_int32
         L.orc_sweeps.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Params),
                                  ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
                                  ctypes.c_int64, ctypes.c_int64, P, P, ctypes.c_int64,
@@ -176,6 +178,11 @@ def bisector(params: Params, idx: int) -> float:
 
 def theta_ref(seed: int, t: int, rid: int) -> float:
     return lib().orc_theta_ref(seed, t, rid)
+
+
+def twist_direction(seed: int, t: int, rid: int) -> int:
+    """+1 / -1: the twist sense drawn per event when bias fields are present."""
+    return lib().orc_twist_direction(seed, t, rid)
 
 
 def init_phases(n, seed, rid0, R, schedule=SCHED_GRID):

@@ -195,6 +195,18 @@ double orc_theta_ref(uint64_t seed, int64_t t, int64_t rid) {
   return (double)(w >> 9) * 360.0 / TWO_POW_23;
 }
 
+/* Direction of the twist.  Without bias fields one direction suffices
+ * (Sec. II-D) and it is always +.  With bias fields the rotation sense matters,
+ * so each twist event draws it: -1 when the top bit of word 1 of the same
+ * Philox draw as theta is set, else +1 (a reading; the paper gives no rule). */
+int32_t orc_twist_direction(uint64_t seed, int64_t t, int64_t rid) {
+  uint32_t ctr[4] = {0u, (uint32_t)t, (uint32_t)rid, ORC_TAG_DWT};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  orc_philox4x32_10(ctr, key, out);
+  return (out[1] >> 31) ? -1 : 1;
+}
+
 /* ------------------------------------------------------------------------ */
 /* One replica's sweeps.                                                      */
 /* ------------------------------------------------------------------------ */
@@ -238,6 +250,19 @@ static void run_replica(const orc_problem *pb, const orc_params *p, uint64_t see
           x[j] = mod_pos(x[j] + dxj, 360.0);
         }
       }
+      /* Bias fields (a reading; the paper leaves h out of the dynamics,
+       * Eq. (7)): h_i couples x_i to a fixed virtual spin at phase 0 with
+       * coupling h_i, applied by Eq. (6) as one more conflict-free sub-sweep
+       * after the C classes; the virtual spin does not move. */
+      if (pb->h != NULL) {
+        for (int32_t i = 0; i < n; i++) {
+          if (pb->h[i] == 0) continue;
+          const double dw = wrapped_difference(x[i] - 0.0);
+          const int s = sgn_b(dw);
+          if (diag) min_margin = dmin(min_margin, decision_margin(dw));
+          x[i] = mod_pos(x[i] - alpha * (double)pb->h[i] * (double)s, 360.0);
+        }
+      }
     } else {
       /* Eq. (8): every edge reads x_t, contributions are summed per variable. */
       for (int32_t i = 0; i < n; i++) acc[i] = 0.0;
@@ -249,16 +274,27 @@ static void run_replica(const orc_problem *pb, const orc_params *p, uint64_t see
         acc[i] += -alpha * (double)pb->J[k] * (double)s;
         acc[j] += +alpha * (double)pb->J[k] * (double)s;
       }
+      /* the virtual spin at phase 0 is one more neighbour (coupling h_i) */
+      if (pb->h != NULL) {
+        for (int32_t i = 0; i < n; i++) {
+          if (pb->h[i] == 0) continue;
+          const double dw = wrapped_difference(x[i] - 0.0);
+          if (diag) min_margin = dmin(min_margin, decision_margin(dw));
+          acc[i] += -alpha * (double)pb->h[i] * (double)sgn_b(dw);
+        }
+      }
       for (int32_t i = 0; i < n; i++) x[i] = mod_pos(x[i] + acc[i], 360.0);
     }
 
     /* Dual window twist, Algorithm 1 and Sec. II-D: two opposing windows of
      * width w centred at theta and theta + 180; members (tested on the
-     * pre-twist phases) rotate by ratio * alpha_t, always in the + direction. */
+     * pre-twist phases) rotate by ratio * alpha_t, in the + direction without
+     * bias fields and in a drawn direction with them. */
     if (p->dwt_period > 0 && t % p->dwt_period == 0) {
       const double theta = orc_theta_ref(seed, t, rid);
       const double w = p->dwt_window_deg;
-      const double twist = p->dwt_ratio * alpha;
+      const double dir = pb->h != NULL ? (double)orc_twist_direction(seed, t, rid) : 1.0;
+      const double twist = dir * p->dwt_ratio * alpha;
       for (int32_t i = 0; i < n; i++) {
         const double pos = mod_pos(x[i] - theta + 0.5 * w, 180.0);
         if (diag) min_margin = dmin(min_margin, dmin(pos, dmin(fabs(pos - w), 180.0 - pos)));

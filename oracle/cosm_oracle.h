@@ -92,6 +92,10 @@ void orc_init_phases(int32_t n, uint64_t seed, int64_t rid0, int32_t R, int32_t 
 /* DWT reference angle for (sweep t, replica rid), degrees. */
 double orc_theta_ref(uint64_t seed, int64_t t, int64_t rid);
 
+/* Twist direction (+1 / -1) for (sweep t, replica rid), used only with bias
+ * fields; word 1 of the reference angle's Philox draw. */
+int32_t orc_twist_direction(uint64_t seed, int64_t t, int64_t rid);
+
 /* Run sweeps t_from+1 .. t_from+n_sweeps for R replicas (rows of x, [R][n]).
  * If margin is not NULL, margin[r] receives the smallest distance (degrees) of
  * any sign decision, window edge or wrap point from its threshold during the

@@ -29,7 +29,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every device buffer inside one allocation.
 struct MemPlan {
-  size_t phases, desc, class_off, slot_vertex, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
+  size_t phases, desc, class_off, slot_vertex, h_slot, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
       inc_off, inc_nbr, inc_J, phases_alt, total;
 };
 
@@ -47,6 +47,7 @@ MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_param
   mp.desc = take(((size_t)32 * m + (size_t)1024 * C + 1024) * sizeof(EdgeDesc));
   mp.class_off = take(((size_t)C + 1) * 4);
   mp.slot_vertex = take(((size_t)n + 1) * 4);
+  mp.h_slot = take(((size_t)n + 1) * 4);
   mp.eu = take((size_t)m * 4);
   mp.ev = take((size_t)m * 4);
   mp.J = take((size_t)m * 4);
@@ -306,7 +307,12 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
     sum_abs += a;
   }
   if (h != nullptr)
-    for (int32_t i = 0; i < n; i++) sum_abs += std::llabs((int64_t)h[i]);
+    for (int32_t i = 0; i < n; i++) {
+      // a field is the coupling to the virtual spin: the same step bound applies
+      const int64_t a = std::llabs((int64_t)h[i]);
+      max_abs_J = (int32_t)std::max<int64_t>(max_abs_J, a);
+      sum_abs += a;
+    }
   if (sum_abs >= ((int64_t)1 << 60)) return set_error(COSM_ERANGE, "couplings too large");
 
   cosm_state *s = new (std::nothrow) cosm_state();
@@ -411,6 +417,7 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   d.desc = at<EdgeDesc>(s->base, mp.desc);
   d.class_off = at<int32_t>(s->base, mp.class_off);
   d.slot_vertex = at<int32_t>(s->base, mp.slot_vertex);
+  d.h_slot = at<int32_t>(s->base, mp.h_slot);
   d.eu = at<int32_t>(s->base, mp.eu);
   d.ev = at<int32_t>(s->base, mp.ev);
   d.J = at<int32_t>(s->base, mp.J);
@@ -437,6 +444,7 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
     rc = rc ? rc : up(d.desc, s->lds.desc.data(), s->lds.desc.size() * sizeof(EdgeDesc));
     rc = rc ? rc : up(d.class_off, s->lds.K.data(), s->lds.K.size() * 4);
     rc = rc ? rc : up(d.slot_vertex, s->lds.slot_vertex.data(), s->lds.slot_vertex.size() * 4);
+    rc = rc ? rc : upload_h_slot(s);
   }
   rc = rc ? rc : up(d.eu, eu, (size_t)m * 4);
   rc = rc ? rc : up(d.ev, ev, (size_t)m * 4);

@@ -47,6 +47,7 @@ int upload_schedule(cosm_state *s) {
                                   hipMemcpyHostToDevice, s->stream));
   COSM_HIP_CHECK(hipMemcpyAsync(s->d.slot_vertex, L.slot_vertex.data(),
                                 L.slot_vertex.size() * 4, hipMemcpyHostToDevice, s->stream));
+  if (int rc = upload_h_slot(s)) return rc;
   COSM_HIP_CHECK(hipStreamSynchronize(s->stream));  // host vectors may change next
   return COSM_OK;
 }
@@ -62,6 +63,16 @@ int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw) {
 }
 
 }  // namespace
+
+int upload_h_slot(cosm_state *s) {
+  if (!s->has_h) return COSM_OK;
+  const LdsSchedule &L = s->lds;
+  s->h_slot.assign(L.slot_vertex.size(), 0);
+  for (size_t k = 0; k < L.slot_vertex.size(); k++) s->h_slot[k] = s->h_h[(size_t)L.slot_vertex[k]];
+  COSM_HIP_CHECK(hipMemcpyAsync(s->d.h_slot, s->h_slot.data(), s->h_slot.size() * 4,
+                                hipMemcpyHostToDevice, s->stream));
+  return COSM_OK;
+}
 
 int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
   const int32_t pw = s->p.storage == COSM_STORE_FP32 ? 1 : 2;

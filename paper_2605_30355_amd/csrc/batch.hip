@@ -139,8 +139,8 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
       sc.phase = 0;
       const int slot = tw % nch;
       if (slot == 0) {
-        theta_fill(theta_buf, nch, nreps, t, sc.period, g.rid0 + (uint32_t)it.r0, g.k0, g.k1,
-                   sc.win);
+        theta_fill(theta_buf, nullptr, nch, nreps, t, sc.period, g.rid0 + (uint32_t)it.r0, g.k0,
+                   g.k1, sc.win);
         __syncthreads();
       }
       tw++;

@@ -41,8 +41,8 @@ __device__ __forceinline__ gptr_mut<T> as_global_mut(T *p) {
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products,
 // Weyl key schedule; only output word 0 is used here.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t philox_first_word(uint32_t c0, uint32_t c1, uint32_t c2,
-                                                      uint32_t c3, uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ uint2 philox_words01(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int i = 0; i < 10; i++) {
     const uint32_t ka = k0 + (uint32_t)i * 0x9E3779B9u;
@@ -56,7 +56,12 @@ __device__ __forceinline__ uint32_t philox_first_word(uint32_t c0, uint32_t c1, 
     c2 = n2;
     c3 = p0lo;
   }
-  return c0;
+  return make_uint2(c0, c1);
+}
+
+__device__ __forceinline__ uint32_t philox_first_word(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                      uint32_t c3, uint32_t k0, uint32_t k1) {
+  return philox_words01(c0, c1, c2, c3, k0, k1).x;
 }
 
 // Logical index of workgroup b of nb when consecutive workgroups are dealt to
@@ -194,6 +199,16 @@ __device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ) {
   xv = Fmt<ST>::wrap(xv + dl);
 }
 
+// Eq. (6) between x (storage convention) and a fixed virtual spin at phase 0
+// coupled with h (the bias field read as one more edge): s = +1 iff x lies in
+// [0, 1/2) turn, x <- wrap(x - alpha h s).
+template <int ST>
+__device__ __forceinline__ void field_update(float &v, float ah) {
+  const float f = fract1(Fmt<ST>::to_turn(v));
+  const float d = (f < 0.5f) ? ah : -ah;
+  v = Fmt<ST>::wrap(v - d);
+}
+
 // Dual window twist membership: mod_{1/2}(x - theta + w/2) < w, evaluated as
 // fract(2x - c) < 2w with c = 2 theta - w (valid for x and for y = x - 1/2).
 __device__ __forceinline__ bool in_windows(float v, float c, float win2) {
@@ -238,15 +253,19 @@ __device__ __forceinline__ void schedule_step(SweepSchedule &sc, int64_t t, floa
 }
 
 // Fills table[q * nrep + k] with c = 2 theta - w for the twist at sweep
-// t_first + q * period (q < nch) and replica rid_base + k (k < nrep).  Every
-// thread of the workgroup takes part; the caller synchronises.
-__device__ __forceinline__ void theta_fill(float *table, int nch, int nrep, int64_t t_first,
-                                           int32_t period, uint32_t rid_base, uint32_t k0,
-                                           uint32_t k1, float win) {
+// t_first + q * period (q < nch) and replica rid_base + k (k < nrep), and, when
+// dirs is not null, dirs[q * nrep + k] with that twist's direction (+-1 from
+// the top bit of word 1 of the same draw; used with bias fields).  Every thread
+// of the workgroup takes part; the caller synchronises.
+__device__ __forceinline__ void theta_fill(float *table, float *dirs, int nch, int nrep,
+                                           int64_t t_first, int32_t period, uint32_t rid_base,
+                                           uint32_t k0, uint32_t k1, float win) {
   for (int i = threadIdx.x; i < nch * nrep; i += blockDim.x) {
     const int q = i / nrep, k = i - q * nrep;
-    table[i] = 2.0f * theta_turns((uint32_t)(t_first + (int64_t)q * period), rid_base + (uint32_t)k,
-                                  k0, k1) - win;
+    const uint2 w = philox_words01(0u, (uint32_t)(t_first + (int64_t)q * period),
+                                   rid_base + (uint32_t)k, kTagDwt, k0, k1);
+    table[i] = 2.0f * ((float)(w.x >> 9) * kQ23) - win;
+    if (dirs != nullptr) dirs[i] = (w.y >> 31) ? -1.0f : 1.0f;
   }
 }
 

@@ -97,6 +97,7 @@ struct DeviceBuffers {
   EdgeDesc *desc = nullptr;     // LDS-form descriptors, grouped by class
   int32_t *class_off = nullptr; // [C+1] offsets into desc
   int32_t *slot_vertex = nullptr; // [n_slots] vertex held by each LDS slot
+  int32_t *h_slot = nullptr;    // [n_slots] bias field of the vertex in each slot (with h)
   int32_t *eu = nullptr;        // [m] (original ids)
   int32_t *ev = nullptr;
   int32_t *J = nullptr;
@@ -147,6 +148,7 @@ struct cosm_state {
   bool has_h = false;
   int64_t sumJ = 0;
   std::vector<int32_t> h_eu, h_ev, h_J, h_h, h_colour;
+  std::vector<int32_t> h_slot;       // h of the vertex in each LDS slot (host copy)
   std::vector<int32_t> class_sizes;  // edges per class
   std::vector<int32_t> class_begin;  // offset of each class in the grouped edge arrays
   // timing
@@ -169,8 +171,11 @@ int lds_capacity_bytes();
 int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out);
 // Measure candidate LDS shapes (row widths in words) and keep the fastest.
 int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths);
+// Uploads the bias field in LDS-slot order (no-op without bias fields).
+int upload_h_slot(cosm_state *s);
 // Reference angles of the dual window twist are drawn kThetaChunk twists at a
-// time into an LDS table of kThetaChunk x (at most 8) floats.
+// time into an LDS table of kThetaChunk x (at most 8) floats, followed by a
+// table of the same size for the twist directions (bias fields).
 constexpr int kThetaChunk = 32;
 constexpr int kThetaFloats = kThetaChunk * 8;
 
@@ -180,7 +185,7 @@ constexpr int kDummyRows = 64;
 // LDS bytes of the sweep kernel: the vertex and dummy rows, the table of
 // reference angles and the slot count of each of the C classes.
 inline size_t lds_sweep_bytes(int32_t n_rows, int W, int32_t C) {
-  return (size_t)(n_rows + kDummyRows) * W * 4 + (size_t)kThetaFloats * 4 + (size_t)C * 4;
+  return (size_t)(n_rows + kDummyRows) * W * 4 + (size_t)2 * kThetaFloats * 4 + (size_t)C * 4;
 }
 
 size_t readout_lds_bytes(int32_t n, int32_t B);

@@ -23,6 +23,7 @@ struct LdsArgs {
   const EdgeDesc *desc;       // [total_slots * nth] lane schedule
   const int32_t *Kc;          // [C] slots per thread of each class
   const int32_t *slot_vertex; // [n_rows]
+  const int32_t *h_slot;      // [n_rows] bias field per slot, or null (no fields)
   int32_t R, n_rows, C, total_slots;
   int64_t t0, nsw;
   SweepSchedule sch;
@@ -84,7 +85,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     lds_store<W>(lds, a.n_rows + s, z);
   }
   float *theta_buf = reinterpret_cast<float *>(lds + (size_t)(a.n_rows + kDummyRows) * W);  // [kThetaChunk][RW]
-  int32_t *Ks = reinterpret_cast<int32_t *>(theta_buf + kThetaFloats);         // [C]
+  float *dir_buf = theta_buf + kThetaFloats;                                  // [kThetaChunk][RW]
+  int32_t *Ks = reinterpret_cast<int32_t *>(dir_buf + kThetaFloats);          // [C]
   if constexpr (EMAX == 0)
     for (int c = tid; c < a.C; c += nth) Ks[c] = a.Kc[c];
   int tw = 0;  // twists done in this call
@@ -140,20 +142,51 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         edge_rows<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha * d.J);
       });
     }
+    // Bias fields: one more conflict-free sub-sweep against the virtual spin
+    // at phase 0, after the classes (rows are final after the last barrier).
+    if (a.h_slot != nullptr) {
+      for (int s0 = tid; s0 < a.n_rows; s0 += 4 * nth) {
+        int32_t hv[4];
+        uint32_t w[4][W];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          hv[q] = s0 + q * nth < a.n_rows ? a.h_slot[s0 + q * nth] : 0;
+          if (hv[q] != 0) lds_load<W>(lds, s0 + q * nth, w[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          if (hv[q] != 0) {
+            float v[RW];
+            F::template unpack<W>(w[q], v);
+            const float ah = alpha * (float)hv[q];
+#pragma unroll
+            for (int k = 0; k < RW; k++) field_update<ST>(v[k], ah);
+            F::template pack<W>(v, w[q]);
+            lds_store<W>(lds, s0 + q * nth, w[q]);
+          }
+        }
+      }
+      __syncthreads();
+    }
     // Dual window twist every `period` sweeps, on the phases after the last
-    // class (a barrier ended it).  Reference angles come from the LDS table,
-    // refilled by the whole workgroup every kThetaChunk twists.
+    // class (a barrier ended it).  Reference angles (and, with bias fields,
+    // directions) come from the LDS tables, refilled by the whole workgroup
+    // every kThetaChunk twists.
     if (sc.period > 0 && ++sc.phase == sc.period) {
       sc.phase = 0;
       const int slot = tw % kThetaChunk;
       if (slot == 0) {
-        theta_fill(theta_buf, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0, a.k0, a.k1, sc.win);
+        theta_fill(theta_buf, a.h_slot != nullptr ? dir_buf : nullptr, kThetaChunk, RW, t,
+                   sc.period, a.rid0 + (uint32_t)r0, a.k0, a.k1, sc.win);
         __syncthreads();
       }
       tw++;
-      float cth[RW];
+      float cth[RW], tws[RW];
 #pragma unroll
-      for (int k = 0; k < RW; k++) cth[k] = theta_buf[slot * RW + k];
+      for (int k = 0; k < RW; k++) {
+        cth[k] = theta_buf[slot * RW + k];
+        tws[k] = a.h_slot != nullptr ? dir_buf[slot * RW + k] * twist : twist;
+      }
       // four rows per thread in flight: all loads, then the updates and stores
       for (int s0 = tid; s0 < a.n_rows; s0 += 4 * nth) {
         uint32_t w[4][W];
@@ -167,7 +200,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
             F::template unpack<W>(w[q], v);
 #pragma unroll
             for (int k = 0; k < RW; k++)
-              if (in_windows(v[k], cth[k], sc.win2)) v[k] = F::wrap(v[k] + twist);
+              if (in_windows(v[k], cth[k], sc.win2)) v[k] = F::wrap(v[k] + tws[k]);
             F::template pack<W>(v, w[q]);
             lds_store<W>(lds, s0 + q * nth, w[q]);
           }
@@ -221,7 +254,7 @@ template <int ST>
 __global__ void __launch_bounds__(256) k_dwt_hbm(void *phases, int32_t n, int32_t R, int32_t rbeg,
                                                  int32_t rcount, int32_t strip, uint32_t t,
                                                  float twist, float win, float win2, uint32_t k0,
-                                                 uint32_t k1, uint32_t rid0) {
+                                                 uint32_t k1, uint32_t rid0, int32_t drawn_dir) {
   using F = Fmt<ST>;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t rchunks = (rcount + 63) / 64;
@@ -231,13 +264,32 @@ __global__ void __launch_bounds__(256) k_dwt_hbm(void *phases, int32_t n, int32_
   const int64_t i0 = (wave / rchunks) * strip;
   if (rloc >= rcount || i0 >= n) return;
   const int32_t r = rbeg + rloc;
-  const float c = 2.0f * theta_turns(t, rid0 + (uint32_t)r, k0, k1) - win;
+  const uint2 wd = philox_words01(0u, t, rid0 + (uint32_t)r, kTagDwt, k0, k1);
+  const float c = 2.0f * ((float)(wd.x >> 9) * kQ23) - win;
+  if (drawn_dir && (wd.y >> 31)) twist = -twist;  // with bias fields: drawn direction
   const int64_t i1 = min((int64_t)n, i0 + strip);
   for (int64_t i = i0; i < i1; i++) {
     const size_t idx = (size_t)i * R + r;
     const float v = F::load_elem(phases, idx);
     if (in_windows(v, c, win2)) F::store_elem(phases, idx, F::wrap(v + twist));
   }
+}
+
+// Bias-field sub-sweep for replicas [rbeg, rbeg + rcount) of the [n][R] array.
+template <int ST>
+__global__ void __launch_bounds__(256) k_field_hbm(void *phases, const int32_t *h, int32_t n,
+                                                   int32_t R, int32_t rbeg, int32_t rcount,
+                                                   float alpha) {
+  using F = Fmt<ST>;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n * rcount) return;
+  const int32_t i = (int32_t)(g / rcount), r = rbeg + (int32_t)(g % rcount);
+  const int32_t hv = h[i];
+  if (hv == 0) return;
+  const size_t idx = (size_t)i * R + r;
+  float v = F::load_elem(phases, idx);
+  field_update<ST>(v, alpha * (float)hv);
+  F::store_elem(phases, idx, v);
 }
 
 template <int ST>
@@ -266,8 +318,8 @@ template <int ST>
 __global__ void __launch_bounds__(256) k_full_gradient(const void *src, void *dst,
                                                        const int32_t *inc_off,
                                                        const uint32_t *inc_nbr,
-                                                       const float *inc_J, int32_t n,
-                                                       int32_t R, float alpha) {
+                                                       const float *inc_J, const int32_t *h,
+                                                       int32_t n, int32_t R, float alpha) {
   using F = Fmt<ST>;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * R) return;
@@ -282,6 +334,10 @@ __global__ void __launch_bounds__(256) k_full_gradient(const void *src, void *ds
     const float f = fract1(i_first ? xi - xj : xj - xi);
     const float aJs = (f < 0.5f) ? alpha * inc_J[a] : -alpha * inc_J[a];
     acc += i_first ? -aJs : aJs;
+  }
+  if (h != nullptr && h[i] != 0) {  // the virtual spin at phase 0 (bias field)
+    const float ah = alpha * (float)h[i];
+    acc += fract1(F::to_turn(xi)) < 0.5f ? -ah : ah;
   }
   F::store_elem(dst, (size_t)idx, F::wrap(xi + acc));
 }
@@ -387,6 +443,7 @@ int sweeps_lds_st(cosm_state *s, int64_t n_sweeps) {
   a.desc = s->d.desc;
   a.Kc = s->d.class_off;
   a.slot_vertex = s->d.slot_vertex;
+  a.h_slot = s->has_h ? s->d.h_slot : nullptr;
   a.R = s->R;
   a.n_rows = s->lds.n_rows;
   a.C = s->C;
@@ -439,8 +496,16 @@ int dwt_hbm_st(cosm_state *s, int64_t t, int32_t rbeg, int32_t rcount) {
   hipLaunchKernelGGL((k_dwt_hbm<ST>), grid, block, 0, s->stream, s->d.phases, s->n, s->R, rbeg,
                      rcount, strip, (uint32_t)t, host_twist(sc, t), sc.window, sc.window2,
                      (uint32_t)(s->seed & 0xffffffffu), (uint32_t)(s->seed >> 32),
-                     (uint32_t)s->rid0);
+                     (uint32_t)s->rid0, (int32_t)s->has_h);
   return launch_check("k_dwt_hbm");
+}
+
+template <int ST>
+int field_hbm_st(cosm_state *s, float alpha, int32_t rbeg, int32_t rcount) {
+  const int64_t threads = (int64_t)s->n * rcount;
+  hipLaunchKernelGGL((k_field_hbm<ST>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                     s->stream, s->d.phases, s->d.h, s->n, s->R, rbeg, rcount, alpha);
+  return launch_check("k_field_hbm");
 }
 
 template <int ST>
@@ -453,7 +518,7 @@ int sweeps_hbm_st(cosm_state *s, int64_t n_sweeps) {
       const int64_t tot = (int64_t)s->n * s->R;
       hipLaunchKernelGGL((k_full_gradient<ST>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
                          s->stream, s->d.phases, s->d.phases_alt, s->d.inc_off, s->d.inc_nbr,
-                         s->d.inc_J, s->n, s->R, alpha);
+                         s->d.inc_J, s->has_h ? s->d.h : nullptr, s->n, s->R, alpha);
       if (int rc = launch_check("k_full_gradient")) return rc;
       std::swap(s->d.phases, s->d.phases_alt);
     } else {
@@ -466,6 +531,8 @@ int sweeps_hbm_st(cosm_state *s, int64_t n_sweeps) {
                            rchunks, alpha);
         if (int rc = launch_check("k_class_hbm")) return rc;
       }
+      if (s->has_h)
+        if (int rc = field_hbm_st<ST>(s, alpha, 0, s->R)) return rc;
     }
     if (sc.dwt_period > 0 && t % sc.dwt_period == 0)
       if (int rc = dwt_hbm_st<ST>(s, t, 0, s->R)) return rc;
@@ -487,6 +554,8 @@ int sweeps_plain_st(cosm_state *s, int64_t n_sweeps) {
                            alpha);
         if (int rc = launch_check("k_class_plain")) return rc;
       }
+      if (s->has_h)
+        if (int rc = field_hbm_st<ST>(s, alpha, r, 1)) return rc;
       if (sc.dwt_period > 0 && t % sc.dwt_period == 0)
         if (int rc = dwt_hbm_st<ST>(s, t, r, 1)) return rc;
     }

@@ -28,6 +28,10 @@ WORKLOADS = {
                     [(512, 2000), (128, 20000)]),
     "maxcut-3reg-n2000": (lambda: ci.random_regular(2000, 3, seed=2, weights="maxcut1"),
                           dict(dwt_ratio=1.0, dwt_period=6), [(512, 10000), (64, 100000)]),
+    # G70-shaped stand-in for the ablation of Table VII: N = 10000, mean degree 2
+    # (m ~ 10000), degree cap 9, unweighted Max-Cut
+    "maxcut-er-n10000": (lambda: ci.erdos_renyi_capped(10000, 2.0, 9, seed=70, weights="maxcut1"),
+                         dict(dwt_ratio=1.0, dwt_period=6), [(256, 10000), (32, 100000)]),
 }
 
 
