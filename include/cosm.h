@@ -240,6 +240,21 @@ int cosm_get_phases(cosm_state *s, int32_t unit, double *out);
  * turn, rounded to the storage format) and set the sweep counter to t. */
 int cosm_set_phases(cosm_state *s, int32_t unit, const double *in, int64_t t);
 
+/* ---- QUBO inputs -------------------------------------------------------------- */
+/* Map the QUBO  min E(x) = sum_k qv[k] x_{qi[k]} x_{qj[k]},  x in {0,1}^n, to the
+ * Ising form of Eq. (1) with s = 2x - 1:  4 E(x) = H(s) + *offset_out, where
+ * J_uv = -(sum of qv over off-diagonal terms on {u, v}, either order),
+ * h_i = -(sum of qv over off-diagonal terms touching i) - 2 (sum of qv[k] with
+ * qi = qj = i).  Repeated terms add up; pairs whose J sums to 0 are dropped.
+ * Outputs (caller-owned): eu_out, ev_out, J_out with room for nnz edges,
+ * sorted by (u, v) with u < v, *m_out edges written; h_out[n]; *offset_out.
+ * Pass the result to cosm_init with h = h_out (a state with h reads out with
+ * the single semicircle; minimising H minimises E).  Host only.
+ * EINVAL (n < 1, NULL, index out of range), ERANGE (a sum overflows int32). */
+int cosm_qubo_to_ising(int32_t n, int64_t nnz, const int32_t *qi, const int32_t *qj,
+                       const int32_t *qv, int32_t *eu_out, int32_t *ev_out, int32_t *J_out,
+                       int64_t *m_out, int32_t *h_out, int64_t *offset_out);
+
 /* ---- introspection ---------------------------------------------------------- */
 typedef struct {
   int32_t n, num_colours, replicas;

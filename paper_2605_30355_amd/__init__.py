@@ -16,5 +16,5 @@ from .cosm import (  # noqa: F401
     UPDATE_FULL_GRADIENT, UPDATE_SCS,
     Batch, CosmError, Params, State, TTSResult,
     build_partitions, default_params, exported_symbols, lds_probe, library_path, load_library,
-    version,
+    qubo_to_ising, version,
 )

@@ -26,7 +26,7 @@ ABI_FUNCTIONS = (
     "cosm_default_params", "cosm_build_partitions", "cosm_workspace_bytes", "cosm_init",
     "cosm_destroy", "cosm_reset", "cosm_sweep", "cosm_energy", "cosm_solve_to_target",
     "cosm_get_phases", "cosm_set_phases", "cosm_get_info", "cosm_set_timing",
-    "cosm_last_error", "cosm_version", "cosm_lds_probe",
+    "cosm_last_error", "cosm_version", "cosm_lds_probe", "cosm_qubo_to_ising",
     "cosm_batch_create", "cosm_batch_destroy", "cosm_batch_add_graph", "cosm_batch_set_seed",
     "cosm_batch_run", "cosm_batch_wait", "cosm_batch_results",
 )
@@ -110,6 +110,8 @@ def load_library():
         "cosm_batch_results": (I32, [P, I32, P, P, P]),
         "cosm_version": (ctypes.c_char_p, []),
         "cosm_lds_probe": (I32, [I32, I32, P, ctypes.POINTER(ctypes.c_double)]),
+        "cosm_qubo_to_ising": (I32, [I32, I64, P, P, P, P, P, P, ctypes.POINTER(ctypes.c_int64), P,
+                                     ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -127,6 +129,25 @@ def exported_symbols():
 
 def version() -> str:
     return load_library().cosm_version().decode()
+
+
+def qubo_to_ising(n: int, qi, qj, qv):
+    """cosm_qubo_to_ising: returns (eu, ev, J, h, offset) with 4 E(x) = H(s) + offset."""
+    qi = np.ascontiguousarray(qi, dtype=np.int32)
+    qj = np.ascontiguousarray(qj, dtype=np.int32)
+    qv = np.ascontiguousarray(qv, dtype=np.int32)
+    nnz = len(qi)
+    eu = np.zeros(max(nnz, 1), np.int32)
+    ev = np.zeros(max(nnz, 1), np.int32)
+    J = np.zeros(max(nnz, 1), np.int32)
+    h = np.zeros(n, np.int32)
+    m = ctypes.c_int64(0)
+    off = ctypes.c_int64(0)
+    _check(load_library().cosm_qubo_to_ising(int(n), int(nnz), _ptr(qi), _ptr(qj), _ptr(qv),
+                                             _ptr(eu), _ptr(ev), _ptr(J), ctypes.byref(m),
+                                             _ptr(h), ctypes.byref(off)))
+    k = m.value
+    return eu[:k].copy(), ev[:k].copy(), J[:k].copy(), h, off.value
 
 
 def lds_probe(row_words: int = 2, blocks_per_cu: int = 2) -> float:

@@ -75,3 +75,28 @@ def test_fields_large_graph_sampled():
     colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [100, 100])
     p = cosm.Params(sweeps_per_trial=60, dwt_ratio=0.5, dwt_period=3)
     _compare(inst, h, colour, C, p, R=8, S=60, seed=14)
+
+
+def test_qubo_solved_on_gpu():
+    """A random 16-variable QUBO through cosm_qubo_to_ising and a GPU solve: the
+    best trial's x attains the enumerated minimum of E."""
+    import itertools
+    rng = np.random.default_rng(21)
+    n = 16
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < 0.25]
+    qi = np.array([p[0] for p in pairs] + list(range(n)), np.int32)
+    qj = np.array([p[1] for p in pairs] + list(range(n)), np.int32)
+    qv = rng.integers(-3, 4, len(qi)).astype(np.int32)
+    eu, ev, J, h, offset = cosm.qubo_to_ising(n, qi, qj, qv)
+    xs = np.array(list(itertools.product((0, 1), repeat=n)), np.int64)
+    E = (xs[:, qi] * xs[:, qj] * qv).sum(axis=1)
+    colour, C = cosm.build_partitions(n, eu, ev, cosm.COLOR_GREEDY)
+    p = cosm.Params(sweeps_per_trial=1000, dwt_ratio=1.5, dwt_period=3)
+    with cosm.State(n, eu, ev, J, colour, C, p, seed=3, replicas=256, h=h) as st:
+        st.sweep(1000)
+        H, _, spins = st.energy()
+    k = int(np.argmin(H))
+    x = (spins[k].astype(np.int64) + 1) // 2
+    e = int((x[qi] * x[qj] * qv).sum())
+    assert 4 * e == int(H[k]) + offset
+    assert e == int(E.min())

@@ -112,3 +112,39 @@ def test_fields_off_leave_dynamics_unchanged():
     oracle.sweeps(p0, P, 3, 0, a, 0, 100)
     oracle.sweeps(pz, P, 3, 0, b, 0, 100)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# QUBO -> Ising at the boundary (host code of the library; no GPU needed)
+# ---------------------------------------------------------------------------
+def _qubo_energy(x, qi, qj, qv):
+    return int(sum(int(v) * int(x[i]) * int(x[j]) for i, j, v in zip(qi, qj, qv)))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_qubo_mapping_by_enumeration(seed):
+    """4 E(x) = H(s) + offset for every x in {0,1}^n (n = 10), with repeated,
+    reversed and diagonal terms; H from the oracle's energy of Eq. (1)."""
+    import paper_2605_30355_amd as cosm
+    rng = np.random.default_rng(seed)
+    n, nnz = 10, 40
+    qi = rng.integers(0, n, nnz).astype(np.int32)
+    qj = rng.integers(0, n, nnz).astype(np.int32)
+    qj[:6] = qi[:6]  # diagonal terms
+    qv = rng.integers(-5, 6, nnz).astype(np.int32)
+    eu, ev, J, h, offset = cosm.qubo_to_ising(n, qi, qj, qv)
+    assert np.all(eu < ev)
+    prob = oracle.Problem(n, eu, ev, J, h=h)
+    xs = np.array(list(itertools.product((0, 1), repeat=n)), np.int8)
+    H, _ = oracle.energy(prob, (2 * xs - 1).astype(np.int8))
+    E = np.array([_qubo_energy(x, qi, qj, qv) for x in xs])
+    assert np.array_equal(4 * E, H + offset)
+
+
+def test_qubo_mapping_errors():
+    import paper_2605_30355_amd as cosm
+    from paper_2605_30355_amd.cosm import CosmError
+    with pytest.raises(CosmError):
+        cosm.qubo_to_ising(3, [0], [3], [1])
+    eu, ev, J, h, off = cosm.qubo_to_ising(3, [0, 1], [1, 0], [2, -2])  # cancels
+    assert len(J) == 0 and off == 0 and np.array_equal(h, [0, 0, 0])
