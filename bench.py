@@ -402,10 +402,11 @@ def main():
     target = load_target()
     if not args.no_ttt and target is not None:
         ttt = {"target_H": target, "target_cut": (int(-inst.J.sum()) - target) // 2}
-        for name, store in (("batched_fp32", cosm.STORE_FP32), ("batched_fp16", cosm.STORE_FP16),
-                            ("batched_bf16", cosm.STORE_BF16)):
-            s2 = st if store == cosm.STORE_FP32 else cosm.State(
-                inst.n, inst.eu, inst.ev, inst.J, colour, C, params(cosm, storage=store), seed=1,
+        for name, over in (("batched_fp32", {}), ("batched_fp16", {"storage": cosm.STORE_FP16}),
+                           ("batched_bf16", {"storage": cosm.STORE_BF16}),
+                           ("batched_fp32_optimal_readout", {"readout": cosm.READOUT_OPTIMAL})):
+            s2 = st if not over else cosm.State(
+                inst.n, inst.eu, inst.ev, inst.J, colour, C, params(cosm, **over), seed=1,
                 replicas=R)
             res, _ = s2.solve_to_target(target, 8 * R)
             ttt[name] = {"ps": res.ps, "ps_ci95": [res.ps_lo, res.ps_hi], "trials": res.trials,

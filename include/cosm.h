@@ -70,7 +70,11 @@ enum { COSM_SCHED_GRID = 0, COSM_SCHED_CONTINUOUS = 1 };
 enum { COSM_UPDATE_SCS = 0, COSM_UPDATE_FULL_GRADIENT = 1 };
 /* Readout rule (Algorithm 1, binarization).  BISECTORS: B equally spaced
  * bisectors.  OPTIMAL: the best of all distinct bisectors (every position where
- * some spin changes side), the alternative the paper cites from Burer et al. */
+ * some spin changes side), the alternative the paper cites from Burer et al.:
+ * lowest H, smallest angle on ties; per replica a segmented sort of the n
+ * values x_i mod 180 and an O(n + m) difference array.  OPTIMAL needs h = NULL,
+ * n <= 32768 and n * replicas < 2^31 (EINVAL / ERANGE at cosm_init); its
+ * device workspace grows by about 16 n R bytes. */
 enum { COSM_READOUT_BISECTORS = 0, COSM_READOUT_OPTIMAL = 1 };
 enum { COSM_UNIT_TURNS = 0, COSM_UNIT_DEGREES = 1, COSM_UNIT_RADIANS = 2 };
 

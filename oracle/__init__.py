@@ -88,6 +88,8 @@ def lib():
         L.orc_energy.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32, P, P, P]
         L.orc_readout.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Params),
                                   ctypes.c_int32, P, P, P, P, P]
+        L.orc_readout_optimal.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32, P, P, P, P, P]
+        L.orc_readout_optimal.restype = ctypes.c_int32
         L.orc_brute_force_ground_state.argtypes = [ctypes.POINTER(_Problem), P, P]
         L.orc_brute_force_ground_state.restype = ctypes.c_int32
         L.orc_r99.argtypes = [ctypes.c_double]
@@ -227,6 +229,21 @@ def readout(problem: Problem, params: Params, x):
     lib().orc_readout(problem.struct(), params.struct(), R, _ptr(x), _ptr(spins), _ptr(H),
                       _ptr(cut), _ptr(bp))
     return spins, H, cut, bp
+
+
+def readout_optimal(problem: Problem, x):
+    """Optimal-bisector binarization of x ([R][n], degrees).
+    Returns (spins, H, cut, beta_deg)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    R = x.shape[0]
+    spins = np.zeros((R, problem.n), dtype=np.int8)
+    H = np.zeros(R, dtype=np.int64)
+    cut = np.zeros(R, dtype=np.int64)
+    beta = np.zeros(R, dtype=np.float64)
+    if lib().orc_readout_optimal(problem.struct(), R, _ptr(x), _ptr(spins), _ptr(H), _ptr(cut),
+                                 _ptr(beta)) != 0:
+        raise ValueError("the optimal bisector needs h = 0")
+    return spins, H, cut, beta
 
 
 def brute_force_ground_state(problem: Problem):

@@ -403,6 +403,53 @@ void orc_readout(const orc_problem *pb, const orc_params *p, int32_t R, const do
 }
 
 /* ------------------------------------------------------------------------ */
+/* Optimal bisector (the exact best line through the origin, as in the         */
+/* Burer-Monteiro-Zhang rank-2 rounding the paper cites for its binarization): */
+/* the spins are constant while the bisector angle beta stays between two      */
+/* consecutive values of x_i mod 180, so every distinct value b of x_i mod 180 */
+/* is tried as beta (+1 on [b, b + 180)), by brute force; the lowest H wins,   */
+/* the smallest b on ties.  h must be NULL (with fields the semicircle is      */
+/* fixed).  beta_out[R] (may be NULL) receives the chosen angle, degrees.      */
+/* ------------------------------------------------------------------------ */
+int32_t orc_readout_optimal(const orc_problem *pb, int32_t R, const double *x, int8_t *spins,
+                            int64_t *H, int64_t *cut, double *beta_out) {
+  if (pb->h != NULL) return -1;
+  const int32_t n = pb->n;
+  int8_t *cand = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
+  int8_t *best = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
+  for (int32_t r = 0; r < R; r++) {
+    const double *xr = x + (size_t)r * n;
+    int64_t bestH = 0, bestCut = 0;
+    double bestB = 0.0;
+    int found = 0;
+    for (int32_t a = 0; a < n; a++) {
+      const double b = mod_pos(xr[a], 180.0);
+      for (int32_t i = 0; i < n; i++) cand[i] = mod_pos(xr[i] - b, 360.0) < 180.0 ? 1 : -1;
+      int64_t e, c;
+      energy_one(pb, cand, &e, &c);
+      if (!found || e < bestH || (e == bestH && b < bestB)) {
+        found = 1;
+        bestH = e;
+        bestCut = c;
+        bestB = b;
+        memcpy(best, cand, (size_t)n);
+      }
+    }
+    if (!found) { /* n = 0 cannot happen (n >= 1) */
+      bestH = 0;
+      bestCut = 0;
+    }
+    H[r] = bestH;
+    cut[r] = bestCut;
+    if (beta_out) beta_out[r] = bestB;
+    if (spins) memcpy(spins + (size_t)r * n, best, (size_t)n);
+  }
+  free(cand);
+  free(best);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exhaustive ground state (pins only).                                       */
 /* ------------------------------------------------------------------------ */
 int32_t orc_brute_force_ground_state(const orc_problem *pb, int8_t *best_spins, int64_t *H) {

@@ -114,6 +114,13 @@ void orc_energy(const orc_problem *pb, int32_t R, const int8_t *spins, int64_t *
 void orc_readout(const orc_problem *pb, const orc_params *p, int32_t R, const double *x,
                  int8_t *spins, int64_t *H, int64_t *cut, int32_t *best_p);
 
+/* Optimal-bisector binarization: every distinct x_i mod 180 tried as the
+ * bisector by brute force, lowest H kept, smallest angle on ties; h must be
+ * NULL.  spins [R][n] (may be NULL), H [R], cut [R], beta_out [R] (may be
+ * NULL, degrees).  Returns 0, or -1 with bias fields. */
+int32_t orc_readout_optimal(const orc_problem *pb, int32_t R, const double *x, int8_t *spins,
+                            int64_t *H, int64_t *cut, double *beta_out);
+
 /* Exhaustive ground state for n <= 26.  Returns 0 or -1 if n is too large. */
 int32_t orc_brute_force_ground_state(const orc_problem *pb, int8_t *best_spins, int64_t *H);
 

@@ -30,7 +30,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Byte offsets of every device buffer inside one allocation.
 struct MemPlan {
   size_t phases, desc, class_off, slot_vertex, h_slot, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
-      inc_off, inc_nbr, inc_J, phases_alt, total;
+      inc_off, inc_nbr, inc_J, phases_alt, opt_keys, opt_keys2, opt_vals, opt_vals2, opt_off,
+      opt_temp, opt_temp_bytes, total;
 };
 
 MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_params &p) {
@@ -64,6 +65,14 @@ MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_param
   mp.inc_nbr = take(fg ? (size_t)(2 * m) * 4 : 0);
   mp.inc_J = take(fg ? (size_t)(2 * m) * 4 : 0);
   mp.phases_alt = take(fg ? nr * storage_bytes(p.storage) : 0);
+  const bool opt = p.readout == COSM_READOUT_OPTIMAL;
+  mp.opt_keys = take(opt ? nr * 4 : 0);
+  mp.opt_keys2 = take(opt ? nr * 4 : 0);
+  mp.opt_vals = take(opt ? nr * 4 : 0);
+  mp.opt_vals2 = take(opt ? nr * 4 : 0);
+  mp.opt_off = take(opt ? ((size_t)R + 1) * 4 : 0);
+  mp.opt_temp_bytes = opt ? opt_readout_temp_bytes(n, R) : 0;
+  mp.opt_temp = take(mp.opt_temp_bytes);
   mp.total = off;
   return mp;
 }
@@ -296,8 +305,15 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   if (h != nullptr && p->n_bisectors != 1) {
     // with bias fields the binarization uses fixed semicircles (B forced to 1)
   }
-  if (p->readout == COSM_READOUT_OPTIMAL)
-    return set_error(COSM_EINVAL, "the optimal-bisector readout is not available in this build");
+  if (p->readout == COSM_READOUT_OPTIMAL) {
+    if (h != nullptr)
+      return set_error(COSM_EINVAL, "the optimal-bisector readout needs h = NULL (with bias "
+                                    "fields the semicircle is fixed)");
+    if (n > kOptReadoutMaxN)
+      return set_error(COSM_ERANGE, "the optimal-bisector readout supports n <= 32768");
+    if ((int64_t)n * replicas >= ((int64_t)1 << 31))
+      return set_error(COSM_ERANGE, "the optimal-bisector readout needs n * replicas < 2^31");
+  }
 
   int32_t max_abs_J = 0;
   int64_t sum_abs = 0;
@@ -335,6 +351,8 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   s->h_eu.assign(eu, eu + m);
   s->h_ev.assign(ev, ev + m);
   s->h_J.assign(J, J + m);
+  s->sumJ = 0;
+  for (int64_t k = 0; k < m; k++) s->sumJ += J[k];
   if (h) s->h_h.assign(h, h + n);
   s->h_colour.assign(colour, colour + m);
 
@@ -433,6 +451,13 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   d.inc_nbr = at<uint32_t>(s->base, mp.inc_nbr);
   d.inc_J = at<float>(s->base, mp.inc_J);
   d.phases_alt = at<void>(s->base, mp.phases_alt);
+  d.opt_keys = at<uint32_t>(s->base, mp.opt_keys);
+  d.opt_keys2 = at<uint32_t>(s->base, mp.opt_keys2);
+  d.opt_vals = at<uint32_t>(s->base, mp.opt_vals);
+  d.opt_vals2 = at<uint32_t>(s->base, mp.opt_vals2);
+  d.opt_off = at<int32_t>(s->base, mp.opt_off);
+  d.opt_temp = at<void>(s->base, mp.opt_temp);
+  s->opt_temp_bytes = mp.opt_temp_bytes;
 
   auto up = [&](void *dst, const void *src, size_t bytes) -> int {
     if (bytes == 0) return COSM_OK;

@@ -114,6 +114,11 @@ struct DeviceBuffers {
   uint32_t *inc_nbr = nullptr;  // [2m] neighbour | (1u << 31 when the vertex is the edge's u)
   float *inc_J = nullptr;       // [2m]
   void *phases_alt = nullptr;   // [n][R]
+  // optimal-bisector readout: sort keys and values [R][n] (twice), segment
+  // offsets [R + 1], the sort's temporary storage
+  uint32_t *opt_keys = nullptr, *opt_keys2 = nullptr, *opt_vals = nullptr, *opt_vals2 = nullptr;
+  int32_t *opt_off = nullptr;
+  void *opt_temp = nullptr;
 };
 
 struct KernelShape {
@@ -146,7 +151,8 @@ struct cosm_state {
   cosm::LdsSchedule lds;  // resolved lane schedule of the LDS form
   std::vector<int32_t> lds_widths;  // row widths (words) that fit, for the autotuner
   bool has_h = false;
-  int64_t sumJ = 0;
+  int64_t sumJ = 0;                 // sum of J over the edges
+  size_t opt_temp_bytes = 0;        // segmented sort workspace (optimal readout)
   std::vector<int32_t> h_eu, h_ev, h_J, h_h, h_colour;
   std::vector<int32_t> h_slot;       // h of the vertex in each LDS slot (host copy)
   std::vector<int32_t> class_sizes;  // edges per class
@@ -163,6 +169,10 @@ namespace cosm {
 int launch_init(cosm_state *s);
 int launch_sweeps(cosm_state *s, int64_t n_sweeps);
 int launch_readout(cosm_state *s);
+// Optimal-bisector readout (readout_opt.hip); h must be absent.
+int launch_readout_optimal(cosm_state *s);
+size_t opt_readout_temp_bytes(int32_t n, int32_t R);
+constexpr int32_t kOptReadoutMaxN = 32768;  // difference array of n + 1 ints in LDS
 int launch_energy(cosm_state *s);  // spins already in s->d.spins
 // Convert between the storage format and FP32 turns in [0, 1), both [n][R].
 int launch_to_turns(cosm_state *s, float *turns_dev);

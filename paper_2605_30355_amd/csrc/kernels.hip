@@ -656,7 +656,10 @@ int launch_to_turns(cosm_state *s, float *out) {
 int launch_from_turns(cosm_state *s, const float *in) {
   return dispatch_storage<FromTurnsFn>(s->p.storage, s, in);
 }
-int launch_readout(cosm_state *s) { return dispatch_storage<ReadoutFn>(s->p.storage, s); }
+int launch_readout(cosm_state *s) {
+  if (s->p.readout == COSM_READOUT_OPTIMAL) return launch_readout_optimal(s);
+  return dispatch_storage<ReadoutFn>(s->p.storage, s);
+}
 
 int launch_sweeps(cosm_state *s, int64_t n_sweeps) {
   if (s->timing) COSM_HIP_CHECK(hipEventRecord(s->ev0, s->stream));
