@@ -204,6 +204,122 @@ def ablation_bench():
     return out
 
 
+SCALING = dict(sizes=(12, 14, 16, 18, 20), seeds=(1, 2, 3, 4, 5), trials=4096,
+               sweep_options=(25, 50, 100, 200, 400, 800, 1600), single_trials=200,
+               alpha0_deg=25.0, dwt_ratio=1.0, dwt_period=3)
+
+
+def fit_log_tts(L, tts):
+    """Least-squares fit of log10 TTS = a + b L (the fit used for the
+    tile-planted scaling, Appendix C).  Returns a, b, R^2 and the 95 %
+    t-interval of b."""
+    import numpy as np
+    from scipy import stats
+    L = np.asarray(L, dtype=np.float64)
+    y = np.log10(np.asarray(tts, dtype=np.float64))
+    n = len(L)
+    Lm, ym = L.mean(), y.mean()
+    sxx = ((L - Lm) ** 2).sum()
+    b = ((L - Lm) * (y - ym)).sum() / sxx
+    a = ym - b * Lm
+    res = y - (a + b * L)
+    ss_res, ss_tot = (res ** 2).sum(), ((y - ym) ** 2).sum()
+    r2 = 1.0 - ss_res / ss_tot
+    se = math.sqrt(ss_res / (n - 2) / sxx)
+    t = stats.t.ppf(0.975, n - 2)
+    return {"a": a, "b": b, "r_squared": r2, "b_ci95": [b - t * se, b + t * se]}
+
+
+def scaling_bench():
+    """TTS scaling on +-1/+-2 tori (the shape of the tile-planted set; random,
+    not planted), L in {12, ..., 20}, five instances per size, Appendix C's
+    parameters.  Per instance: P_s of 4096 batched trials at each sweep budget,
+    the budget with the fewest sweeps-to-solution kept (the paper tuned its
+    sweeps the same way), then t_trial measured two ways: batched (device time
+    of 4096 parallel trials / 4096) and single-replica latency (one trial at a
+    time, init + sweeps + readout, averaged over sequential trials).  TTS =
+    t_trial x R99; the median over instances per size is fitted to
+    log10 TTS = a + b L."""
+    import numpy as np
+    import torch
+
+    import cosm_inputs as ci
+    import paper_2605_30355_amd as cosm
+
+    torch.cuda.set_device(0)
+    with open(os.path.join(ROOT, "tests", "golden", "targets.json")) as f:
+        targets = json.load(f)
+    cfg = SCALING
+    stream = torch.cuda.current_stream()
+
+    def params(S, R_form=None):
+        return cosm.Params(alpha0_deg=cfg["alpha0_deg"], dwt_ratio=cfg["dwt_ratio"],
+                           dwt_period=cfg["dwt_period"], sweeps_per_trial=S)
+
+    def timed_batch(st, S, rid0):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st.reset(7, rid0)
+        st.sweep(S)
+        H, _, _ = st.energy(return_spins=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return H.copy(), e0.elapsed_time(e1) * 1e-3
+
+    out = {"metric": "TTS scaling on +-1/+-2 tori: median TTS vs L, fit log10 TTS = a + b L",
+           "parameters": {k: v for k, v in cfg.items() if k != "sizes"}, "sizes": {}}
+    med_b, med_s = [], []
+    for L in cfg["sizes"]:
+        per = []
+        for sd in cfg["seeds"]:
+            inst = ci.torus(L, seed=1000 * L + sd, weights="pm12")
+            colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [L, L])
+            target = targets[f"torus-pm12-L{L}-s{sd}"]["target_H"]
+            R = cfg["trials"]
+            best = None
+            for S in cfg["sweep_options"]:
+                with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, params(S), seed=7,
+                                replicas=R) as st:
+                    H, secs = timed_batch(st, S, 0)
+                ps = float((H <= target).mean())
+                if ps <= 0.0:
+                    continue
+                r99 = 1.0 if ps >= 1.0 else math.log(0.01) / math.log(1.0 - ps)
+                if best is None or S * r99 < best["sts"]:
+                    best = {"sweeps": S, "ps": ps, "r99": r99, "sts": S * r99,
+                            "t_trial_batched_s": secs / R}
+            if best is None:
+                per.append({"seed": sd, "reached": False})
+                continue
+            S = best["sweeps"]
+            # single-replica latency: one trial at a time on its own state
+            with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, params(S), seed=7,
+                            replicas=1) as s1:
+                timed_batch(s1, S, 0)
+                tot = 0.0
+                for k in range(cfg["single_trials"]):
+                    _, secs = timed_batch(s1, S, k + 1)
+                    tot += secs
+            best["t_trial_single_s"] = tot / cfg["single_trials"]
+            best["tts_batched_s"] = best["t_trial_batched_s"] * best["r99"]
+            best["tts_single_s"] = best["t_trial_single_s"] * best["r99"]
+            best.update({"seed": sd, "target_H": target, "reached": True})
+            per.append(best)
+            log(f"scaling L={L} seed={sd}: {best}")
+        ok = [p for p in per if p["reached"]]
+        rec = {"instances": per,
+               "median_tts_batched_s": float(np.median([p["tts_batched_s"] for p in ok])) if ok else None,
+               "median_tts_single_s": float(np.median([p["tts_single_s"] for p in ok])) if ok else None}
+        out["sizes"][str(L)] = rec
+        med_b.append(rec["median_tts_batched_s"])
+        med_s.append(rec["median_tts_single_s"])
+    Ls = list(cfg["sizes"])
+    if all(v is not None for v in med_b):
+        out["fit_batched"] = fit_log_tts(Ls, med_b)
+        out["fit_single_replica"] = fit_log_tts(Ls, med_s)
+    return out
+
+
 def stream_bench():
     """Mixed request stream: 256 solve requests (N uniform in [400, 20000]; torus,
     3-regular Max-Cut and 5-regular +-1 graphs), each a whole trial of 256
@@ -296,6 +412,8 @@ def main():
                     help="measure the mixed request stream instead (prints its own JSON line)")
     ap.add_argument("--ablation", action="store_true",
                     help="run the Table VII ablation instead (prints its own JSON line)")
+    ap.add_argument("--scaling", action="store_true",
+                    help="run the TTS scaling study on +-1/+-2 tori instead (own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's replicas are independent, so several "
@@ -307,6 +425,9 @@ def main():
         return
     if args.ablation:
         print(json.dumps(ablation_bench()), flush=True)
+        return
+    if args.scaling:
+        print(json.dumps(scaling_bench()), flush=True)
         return
 
     import numpy as np

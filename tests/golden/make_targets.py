@@ -33,6 +33,14 @@ WORKLOADS = {
     "maxcut-er-n10000": (lambda: ci.erdos_renyi_capped(10000, 2.0, 9, seed=70, weights="maxcut1"),
                          dict(dwt_ratio=1.0, dwt_period=6), [(256, 10000), (32, 100000)]),
 }
+# +-1/+-2 tori for the TTS scaling study (the shape of the tile-planted set:
+# L x L, periodic, weights in {+-1, +-2}; random, not planted); Appendix C's
+# parameters alpha0 = 25, ratio 1.0, period 3
+for _L in (12, 14, 16, 18, 20):
+    for _s in range(1, 6):
+        WORKLOADS[f"torus-pm12-L{_L}-s{_s}"] = (
+            (lambda L=_L, sd=_s: ci.torus(L, seed=1000 * L + sd, weights="pm12")),
+            dict(alpha0_deg=25.0, dwt_ratio=1.0, dwt_period=3), [(512, 2000), (128, 10000)])
 
 
 def run(name):

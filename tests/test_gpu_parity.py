@@ -267,3 +267,12 @@ def test_continuous_first_sweeps_within_tolerance(inst):
     say(f"continuous: {clean.sum()} of {R} replicas clear of ties; max err {err[clean].max():.2e} rad")
     assert clean.sum() >= R // 2
     assert np.all(err[clean] <= 1e-4)
+
+
+def test_pm12_torus_alpha25():
+    """+-1/+-2 torus (the scaling study's instances) with Appendix C's
+    parameters: alpha0 = 25 degrees, ratio 1, period 3; |alpha J| up to 50."""
+    inst = ci.torus(16, seed=16001, weights="pm12")
+    colour, C, prob = make(inst, cosm.COLOR_TORUS, [16, 16])
+    p = cosm.Params(alpha0_deg=25.0, sweeps_per_trial=800, dwt_ratio=1.0, dwt_period=3)
+    check_trial(inst, colour, C, prob, p, seed=31, R=96, sweeps=800)

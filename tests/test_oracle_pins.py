@@ -463,3 +463,16 @@ def test_readout_lowest_index_on_ties():
     x = np.full((1, inst.n), 100.0)  # every bisector before 100 and after 100-180 ties
     _, H, _, bp = oracle.readout(prob, oracle.Params(), x)
     assert H[0] == -inst.m and bp[0] == 0
+
+
+def test_tts_scaling_fit_reproduces_appendix_c(golden_dir):
+    """The fit of log10 TTS = a + b L used by bench.py's scaling study, on the
+    median TTS values Appendix C prints for L = 12..20, gives the printed
+    slope 0.139, R^2 0.981 and 95 % interval 0.104-0.175."""
+    import bench
+    ref = load(golden_dir, "paper_printed_values.json")["tts_scaling_appendix_C"]
+    fit = bench.fit_log_tts(ref["L"], ref["tts_ms"])
+    assert abs(fit["b"] - ref["slope_b"]) < 5e-4
+    assert abs(fit["r_squared"] - ref["r_squared"]) < 5e-4
+    assert abs(fit["b_ci95"][0] - ref["slope_ci95"][0]) < 1.5e-3
+    assert abs(fit["b_ci95"][1] - ref["slope_ci95"][1]) < 1.5e-3
