@@ -525,14 +525,20 @@ def main():
         ttt = {"target_H": target, "target_cut": (int(-inst.J.sum()) - target) // 2}
         for name, over in (("batched_fp32", {}), ("batched_fp16", {"storage": cosm.STORE_FP16}),
                            ("batched_bf16", {"storage": cosm.STORE_BF16}),
-                           ("batched_fp32_optimal_readout", {"readout": cosm.READOUT_OPTIMAL})):
-            s2 = st if not over else cosm.State(
-                inst.n, inst.eu, inst.ev, inst.J, colour, C, params(cosm, **over), seed=1,
+                           ("batched_fp32_optimal_readout", {"readout": cosm.READOUT_OPTIMAL}),
+                           ("batched_fp32_minimum_colouring", {"colouring": cosm.COLOR_MINIMUM})):
+            col2, C2 = colour, C
+            if "colouring" in over:  # 3 classes of 1000 instead of 4 of 750
+                col2, C2 = cosm.build_partitions(inst.n, inst.eu, inst.ev, over.pop("colouring"))
+            s2 = st if not over and col2 is colour else cosm.State(
+                inst.n, inst.eu, inst.ev, inst.J, col2, C2, params(cosm, **over), seed=1,
                 replicas=R)
             res, _ = s2.solve_to_target(target, 8 * R)
             ttt[name] = {"ps": res.ps, "ps_ci95": [res.ps_lo, res.ps_hi], "trials": res.trials,
                          "r99": res.r99, "t_trial_s": res.t_trial_s, "ttt_s": res.ttt_s,
                          "best_H": res.best_H}
+            if col2 is not colour:
+                ttt[name]["classes"] = C2
             if s2 is not st:
                 s2.close()
             log(f"{name}: {ttt[name]}")

@@ -55,7 +55,7 @@ enum {
 
 /* ---- enumerations ---------------------------------------------------------- */
 enum { COSM_COLOR_GREEDY = 0, COSM_COLOR_MISRA_GRIES = 1, COSM_COLOR_TORUS = 2,
-       COSM_COLOR_BALANCED = 3 };
+       COSM_COLOR_BALANCED = 3, COSM_COLOR_MINIMUM = 4 };
 enum { COSM_STORE_FP32 = 0, COSM_STORE_FP16 = 1, COSM_STORE_BF16 = 2 };
 /* Where a replica's phases live during a sweep.  LDS: a workgroup holds whole
  * replicas in LDS for all sweeps of a call.  HBM: phases stay in device memory,
@@ -116,6 +116,11 @@ typedef struct cosm_state cosm_state;
  *     smallest <= 1 where Kempe swaps allow) by recolouring alternating
  *     two-colour paths; same number of colours.  Appendix B notes that
  *     colourings which balance the edges per colour are admissible.
+ *   method MINIMUM: Misra-Gries, then the edges of colour Delta moved into
+ *     Delta colours by alternating-path swaps when that succeeds (a minimum
+ *     colouring, as the paper's greedy heuristic reached on its non-lattice
+ *     graphs, Sec. III-B); Delta + 1 colours otherwise (class-2 graphs); then
+ *     equalised as BALANCED.  Deterministic for a given input.
  * colour_out[m] (caller-owned) receives the class of every edge; class indices
  * are also the order in which a sweep applies them.  *num_colours_out = C.
  * Errors: EINVAL (NULL, n < 1, endpoint out of range, self-loop, TORUS edge that

@@ -264,6 +264,10 @@ int cosm_build_partitions(int32_t n, int64_t m, const int32_t *eu, const int32_t
       C = colour_misra_gries(n, m, eu, ev, colour_out);
       equalise_classes(n, m, eu, ev, C, colour_out);
       break;
+    case COSM_COLOR_MINIMUM:
+      C = colour_minimum(n, m, eu, ev, colour_out);
+      equalise_classes(n, m, eu, ev, C, colour_out);
+      break;
     case COSM_COLOR_TORUS:
       if (method_args == nullptr) return set_error(COSM_EINVAL, "TORUS needs {Lx, Ly}");
       C = colour_torus(n, m, eu, ev, method_args[0], method_args[1], colour_out);

@@ -2,6 +2,7 @@
 // cosm_build_partitions (Sec. II-B: "a proper edge coloring of the input
 // graph"; classes are the matchings E_1..E_C of Eqs. (9)-(11)).
 #include <algorithm>
+#include <random>
 #include <cstdio>
 #include <numeric>
 
@@ -316,6 +317,112 @@ int32_t colour_torus(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
   for (int c = 0; c < 6; c++) remap[c] = used[c] ? C++ : -1;
   for (int64_t k = 0; k < m; k++) colour[k] = remap[colour[k]];
   return C;
+}
+
+// Delta-edge-colouring attempt ("minimum colouring", which the paper reports
+// its greedy heuristic reached on its non-lattice graphs).  Start from
+// Misra-Gries (<= Delta + 1 colours).  If it used colour Delta, move each edge
+// e = (u, v) of that colour into [0, Delta): with a free at u and b free at v,
+// either one colour is free at both, or swapping the (a, b)-alternating path
+// that starts at v (v lacks b, so the path ends there) frees a at v while a
+// stays free at u -- unless the path ends at u.  Edges left over after a pass
+// wait for the next one, after a random Kempe-chain swap elsewhere changes the
+// colouring.  Gives up after a fixed number of passes and then keeps
+// Delta + 1 colours (graphs of class 2, such as the Petersen graph, need them).
+// Returns the number of colours.
+int32_t colour_minimum(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                       int32_t *colour) {
+  int32_t C = colour_misra_gries(n, m, eu, ev, colour);
+  if (m == 0) return C;
+  std::vector<int32_t> deg((size_t)n, 0);
+  for (int64_t k = 0; k < m; k++) {
+    deg[(size_t)eu[k]]++;
+    deg[(size_t)ev[k]]++;
+  }
+  const int32_t delta = *std::max_element(deg.begin(), deg.end());
+  if (C <= delta) return C;
+  const int32_t K = delta + 1;
+  std::vector<int64_t> at((size_t)n * K, -1);
+  for (int64_t k = 0; k < m; k++) {
+    at[(size_t)eu[k] * K + colour[k]] = k;
+    at[(size_t)ev[k] * K + colour[k]] = k;
+  }
+  auto other = [&](int64_t e, int32_t v) { return eu[e] == v ? ev[e] : eu[e]; };
+  auto set_colour = [&](int64_t e, int32_t c) {
+    at[(size_t)eu[e] * K + colour[e]] = -1;
+    at[(size_t)ev[e] * K + colour[e]] = -1;
+    colour[e] = c;
+    at[(size_t)eu[e] * K + c] = e;
+    at[(size_t)ev[e] * K + c] = e;
+  };
+  // the maximal (a, b)-alternating path from v, which must lack b
+  std::vector<int64_t> path;
+  auto chain_from = [&](int32_t v, int32_t a, int32_t b) {
+    path.clear();
+    int32_t want = a;
+    while (true) {
+      const int64_t e = at[(size_t)v * K + want];
+      if (e < 0) break;
+      path.push_back(e);
+      v = other(e, v);
+      want = want == a ? b : a;
+    }
+    return v;  // the other end
+  };
+  auto swap_path = [&](int32_t a, int32_t b) {
+    for (int64_t e : path) {
+      at[(size_t)eu[e] * K + colour[e]] = -1;
+      at[(size_t)ev[e] * K + colour[e]] = -1;
+    }
+    for (int64_t e : path) {
+      colour[e] = colour[e] == a ? b : a;
+      at[(size_t)eu[e] * K + colour[e]] = e;
+      at[(size_t)ev[e] * K + colour[e]] = e;
+    }
+  };
+  std::vector<int64_t> extra;
+  for (int64_t k = 0; k < m; k++)
+    if (colour[k] == delta) extra.push_back(k);
+  std::mt19937_64 rng(0x5eed5eedull);
+  for (int pass = 0; pass < 400 && !extra.empty(); pass++) {
+    std::vector<int64_t> left;
+    for (int64_t e : extra) {
+      const int32_t u = eu[e], v = ev[e];
+      bool done = false;
+      for (int32_t a = 0; a < delta && !done; a++) {
+        if (at[(size_t)u * K + a] >= 0) continue;
+        if (at[(size_t)v * K + a] < 0) {
+          set_colour(e, a);
+          done = true;
+          break;
+        }
+        for (int32_t b = 0; b < delta && !done; b++) {
+          if (b == a || at[(size_t)v * K + b] >= 0) continue;
+          if (chain_from(v, a, b) == u) continue;
+          bool touches_u = false;
+          for (int64_t f : path) touches_u |= (eu[f] == u || ev[f] == u);
+          if (touches_u) continue;
+          swap_path(a, b);
+          set_colour(e, a);
+          done = true;
+        }
+      }
+      if (!done) left.push_back(e);
+    }
+    extra.swap(left);
+    if (extra.empty()) break;
+    // perturb: swap a random Kempe chain that starts at a chain end
+    for (int tries = 0; tries < 64; tries++) {
+      const int32_t x = (int32_t)(rng() % (uint64_t)n);
+      const int32_t a = (int32_t)(rng() % (uint64_t)delta), b = (int32_t)(rng() % (uint64_t)delta);
+      if (a == b || at[(size_t)x * K + a] < 0 || at[(size_t)x * K + b] >= 0) continue;
+      chain_from(x, a, b);
+      swap_path(a, b);
+      break;
+    }
+  }
+  if (!extra.empty()) return C;
+  return delta;
 }
 
 }  // namespace cosm

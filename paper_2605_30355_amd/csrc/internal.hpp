@@ -38,6 +38,9 @@ int32_t colour_misra_gries(int32_t n, int64_t m, const int32_t *eu, const int32_
                            int32_t *colour);
 void equalise_classes(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, int32_t C,
                       int32_t *colour);
+// Misra-Gries, then Kempe-chain moves towards Delta colours; returns C.
+int32_t colour_minimum(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                       int32_t *colour);
 // Returns C, or a negative status for a non-lattice edge.
 int32_t colour_torus(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev, int32_t Lx,
                      int32_t Ly, int32_t *colour);

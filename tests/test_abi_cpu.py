@@ -117,3 +117,20 @@ def test_bad_graphs_rejected(eu, ev, status):
 def test_empty_graph():
     colour, C = cosm.build_partitions(5, [], [], cosm.COLOR_GREEDY)
     assert C == 0 and len(colour) == 0
+
+
+def test_minimum_colouring():
+    """MINIMUM: Delta colours on random 3- and 5-regular graphs (class 1),
+    Delta + 1 on the Petersen graph (class 2); always proper and equalised."""
+    import cosm_inputs as ci
+    for g, delta in ((ci.random_regular(400, 3, seed=3), 3), (ci.random_regular(300, 5, seed=4), 5)):
+        c, C = cosm.build_partitions(g.n, g.eu, g.ev, cosm.COLOR_MINIMUM)
+        assert C == delta and oracle.is_proper_colouring(g.n, g.eu, g.ev, c, C)
+        sizes = np.bincount(c, minlength=C)
+        assert sizes.max() - sizes.min() <= 1
+    outer = [(i, (i + 1) % 5) for i in range(5)]
+    spokes = [(i, i + 5) for i in range(5)]
+    inner = [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
+    E = np.array(outer + spokes + inner, np.int32)
+    c, C = cosm.build_partitions(10, E[:, 0], E[:, 1], cosm.COLOR_MINIMUM)
+    assert C == 4 and oracle.is_proper_colouring(10, E[:, 0], E[:, 1], c, C)
