@@ -204,7 +204,7 @@ def ablation_bench():
     return out
 
 
-SCALING = dict(sizes=(12, 14, 16, 18, 20), seeds=(1, 2, 3, 4, 5), trials=4096,
+SCALING = dict(sizes=(12, 14, 16, 18, 20), seeds=tuple(range(1, 16)), trials=4096,
                sweep_options=(25, 50, 100, 200, 400, 800, 1600), single_trials=200,
                alpha0_deg=25.0, dwt_ratio=1.0, dwt_period=3)
 
@@ -232,7 +232,7 @@ def fit_log_tts(L, tts):
 
 def scaling_bench():
     """TTS scaling on +-1/+-2 tori (the shape of the tile-planted set; random,
-    not planted), L in {12, ..., 20}, five instances per size, Appendix C's
+    not planted), L in {12, ..., 20}, fifteen instances per size, Appendix C's
     parameters.  Per instance: P_s of 4096 batched trials at each sweep budget,
     the budget with the fewest sweeps-to-solution kept (the paper tuned its
     sweeps the same way), then t_trial measured two ways: batched (device time

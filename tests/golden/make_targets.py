@@ -37,7 +37,7 @@ WORKLOADS = {
 # L x L, periodic, weights in {+-1, +-2}; random, not planted); Appendix C's
 # parameters alpha0 = 25, ratio 1.0, period 3
 for _L in (12, 14, 16, 18, 20):
-    for _s in range(1, 6):
+    for _s in range(1, 16):
         WORKLOADS[f"torus-pm12-L{_L}-s{_s}"] = (
             (lambda L=_L, sd=_s: ci.torus(L, seed=1000 * L + sd, weights="pm12")),
             dict(alpha0_deg=25.0, dwt_ratio=1.0, dwt_period=3), [(512, 2000), (128, 10000)])
