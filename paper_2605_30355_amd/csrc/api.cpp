@@ -31,7 +31,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct MemPlan {
   size_t phases, desc, class_off, slot_vertex, h_slot, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
       inc_off, inc_nbr, inc_J, phases_alt, opt_keys, opt_keys2, opt_vals, opt_vals2, opt_off,
-      opt_temp, opt_temp_bytes, total;
+      opt_temp, opt_temp_bytes, codes, total;
 };
 
 MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_params &p) {
@@ -73,6 +73,9 @@ MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_param
   mp.opt_off = take(opt ? ((size_t)R + 1) * 4 : 0);
   mp.opt_temp_bytes = opt ? opt_readout_temp_bytes(n, R) : 0;
   mp.opt_temp = take(mp.opt_temp_bytes);
+  // readout codes in device memory when n is too large for them to sit in LDS
+  const bool codes = readout_lds_bytes(n, p.n_bisectors) > kReadoutLdsLimit;
+  mp.codes = take(codes ? nr * 2 : 0);
   mp.total = off;
   return mp;
 }
@@ -306,9 +309,6 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   if ((int64_t)n * replicas >= ((int64_t)1 << 40)) return set_error(COSM_ERANGE, "n * R too large");
   if (int rc = validate_graph(n, m, eu, ev, nullptr)) return rc;
   if (int rc = validate_colouring(n, m, eu, ev, colour, num_colours)) return rc;
-  if (h != nullptr && p->n_bisectors != 1) {
-    // with bias fields the binarization uses fixed semicircles (B forced to 1)
-  }
   if (p->readout == COSM_READOUT_OPTIMAL) {
     if (h != nullptr)
       return set_error(COSM_EINVAL, "the optimal-bisector readout needs h = NULL (with bias "
@@ -412,10 +412,6 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   const bool autotune = s->shape.residency == COSM_RES_LDS && p->replicas_per_wg == 0 &&
                         p->threads_per_wg == 0 && s->lds_widths.size() > 0 &&
                         !(tune_env && tune_env[0] == '0');
-  if (readout_lds_bytes(n, s->p.n_bisectors) > (size_t)lds_capacity_bytes()) {
-    delete s;
-    return set_error(COSM_ERANGE, "the readout of one replica does not fit in LDS");
-  }
 
   const MemPlan mp = plan_memory(n, m, num_colours, replicas, s->p);
   if (device_workspace != nullptr) {
@@ -461,6 +457,8 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   d.opt_vals2 = at<uint32_t>(s->base, mp.opt_vals2);
   d.opt_off = at<int32_t>(s->base, mp.opt_off);
   d.opt_temp = at<void>(s->base, mp.opt_temp);
+  d.codes = readout_lds_bytes(n, s->p.n_bisectors) > kReadoutLdsLimit
+                ? at<uint16_t>(s->base, mp.codes) : nullptr;
   s->opt_temp_bytes = mp.opt_temp_bytes;
 
   auto up = [&](void *dst, const void *src, size_t bytes) -> int {

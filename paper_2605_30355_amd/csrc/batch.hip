@@ -489,6 +489,7 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
   ro.ev = reinterpret_cast<const int32_t *>(base + o_ev);
   ro.J = reinterpret_cast<const int32_t *>(base + o_J);
   ro.h = nullptr;
+  ro.code_global = nullptr;  // the batch keeps readout codes in LDS (max_n bounded)
   ro.spins = reinterpret_cast<int8_t *>(base + o_sp);
   ro.H = reinterpret_cast<int64_t *>(base + o_H);
   ro.cut = reinterpret_cast<int64_t *>(base + o_cut);

@@ -413,6 +413,7 @@ __device__ __forceinline__ void stream_classes(const EdgeDesc *desc_any, const i
 struct ReadoutArgs {
   const void *phases;
   const int32_t *eu, *ev, *J, *h;
+  uint16_t *code_global;  // [R][n] bisector codes in device memory, or null: in LDS
   int8_t *spins;
   int64_t *H, *cut;
   int32_t *best_p;
@@ -426,14 +427,16 @@ struct ReadoutArgs {
 // q_i = #{p : beta_p <= y_i}, y_i = x_i mod 1/2.  An edge's term -J s_u s_v thus
 // changes sign at min(q_u, q_v) and back at max(q_u, q_v): a difference array
 // over p gives every H_p in O(n + m + B).  sm64: dynamic LDS of
-// readout_lds_bytes(n, B) bytes.
+// readout_lds_bytes(n, B) bytes (readout_lds_bytes(0, B) when the codes live
+// in device memory, for n too large for LDS).
 template <int ST>
 __device__ void readout_block(const ReadoutArgs &a, int r, int64_t *sm64) {
   using F = Fmt<ST>;
   int64_t *red = sm64;            // 16
   int64_t *bins = sm64 + 16;      // B + 1
   float *beta = reinterpret_cast<float *>(bins + a.B + 1);  // B
-  uint16_t *code = reinterpret_cast<uint16_t *>(beta + a.B); // n
+  uint16_t *code = a.code_global != nullptr ? a.code_global + (size_t)r * a.n
+                                             : reinterpret_cast<uint16_t *>(beta + a.B);  // n
   const int tid = threadIdx.x, nth = blockDim.x;
   const int B = a.B;
   int64_t &s_best = red[14];

@@ -109,6 +109,7 @@ struct DeviceBuffers {
   int32_t *pev = nullptr;
   float *pJ = nullptr;
   int8_t *spins = nullptr;      // [R][n]
+  uint16_t *codes = nullptr;    // [R][n] readout codes when n is too large for LDS, else null
   int64_t *H = nullptr;         // [R]
   int64_t *cut = nullptr;       // [R]
   int32_t *best_p = nullptr;    // [R]
@@ -202,4 +203,6 @@ inline size_t lds_sweep_bytes(int32_t n_rows, int W, int32_t C) {
 }
 
 size_t readout_lds_bytes(int32_t n, int32_t B);
+// The readout keeps its per-vertex codes in LDS up to this many bytes.
+constexpr size_t kReadoutLdsLimit = 163840;
 }  // namespace cosm

@@ -580,7 +580,8 @@ int readout_st(cosm_state *s) {
   a.B = s->p.n_bisectors;
   a.grid = s->sched.grid;
   a.m = s->m;
-  const size_t lds = readout_lds_bytes(s->n, a.B);
+  a.code_global = s->d.codes;
+  const size_t lds = readout_lds_bytes(a.code_global != nullptr ? 0 : s->n, a.B);
   (void)hipFuncSetAttribute((const void *)k_readout<ST>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   hipLaunchKernelGGL((k_readout<ST>), dim3(s->R), dim3(256), lds, s->stream, a);

@@ -276,3 +276,24 @@ def test_pm12_torus_alpha25():
     colour, C, prob = make(inst, cosm.COLOR_TORUS, [16, 16])
     p = cosm.Params(alpha0_deg=25.0, sweeps_per_trial=800, dwt_ratio=1.0, dwt_period=3)
     check_trial(inst, colour, C, prob, p, seed=31, R=96, sweeps=800)
+
+
+def test_erdos_renyi_capped_sampled():
+    """Erdos-Renyi N = 10000, mean degree 4, degree cap 8 (the irregular
+    bounded-degree workload), equalised colouring, 2048 replicas in the LDS form;
+    3 replicas checked against the oracle."""
+    inst = ci.erdos_renyi_capped(10000, 4, 8, seed=3)
+    colour, C, prob = make(inst, cosm.COLOR_BALANCED)
+    p = cosm.Params(sweeps_per_trial=120, dwt_ratio=1.5, dwt_period=3)
+    info = check_trial(inst, colour, C, prob, p, seed=8, R=2048, sweeps=120, sample=[0, 1023, 2047])
+    assert info["residency"] == cosm.RES_LDS
+
+
+def test_beyond_lds_capacity_uses_hbm_form():
+    """A 300 x 300 torus (N = 90000) does not fit one replica in 160 KB of LDS:
+    AUTO residency must fall back to the HBM form and still match the oracle."""
+    inst = ci.torus(300, seed=9)
+    colour, C, prob = make(inst, cosm.COLOR_TORUS, [300, 300])
+    p = cosm.Params(sweeps_per_trial=30, dwt_ratio=0.5, dwt_period=3)
+    info = check_trial(inst, colour, C, prob, p, seed=4, R=64, sweeps=30, sample=[0, 63])
+    assert info["residency"] == cosm.RES_HBM
