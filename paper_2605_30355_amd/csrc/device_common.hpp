@@ -385,8 +385,13 @@ __device__ __forceinline__ void stream_classes(const EdgeDesc *desc_any, const i
                                                EdgeFn edge) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const gptr<EdgeDesc> desc = as_global(desc_any);
+  // x % total for x <= total + 2 (slots past the end wrap to the next sweep's
+  // first ones) without an integer division on the scalar unit
   auto at = [&](int x) {
-    const gptr<EdgeDesc> p = desc + (size_t)(x % total) * nth + tid;
+    if (x >= total) x -= total;
+    if (x >= total) x -= total;
+    if (x >= total) x -= total;
+    const gptr<EdgeDesc> p = desc + (size_t)x * nth + tid;
     return EdgeDesc{p->slots, p->J};
   };
   for (int c = 0; c < C; c++) {
