@@ -35,8 +35,8 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-ops per second, non-packed FP32
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the counter
 # reads for a 256 MiB device copy (FETCH_SIZE 131087 KiB -> x2.0; WRITE_SIZE
 # 262144 KiB -> x1.0).  Valid only for the kernel sources they were taken on.
-TRAFFIC = dict(fetch_kib=4162.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
-               sources_sha256="72daaba8cf803c1974997309e213be5c37a94c18d1bb47ad574c653c30a4a9c2")
+TRAFFIC = dict(fetch_kib=4167.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
+               sources_sha256="e866f9a1dddd65202b428c45dd1dd7df4a5a57bf743820516ba9e401d4188bb9")
 TRAFFIC_SOURCES = ("paper_2605_30355_amd/csrc/kernels.hip",
                    "paper_2605_30355_amd/csrc/device_common.hpp")
 
