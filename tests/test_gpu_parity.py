@@ -297,3 +297,33 @@ def test_beyond_lds_capacity_uses_hbm_form():
     p = cosm.Params(sweeps_per_trial=30, dwt_ratio=0.5, dwt_period=3)
     info = check_trial(inst, colour, C, prob, p, seed=4, R=64, sweeps=30, sample=[0, 63])
     assert info["residency"] == cosm.RES_HBM
+
+
+def test_library_owned_memory_and_small_workspace():
+    """cosm_init with device_workspace = NULL (the library's own hipMalloc) gives
+    the same trial as a caller workspace; a caller workspace smaller than
+    cosm_workspace_bytes() is refused with ENOMEM before any device work."""
+    import ctypes
+    import torch
+    inst = ci.torus(12, seed=2)
+    colour, C, _ = make(inst, cosm.COLOR_TORUS, [12, 12])
+    p = cosm.Params(sweeps_per_trial=200, dwt_ratio=0.5, dwt_period=3)
+    res = []
+    for own in (False, True):
+        with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=5, replicas=16,
+                        torch_workspace=not own) as st:
+            st.sweep(200)
+            res.append(st.energy())
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][2], res[1][2])
+    L = cosm.load_library()
+    cp = cosm.cosm._CParams()
+    L.cosm_default_params(ctypes.byref(cp))
+    need = ctypes.c_size_t(0)
+    assert L.cosm_workspace_bytes(inst.n, inst.m, C, 16, ctypes.byref(cp), ctypes.byref(need)) == 0
+    ws = torch.empty(max(need.value // 2, 1), dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    eu, ev, J, col = (np.ascontiguousarray(a, np.int32) for a in (inst.eu, inst.ev, inst.J, colour))
+    rc = L.cosm_init(ctypes.byref(h), inst.n, inst.m, eu.ctypes.data, ev.ctypes.data, J.ctypes.data,
+                     None, col.ctypes.data, C, ctypes.byref(cp), 1, 16, None,
+                     ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(need.value // 2))
+    assert rc == -5 and not h.value
