@@ -236,6 +236,10 @@ int cosm_batch_set_seed(cosm_batch *b, int32_t graph_id, uint64_t seed, int64_t 
 int cosm_batch_run(cosm_batch *b, const int32_t *graph_ids, int32_t count);
 /* Wait for the last run; *device_ms_out (may be NULL) = its device time. */
 int cosm_batch_wait(cosm_batch *b, double *device_ms_out);
+/* Non-blocking check of the last run: *done_out = 1 once its work (init,
+ * sweeps, readout) has finished on the device, else 0.  Never waits, so a
+ * serving loop can keep submitting to other batches; 1 before any run. */
+int cosm_batch_poll(cosm_batch *b, int32_t *done_out);
 /* Results of an instance's last run: H, cut ([R] int64) and spins ([R][n]); any
  * output may be NULL.  Synchronises the batch's stream. */
 int cosm_batch_results(cosm_batch *b, int32_t graph_id, int64_t *H_out, int64_t *cut_out,

@@ -86,6 +86,9 @@ def lib():
                                  ctypes.c_int32]
         L.orc_sweeps.restype = ctypes.c_int32
         L.orc_energy.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32, P, P, P]
+        L.orc_coupling_v.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_coupling_v.restype = ctypes.c_double
+        L.orc_relaxed_objective.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32, P, P]
         L.orc_readout.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Params),
                                   ctypes.c_int32, P, P, P, P, P]
         L.orc_readout_optimal.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32, P, P, P, P, P]
@@ -217,6 +220,21 @@ def energy(problem: Problem, spins):
     cut = np.zeros(R, dtype=np.int64)
     lib().orc_energy(problem.struct(), R, _ptr(s), _ptr(H), _ptr(cut))
     return H, cut
+
+
+def coupling_v(xi_deg: float, xj_deg: float) -> float:
+    """Relaxed coupling v of Eq. (2), phases in degrees."""
+    return float(lib().orc_coupling_v(float(xi_deg), float(xj_deg)))
+
+
+def relaxed_objective(problem: Problem, x):
+    """Relaxed objective f(x) of Eq. (7) for x ([R][n] or [n], degrees)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[None, :]
+    f = np.zeros(x.shape[0], dtype=np.float64)
+    lib().orc_relaxed_objective(problem.struct(), x.shape[0], _ptr(x), _ptr(f))
+    return f
 
 
 def readout(problem: Problem, params: Params, x):

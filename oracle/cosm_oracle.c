@@ -361,6 +361,27 @@ void orc_energy(const orc_problem *pb, int32_t R, const int8_t *spins, int64_t *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Relaxed coupling and objective, Eqs. (2), (3) and (7) (a diagnostic: the    */
+/* sweep itself only evaluates the sign of Eq. (4)).                          */
+/* ------------------------------------------------------------------------ */
+double orc_coupling_v(double xi, double xj) {
+  return 1.0 - fabs(wrapped_difference(xi - xj)) / 90.0;
+}
+
+void orc_relaxed_objective(const orc_problem *pb, int32_t R, const double *x, double *f) {
+  for (int32_t r = 0; r < R; r++) {
+    const double *xr = x + (size_t)r * pb->n;
+    double acc = 0.0;
+    for (int64_t k = 0; k < pb->m; k++)
+      acc -= (double)pb->J[k] * orc_coupling_v(xr[pb->eu[k]], xr[pb->ev[k]]);
+    /* bias fields: the same pair term against a fixed spin at phase 0 */
+    if (pb->h != NULL)
+      for (int32_t i = 0; i < pb->n; i++) acc -= (double)pb->h[i] * orc_coupling_v(xr[i], 0.0);
+    f[r] = acc;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Binarization, Algorithm 1 (final loop) and Appendix B.                      */
 /* ------------------------------------------------------------------------ */
 void orc_readout(const orc_problem *pb, const orc_params *p, int32_t R, const double *x,

@@ -10,6 +10,7 @@
  * Accurate Sparse Ising Optimization" (Zick, Shukla, Marakov):
  *   - Ising energy, Eq. (1); Max-Cut form and w = -J, Appendix A, Eq. (14);
  *   - circular variables in degrees on [0, 360) with non-negative mod, Sec. II-A;
+ *   - relaxed coupling v and objective f, Eqs. (2), (3), (7) (diagnostic);
  *   - biased sign and pair contributions, Eqs. (4)-(6);
  *   - sequential conflict-free search over a proper edge colouring,
  *     Eqs. (9)-(13), Sec. II-C;
@@ -107,6 +108,16 @@ int32_t orc_sweeps(const orc_problem *pb, const orc_params *p, uint64_t seed, in
 
 /* Energy, Eq. (1), and cut, Eq. (14) with w = -J, for spins [R][n] in {-1,+1}. */
 void orc_energy(const orc_problem *pb, int32_t R, const int8_t *spins, int64_t *H, int64_t *cut);
+
+/* Relaxed coupling v of Eq. (2) for two phases in degrees: 1 at equal phases,
+ * -1 diametrically opposite, linear in the shorter angular distance between. */
+double orc_coupling_v(double xi, double xj);
+
+/* Relaxed objective f(x) of Eq. (7) for x [R][n] (degrees) into f [R]: the sum
+ * of the pair energies -J v of Eq. (3); with bias fields each h_i adds the pair
+ * term of a coupling h_i to a fixed spin at phase 0 (the reading the sweep
+ * uses).  At phases restricted to {0, 180} f equals H of Eq. (1). */
+void orc_relaxed_objective(const orc_problem *pb, int32_t R, const double *x, double *f);
 
 /* Binarize x ([R][n], degrees) by B bisectors, keeping the lowest-H one (lowest
  * index on ties); with h present a single semicircle centred at 0.

@@ -28,7 +28,7 @@ ABI_FUNCTIONS = (
     "cosm_get_phases", "cosm_set_phases", "cosm_get_info", "cosm_set_timing",
     "cosm_last_error", "cosm_version", "cosm_lds_probe", "cosm_qubo_to_ising",
     "cosm_batch_create", "cosm_batch_destroy", "cosm_batch_add_graph", "cosm_batch_set_seed",
-    "cosm_batch_run", "cosm_batch_wait", "cosm_batch_results",
+    "cosm_batch_run", "cosm_batch_wait", "cosm_batch_poll", "cosm_batch_results",
 )
 
 
@@ -107,6 +107,7 @@ def load_library():
         "cosm_batch_set_seed": (I32, [P, I32, U64, I64]),
         "cosm_batch_run": (I32, [P, P, I32]),
         "cosm_batch_wait": (I32, [P, ctypes.POINTER(ctypes.c_double)]),
+        "cosm_batch_poll": (I32, [P, ctypes.POINTER(ctypes.c_int32)]),
         "cosm_batch_results": (I32, [P, I32, P, P, P]),
         "cosm_version": (ctypes.c_char_p, []),
         "cosm_lds_probe": (I32, [I32, I32, P, ctypes.POINTER(ctypes.c_double)]),
@@ -374,6 +375,12 @@ class Batch:
         ms = ctypes.c_double(0.0)
         _check(load_library().cosm_batch_wait(self._b, ctypes.byref(ms)))
         return float(ms.value)
+
+    def poll(self):
+        """True once the last run has finished on the device (never blocks)."""
+        done = ctypes.c_int32(0)
+        _check(load_library().cosm_batch_poll(self._b, ctypes.byref(done)))
+        return bool(done.value)
 
     def results(self, graph_id, return_spins=False):
         n, R = self._sizes[graph_id]

@@ -643,6 +643,20 @@ int cosm_batch_wait(cosm_batch *b, double *device_ms_out) {
   return COSM_OK;
 }
 
+int cosm_batch_poll(cosm_batch *b, int32_t *done_out) {
+  clear_error();
+  if (b == nullptr || done_out == nullptr)
+    return set_error(COSM_EINVAL, "batch and done_out must not be NULL");
+  hipError_t q = hipEventQuery(b->e1);
+  if (q == hipErrorNotReady) {
+    *done_out = 0;
+    return COSM_OK;
+  }
+  COSM_HIP_CHECK(q);
+  *done_out = 1;
+  return COSM_OK;
+}
+
 int cosm_batch_results(cosm_batch *b, int32_t graph_id, int64_t *H_out, int64_t *cut_out,
                        int8_t *spins_out) {
   clear_error();

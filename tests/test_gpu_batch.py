@@ -4,6 +4,7 @@ in one launch must give exactly the trajectories, energies and spins they give
 alone (grid schedule), including on replays of the captured hipGraph with new
 seeds and subsets of the instances."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -81,7 +82,13 @@ def test_batch_matches_oracle_sample():
     inst, c, C, p, seed, R = graphs()[0]
     with cosm.Batch(max_graphs=4, max_n=400) as b:
         gid = b.add(inst.n, inst.eu, inst.ev, inst.J, c, C, p, seed=seed, replicas=R)
+        assert b.poll()  # nothing submitted yet
         b.run([gid])
+        # the non-blocking poll turns true once the run has drained
+        deadline = time.monotonic() + 60.0
+        while not b.poll():
+            assert time.monotonic() < deadline, "batch run did not finish within 60 s"
+            time.sleep(0.001)
         b.wait()
         H, cut, sp = b.results(gid, return_spins=True)
     prob = oracle.Problem(inst.n, inst.eu, inst.ev, inst.J, colour=c, C=C)
