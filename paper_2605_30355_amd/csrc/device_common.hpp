@@ -313,6 +313,58 @@ __device__ __forceinline__ void edge_rows(uint32_t *lds, uint32_t bu, uint32_t b
   lds_store_at<W>(lds, bv, wv);
 }
 
+// The dual window twist on the RW values of one row (membership tested on the
+// values given, c and tws per replica).
+template <int ST, int RW>
+__device__ __forceinline__ void twist_values(float (&x)[RW], const float (&c)[RW],
+                                             const float (&tws)[RW], float win2) {
+#pragma unroll
+  for (int k = 0; k < RW; k++)
+    if (in_windows(x[k], c[k], win2)) x[k] = Fmt<ST>::wrap(x[k] + tws[k]);
+}
+
+// Eq. (6) on every replica of one edge of the last class, followed by the
+// twist of both endpoints: their phases are final for the sweep once the
+// update is done, so the twist needs no pass of its own for them.
+template <int ST, int W>
+__device__ __forceinline__ void edge_rows_twist(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ,
+                                                const float (&c)[W * Fmt<ST>::kPerWord],
+                                                const float (&tws)[W * Fmt<ST>::kPerWord],
+                                                float win2) {
+  using F = Fmt<ST>;
+  constexpr int RW = W * F::kPerWord;
+  uint32_t wu[W], wv[W];
+  lds_load_at<W>(lds, bu, wu);
+  lds_load_at<W>(lds, bv, wv);
+  float xu[RW], xv[RW];
+  F::template unpack<W>(wu, xu);
+  F::template unpack<W>(wv, xv);
+#pragma unroll
+  for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
+  twist_values<ST, RW>(xu, c, tws, win2);
+  twist_values<ST, RW>(xv, c, tws, win2);
+  F::template pack<W>(xu, wu);
+  F::template pack<W>(xv, wv);
+  lds_store_at<W>(lds, bu, wu);
+  lds_store_at<W>(lds, bv, wv);
+}
+
+// The twist of one row that no edge of the last class touches.
+template <int ST, int W>
+__device__ __forceinline__ void row_twist(uint32_t *lds, uint32_t b,
+                                          const float (&c)[W * Fmt<ST>::kPerWord],
+                                          const float (&tws)[W * Fmt<ST>::kPerWord], float win2) {
+  using F = Fmt<ST>;
+  constexpr int RW = W * F::kPerWord;
+  uint32_t w[W];
+  lds_load_at<W>(lds, b, w);
+  float x[RW];
+  F::template unpack<W>(w, x);
+  twist_values<ST, RW>(x, c, tws, win2);
+  F::template pack<W>(x, w);
+  lds_store_at<W>(lds, b, w);
+}
+
 
 
 // ---------------------------------------------------------------------------

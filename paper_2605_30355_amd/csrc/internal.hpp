@@ -92,8 +92,15 @@ struct LdsSchedule {
   std::vector<int32_t> slot_vertex;  // [n_rows] vertex of each slot
   std::vector<int32_t> K;          // [C] slots per thread for each class
   std::vector<int32_t> padded;     // [C] padded list length of each class
-  std::vector<EdgeDesc> desc;      // [total_slots * nth]
+  std::vector<EdgeDesc> desc;      // [(total_slots + fuse_k) * nth]
+  // Rows that no edge of the last class touches, fuse_k per thread, stored in
+  // desc after the lane schedule (slots = row, kEmptySlot for none).  They let
+  // the twist run inside the last class's sub-sweep; fuse is false when they
+  // would need more than kFuseRowsMax per thread.
+  bool fuse = false;
+  int32_t fuse_k = 0;
 };
+constexpr int32_t kFuseRowsMax = 4;
 
 struct DeviceBuffers {
   void *phases = nullptr;       // [n][R] float or 16-bit, replica-major

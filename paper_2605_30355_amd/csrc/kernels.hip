@@ -29,6 +29,10 @@ struct LdsArgs {
   SweepSchedule sch;
   uint32_t k0, k1, rid0;
   uint32_t bar_mask;          // register-resident schedule: barrier after slot j
+  // fused form: the twist runs inside the last class's sub-sweep, with fuse_k
+  // rows per thread (after the lane schedule in desc) that no edge of that
+  // class touches
+  int32_t fuse_k;
 };
 
 // ---------------------------------------------------------------------------
@@ -53,8 +57,9 @@ __global__ void __launch_bounds__(256) k_init(void *phases, int32_t n, int32_t R
 // distinct LDS bank groups).  EMAX > 0: the schedule (at most EMAX slots) is
 // loaded into registers once; EMAX == 0: it streams from memory, one slot ahead.
 // ---------------------------------------------------------------------------
-template <int ST, int W, int EMAX, bool EXACT>
+template <int ST, int W, int EMAX, bool EXACT, bool FUSE>
 __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
+  static_assert(!FUSE || EXACT, "the fused twist needs the one-slot-per-class form");
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
@@ -108,6 +113,18 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       jr[j] = empty ? 0.0f : d.J;
     }
   }
+  // rows outside the last class (twist only)
+  uint32_t fr[FUSE ? kFuseRowsMax : 1];
+  if constexpr (FUSE) {
+#pragma unroll
+    for (int q = 0; q < kFuseRowsMax; q++) {
+      fr[q] = kEmptySlot;
+      if (q < a.fuse_k) {
+        const uint32_t sl = a.desc[(size_t)(a.total_slots + q) * nth + tid].slots;
+        if (sl != kEmptySlot) fr[q] = sl * ROWB;
+      }
+    }
+  }
   // streamed schedule: the first two slots in flight
   EdgeDesc dA{kEmptySlot, 0.0f}, dB{kEmptySlot, 0.0f};
   int jslot = 0;
@@ -122,7 +139,40 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     float alpha, twist;
     schedule_step(sc, t, alpha, twist);
     // Sequential conflict-free search: classes in order, a barrier after each.
-    if constexpr (EXACT) {
+    if constexpr (FUSE) {
+      // EMAX slots, one class each.  On a twist sweep the last class twists
+      // the rows it updates and, concurrently, the rows it leaves out.
+      const bool fuse_now = sc.phase + 1 == sc.period;
+      float cth[RW], tws[RW];
+      if (fuse_now) {
+        const int slot = tw % kThetaChunk;
+        if (slot == 0) {
+          theta_fill(theta_buf, nullptr, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0,
+                     a.k0, a.k1, sc.win);
+          __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < RW; k++) {
+          cth[k] = theta_buf[slot * RW + k];
+          tws[k] = twist;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < EMAX - 1; j++) {
+        edge_rows<ST, W>(lds, ua[j], va[j], alpha * jr[j]);
+        __syncthreads();
+      }
+      if (fuse_now) {
+        edge_rows_twist<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha * jr[EMAX - 1], cth, tws,
+                               sc.win2);
+#pragma unroll
+        for (int q = 0; q < kFuseRowsMax; q++)
+          if (q < a.fuse_k && fr[q] != kEmptySlot) row_twist<ST, W>(lds, fr[q], cth, tws, sc.win2);
+      } else {
+        edge_rows<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha * jr[EMAX - 1]);
+      }
+      __syncthreads();
+    } else if constexpr (EXACT) {
       // EMAX slots, one class each
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
@@ -144,7 +194,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     }
     // Bias fields: one more conflict-free sub-sweep against the virtual spin
     // at phase 0, after the classes (rows are final after the last barrier).
-    if (a.h_slot != nullptr) {
+    if (!FUSE && a.h_slot != nullptr) {
       for (int s0 = tid; s0 < a.n_rows; s0 += 4 * nth) {
         int32_t hv[4];
         uint32_t w[4][W];
@@ -172,7 +222,12 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     // class (a barrier ended it).  Reference angles (and, with bias fields,
     // directions) come from the LDS tables, refilled by the whole workgroup
     // every kThetaChunk twists.
-    if (sc.period > 0 && ++sc.phase == sc.period) {
+    if constexpr (FUSE) {
+      if (++sc.phase == sc.period) {
+        sc.phase = 0;
+        tw++;  // done inside the last class
+      }
+    } else if (sc.period > 0 && ++sc.phase == sc.period) {
       sc.phase = 0;
       const int slot = tw % kThetaChunk;
       if (slot == 0) {
@@ -413,12 +468,12 @@ float host_twist(const Schedule &sc, int64_t t) {
   return sc.dwt_ratio * host_alpha(sc, t);
 }
 
-template <int ST, int W, int EMAX, bool EXACT>
+template <int ST, int W, int EMAX, bool EXACT, bool FUSE = false>
 int launch_lds(cosm_state *s, const LdsArgs &a) {
   const size_t lds = s->shape.lds_bytes;
-  (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, W, EMAX, EXACT>,
+  (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, W, EMAX, EXACT, FUSE>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_sweep_lds<ST, W, EMAX, EXACT>), dim3(s->shape.blocks),
+  hipLaunchKernelGGL((k_sweep_lds<ST, W, EMAX, EXACT, FUSE>), dim3(s->shape.blocks),
                      dim3(s->shape.threads), lds, s->stream, a);
   return launch_check("k_sweep_lds");
 }
@@ -428,6 +483,11 @@ int launch_lds_w(cosm_state *s, const LdsArgs &a) {
   const int slots = a.total_slots;
   // one slot per class and exactly 4 / 8 slots: the unconditional form
   const bool one_each = slots == a.C && slots <= 32 && a.bar_mask == (uint32_t)((1ull << slots) - 1);
+  // the twist inside the last class: a twist period, no field pass after the
+  // classes, and the rows outside the last class few enough for registers
+  const bool fuse = one_each && a.sch.period > 0 && a.h_slot == nullptr && s->lds.fuse;
+  if (fuse && slots == 4) return launch_lds<ST, W, 4, true, true>(s, a);
+  if (fuse && slots == 8) return launch_lds<ST, W, 8, true, true>(s, a);
   if (one_each && slots == 4) return launch_lds<ST, W, 4, true>(s, a);
   if (one_each && slots == 8) return launch_lds<ST, W, 8, true>(s, a);
   if (slots <= 4) return launch_lds<ST, W, 4, false>(s, a);
@@ -459,6 +519,7 @@ int sweeps_lds_st(cosm_state *s, int64_t n_sweeps) {
     }
   }
   a.bar_mask = mask;
+  a.fuse_k = s->lds.fuse_k;
   const Schedule &sc = s->sched;
   SweepSchedule &w = a.sch;
   w.grid = sc.grid;

@@ -286,6 +286,29 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
   int64_t pad = 0;
   for (int32_t c = 0; c < C; c++) pad += L.padded[(size_t)c] - (int64_t)by_class[(size_t)c].size();
   L.pad_entries = pad;
+  // 4. rows outside the last class, in slot order (consecutive lanes read
+  // consecutive rows), kFuseRowsMax per thread at most.
+  L.fuse = false;
+  L.fuse_k = 0;
+  if (C > 0) {
+    std::vector<char> touched((size_t)n, 0);
+    for (const EdgeDesc &d : lists[(size_t)C - 1]) {
+      if (d.slots == kEmptySlot) continue;
+      touched[(size_t)(d.slots & 0xffffu)] = 1;
+      touched[(size_t)(d.slots >> 16)] = 1;
+    }
+    std::vector<int32_t> rest;
+    for (int32_t r = 0; r < n; r++)
+      if (!touched[(size_t)r]) rest.push_back(r);
+    const int32_t fk = (int32_t)(((int64_t)rest.size() + nth - 1) / nth);
+    if (fk <= kFuseRowsMax) {
+      L.fuse = true;
+      L.fuse_k = fk;
+      L.desc.resize((size_t)(L.total_slots + fk) * nth, EdgeDesc{kEmptySlot, 0.0f});
+      for (size_t q = 0; q < rest.size(); q++)
+        L.desc[(size_t)L.total_slots * nth + q] = EdgeDesc{(uint32_t)rest[q], 0.0f};
+    }
+  }
   return COSM_OK;
 }
 

@@ -54,6 +54,29 @@ int main(int argc, char** argv) {
     }
   }
   got = got_c;
-  printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got));
+  // rows outside the last class: together with the last class's rows, every
+  // row exactly once (without fuse the twist keeps its own pass)
+  int fuse_ok = 1;
+  if (L.fuse) {
+    if (L.desc.size() != (size_t)(L.total_slots + L.fuse_k) * L.nth) fuse_ok = 0;
+    std::vector<int> hit(n, 0);
+    for (int k = 0; k < L.K[C - 1]; k++)
+      for (int t = 0; t < L.nth; t++) {
+        auto d = L.desc[(size_t)(L.total_slots - L.K[C - 1] + k) * L.nth + t];
+        if (d.slots == cosm::kEmptySlot) continue;
+        hit[d.slots & 0xffff]++; hit[d.slots >> 16]++;
+      }
+    for (int q = 0; q < L.fuse_k && fuse_ok; q++)
+      for (int t = 0; t < L.nth; t++) {
+        auto d = L.desc[(size_t)(L.total_slots + q) * L.nth + t];
+        if (d.slots == cosm::kEmptySlot) continue;
+        if (d.slots >= (uint32_t)n) { fuse_ok = 0; break; }
+        hit[d.slots]++;
+      }
+    for (int r = 0; r < n; r++) if (hit[r] != 1) fuse_ok = 0;
+  } else if (L.desc.size() != (size_t)L.total_slots * L.nth) {
+    fuse_ok = 0;
+  }
+  printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d fuse=%d fuse_k=%d fuse_ok=%d\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got), (int)L.fuse, L.fuse_k, fuse_ok);
   return 0;
 }

@@ -3,7 +3,8 @@ run on the CPU: every edge appears once, in its own class, and no LDS bank is
 touched twice by the u-rows, or by the v-rows, of one group of lanes that the
 gfx950 LDS serves together (reads: 256 bytes of lanes, 32 lanes for 4-byte
 rows; writes: 128 bytes of lanes; the model is written out in
-sched_check.cpp)."""
+sched_check.cpp); and the rows outside the last class, which the twist visits
+inside that class's sub-sweep, are exactly the rows its edges leave out."""
 import os
 import subprocess
 
@@ -44,4 +45,4 @@ def test_schedule_conflict_free_and_complete(checker, case, W):
         f"{u} {v} {J} {c}" for u, v, J, c in zip(inst.eu, inst.ev, inst.J, colour))
     r = subprocess.run([checker, str(W)], input=txt, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert "conflicts=0" in r.stdout and "equal=1" in r.stdout, r.stdout
+    assert "conflicts=0" in r.stdout and "equal=1" in r.stdout and "fuse_ok=1" in r.stdout, r.stdout
