@@ -45,9 +45,9 @@ MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_param
   const size_t nr = (size_t)n * (size_t)R;
   mp.phases = take(nr * storage_bytes(p.storage));
   // lane schedule: at most 32 lanes per edge group plus one partial pass per
-  // class, then the rows outside the last class
-  mp.desc = take(((size_t)32 * m + (size_t)1024 * C + 1024 + (size_t)kFuseRowsMax * 1024) *
-                 sizeof(EdgeDesc));
+  // class, the repeated slots, then the rows outside the last class
+  mp.desc = take(((size_t)32 * m + (size_t)1024 * C + 1024 +
+                  (size_t)(kStreamRepeat + kFuseRowsMax) * 1024) * sizeof(EdgeDesc));
   mp.class_off = take(((size_t)C + 1) * 4);
   mp.slot_vertex = take(((size_t)n + 1) * 4);
   mp.h_slot = take(((size_t)n + 1) * 4);

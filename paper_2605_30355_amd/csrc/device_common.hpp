@@ -341,6 +341,12 @@ __device__ __forceinline__ void edge_rows_twist(uint32_t *lds, uint32_t bu, uint
   F::template unpack<W>(wv, xv);
 #pragma unroll
   for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
+  // the twist sees the stored (rounded) phases, as a pass of its own would;
+  // a no-op for FP32
+  F::template pack<W>(xu, wu);
+  F::template pack<W>(xv, wv);
+  F::template unpack<W>(wu, xu);
+  F::template unpack<W>(wv, xv);
   twist_values<ST, RW>(xu, c, tws, win2);
   twist_values<ST, RW>(xv, c, tws, win2);
   F::template pack<W>(xu, wu);
@@ -436,14 +442,11 @@ __device__ __forceinline__ void stream_classes(const EdgeDesc *desc_any, const i
                                                int total, EdgeDesc &A, EdgeDesc &B, int &j,
                                                EdgeFn edge) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  const gptr<EdgeDesc> desc = as_global(desc_any);
-  // x % total for x <= total + 2 (slots past the end wrap to the next sweep's
-  // first ones) without an integer division on the scalar unit
+  const gptr<EdgeDesc> desc = as_global(desc_any) + tid;
+  // slot x <= total + 1: the schedule repeats its first slots after the last,
+  // so the prefetch of the next sweep's first slots needs no wrap
   auto at = [&](int x) {
-    if (x >= total) x -= total;
-    if (x >= total) x -= total;
-    if (x >= total) x -= total;
-    const gptr<EdgeDesc> p = desc + (size_t)x * nth + tid;
+    const gptr<EdgeDesc> p = desc + (uint32_t)(x * nth);
     return EdgeDesc{p->slots, p->J};
   };
   for (int c = 0; c < C; c++) {

@@ -92,15 +92,18 @@ struct LdsSchedule {
   std::vector<int32_t> slot_vertex;  // [n_rows] vertex of each slot
   std::vector<int32_t> K;          // [C] slots per thread for each class
   std::vector<int32_t> padded;     // [C] padded list length of each class
-  std::vector<EdgeDesc> desc;      // [(total_slots + fuse_k) * nth]
+  // [(total_slots + kStreamRepeat + fuse_k) * nth]: the slots, the first
+  // kStreamRepeat slots again (mod total_slots), then the rows below
+  std::vector<EdgeDesc> desc;
   // Rows that no edge of the last class touches, fuse_k per thread, stored in
-  // desc after the lane schedule (slots = row, kEmptySlot for none).  They let
+  // desc after the repeated slots (slots = row, kEmptySlot for none).  They let
   // the twist run inside the last class's sub-sweep; fuse is false when they
   // would need more than kFuseRowsMax per thread.
   bool fuse = false;
   int32_t fuse_k = 0;
 };
 constexpr int32_t kFuseRowsMax = 4;
+constexpr int32_t kStreamRepeat = 3;
 
 struct DeviceBuffers {
   void *phases = nullptr;       // [n][R] float or 16-bit, replica-major

@@ -30,7 +30,7 @@ struct LdsArgs {
   uint32_t k0, k1, rid0;
   uint32_t bar_mask;          // register-resident schedule: barrier after slot j
   // fused form: the twist runs inside the last class's sub-sweep, with fuse_k
-  // rows per thread (after the lane schedule in desc) that no edge of that
+  // rows per thread (after the repeated slots in desc) that no edge of that
   // class touches
   int32_t fuse_k;
 };
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     for (int q = 0; q < kFuseRowsMax; q++) {
       fr[q] = kEmptySlot;
       if (q < a.fuse_k) {
-        const uint32_t sl = a.desc[(size_t)(a.total_slots + q) * nth + tid].slots;
+        const uint32_t sl = a.desc[(size_t)(a.total_slots + kStreamRepeat + q) * nth + tid].slots;
         if (sl != kEmptySlot) fr[q] = sl * ROWB;
       }
     }

@@ -286,7 +286,18 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
   int64_t pad = 0;
   for (int32_t c = 0; c < C; c++) pad += L.padded[(size_t)c] - (int64_t)by_class[(size_t)c].size();
   L.pad_entries = pad;
-  // 4. rows outside the last class, in slot order (consecutive lanes read
+  // 4. kStreamRepeat slots after the last repeat slots 0, 1, ... (mod
+  // total), so that a schedule streamed one or two slots ahead never wraps.
+  if (L.total_slots > 0) {
+    L.desc.resize((size_t)(L.total_slots + kStreamRepeat) * nth);
+    for (int32_t q = 0; q < kStreamRepeat; q++)
+      for (int32_t t = 0; t < nth; t++)
+        L.desc[(size_t)(L.total_slots + q) * nth + t] =
+            L.desc[(size_t)(q % L.total_slots) * nth + t];
+  } else {
+    L.desc.assign((size_t)kStreamRepeat * nth, EdgeDesc{kEmptySlot, 0.0f});
+  }
+  // 5. rows outside the last class, in slot order (consecutive lanes read
   // consecutive rows), kFuseRowsMax per thread at most.
   L.fuse = false;
   L.fuse_k = 0;
@@ -304,9 +315,9 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
     if (fk <= kFuseRowsMax) {
       L.fuse = true;
       L.fuse_k = fk;
-      L.desc.resize((size_t)(L.total_slots + fk) * nth, EdgeDesc{kEmptySlot, 0.0f});
-      for (size_t q = 0; q < rest.size(); q++)
-        L.desc[(size_t)L.total_slots * nth + q] = EdgeDesc{(uint32_t)rest[q], 0.0f};
+      const size_t base = (size_t)(L.total_slots + kStreamRepeat) * nth;
+      L.desc.resize(base + (size_t)fk * nth, EdgeDesc{kEmptySlot, 0.0f});
+      for (size_t q = 0; q < rest.size(); q++) L.desc[base + q] = EdgeDesc{(uint32_t)rest[q], 0.0f};
     }
   }
   return COSM_OK;

@@ -54,11 +54,21 @@ int main(int argc, char** argv) {
     }
   }
   got = got_c;
-  // rows outside the last class: together with the last class's rows, every
-  // row exactly once (without fuse the twist keeps its own pass)
+  // rows outside the last class (after the repeated slots): together with the
+  // last class's rows, every row exactly once (without fuse the twist keeps
+  // its own pass)
   int fuse_ok = 1;
+  // the kStreamRepeat slots after the last repeat slots 0, 1, ... mod total
+  const size_t rep = (size_t)(L.total_slots + cosm::kStreamRepeat) * L.nth;
+  if (L.desc.size() < rep) fuse_ok = 0;
+  for (int q = 0; q < cosm::kStreamRepeat && fuse_ok && L.total_slots > 0; q++)
+    for (int t = 0; t < L.nth; t++) {
+      auto a = L.desc[(size_t)(L.total_slots + q) * L.nth + t];
+      auto b = L.desc[(size_t)(q % L.total_slots) * L.nth + t];
+      if (a.slots != b.slots || a.J != b.J) { fuse_ok = 0; break; }
+    }
   if (L.fuse) {
-    if (L.desc.size() != (size_t)(L.total_slots + L.fuse_k) * L.nth) fuse_ok = 0;
+    if (L.desc.size() != rep + (size_t)L.fuse_k * L.nth) fuse_ok = 0;
     std::vector<int> hit(n, 0);
     for (int k = 0; k < L.K[C - 1]; k++)
       for (int t = 0; t < L.nth; t++) {
@@ -68,13 +78,13 @@ int main(int argc, char** argv) {
       }
     for (int q = 0; q < L.fuse_k && fuse_ok; q++)
       for (int t = 0; t < L.nth; t++) {
-        auto d = L.desc[(size_t)(L.total_slots + q) * L.nth + t];
+        auto d = L.desc[rep + (size_t)q * L.nth + t];
         if (d.slots == cosm::kEmptySlot) continue;
         if (d.slots >= (uint32_t)n) { fuse_ok = 0; break; }
         hit[d.slots]++;
       }
     for (int r = 0; r < n; r++) if (hit[r] != 1) fuse_ok = 0;
-  } else if (L.desc.size() != (size_t)L.total_slots * L.nth) {
+  } else if (L.desc.size() != rep) {
     fuse_ok = 0;
   }
   printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d fuse=%d fuse_k=%d fuse_ok=%d\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got), (int)L.fuse, L.fuse_k, fuse_ok);
