@@ -127,9 +127,10 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
   SweepSchedule sc = g.sch;
   __syncthreads();
 
-  for (int64_t t = 1; t <= g.S; t++) {
+  const uint32_t S = (uint32_t)g.S;  // at most 2^31 sweeps
+  for (uint32_t t = 1; t - 1 < S; t++) {
     float alpha, twist;
-    schedule_step(sc, t, alpha, twist);
+    schedule_step(sc, alpha, twist);
     if (g.total_slots > 0)
       stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
         edge_rows_sets<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, set_bytes,
@@ -465,20 +466,7 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
   d.W = W;
   d.S = s.p.sweeps_per_trial;
   const Schedule &sc = s.sched;
-  const int64_t num = sc.a0_units * sc.S + sc.S / 2;
-  d.sch.grid = sc.grid;
-  d.sch.S = sc.S;
-  d.sch.q = (int32_t)(num / sc.S);
-  d.sch.r = num % sc.S;
-  d.sch.aq = (int32_t)(sc.a0_units / sc.S);
-  d.sch.ar = sc.a0_units % sc.S;
-  d.sch.alpha_cont_per = sc.alpha0_turns / (float)sc.S;
-  d.sch.twist2 = sc.twist_num2;
-  d.sch.ratio = sc.dwt_ratio;
-  d.sch.period = sc.dwt_period;
-  d.sch.phase = 0;
-  d.sch.win = sc.window;
-  d.sch.win2 = sc.window2;
+  d.sch = make_sweep_schedule(sc, 0);
   d.k0 = (uint32_t)(seed & 0xffffffffu);
   d.k1 = (uint32_t)(seed >> 32);
   d.rid0 = 0;

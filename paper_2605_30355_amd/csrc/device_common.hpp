@@ -220,36 +220,90 @@ __device__ __forceinline__ float theta_turns(uint32_t t, uint32_t rid, uint32_t 
 }
 
 // Per-sweep schedule evaluated on the device.  Grid: alpha = q * 2^-22 with
-// q = floor(num / S), num = a0 (S - t + 1) + S/2, stepped by subtraction
-// (q < 2^22 and 2 rho q < 2^23, so the int32 products and conversions are exact).
+// q = floor(num / S), num = a0 (S - t + 1) + S/2, stepped by subtraction with
+// a 32-bit remainder (S <= 2^31; q < 2^22 and 2 rho q < 2^23, so the int32
+// products and conversions are exact).  Few scalar instructions per sweep:
+// every wave of the CU shares one scalar unit.
 struct SweepSchedule {
   int32_t grid;
-  int64_t S, r, ar;
-  int32_t q, aq;
+  uint32_t S, r, ar;     // grid: remainder of num / S and of a0 / S
+  int32_t q, aq;         // grid: quotients
+  uint32_t u;            // continuous: S - t + 1 of the next sweep t
   float alpha_cont_per;  // alpha0 / S in turns (continuous)
   int32_t twist2;        // 2 * ratio (grid)
   float ratio;           // continuous
   int32_t period, phase; // twist when ++phase == period
   float win, win2;
+  int64_t a0;            // grid: alpha0 in units of 2^-22 turn
 };
 
-// alpha_t and the twist angle rho * alpha_t of sweep t (Algorithm 1's ramp);
-// advances the grid numerator to sweep t + 1.  S - t + 1 <= 2^31 fits uint32.
-__device__ __forceinline__ void schedule_step(SweepSchedule &sc, int64_t t, float &alpha,
-                                              float &twist) {
+// alpha_t and the twist of sweep t (1 <= t <= S) computed directly, as the
+// host does: the same values schedule_step produces by stepping.
+__device__ __forceinline__ void schedule_at(const SweepSchedule &sc, uint32_t t, float &alpha,
+                                            float &twist) {
+  const uint32_t u = sc.S - t + 1u;  // S - t + 1 >= 1
+  if (sc.grid) {
+    const int32_t q = (int32_t)((sc.a0 * (int64_t)u + (int64_t)(sc.S / 2u)) / (int64_t)sc.S);
+    alpha = (float)q * kQ22;
+    twist = (float)(sc.twist2 * q) * kQ23;
+  } else {
+    alpha = (float)u * sc.alpha_cont_per;
+    twist = sc.ratio * alpha;
+  }
+}
+
+// One wave's table of 64 sweeps: lane i holds alpha and the twist of sweep
+// t_next + i (clamped to S); a sweep then reads its pair with two readlanes
+// instead of stepping the ramp on the scalar and vector units every sweep.
+struct ScheduleChunk {
+  float alpha, twist;
+  __device__ __forceinline__ void fill(const SweepSchedule &sc, uint32_t t_next) {
+    const uint32_t lane = __lane_id();
+    const uint32_t t = min(t_next + lane, sc.S);
+    schedule_at(sc, t, alpha, twist);
+  }
+  __device__ __forceinline__ void get(uint32_t i, float &a, float &tw) const {
+    a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(alpha), i));
+    tw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(twist), i));
+  }
+};
+
+// alpha_t and the twist angle rho * alpha_t of the next sweep (Algorithm 1's
+// ramp); advances to the sweep after it.
+__device__ __forceinline__ void schedule_step(SweepSchedule &sc, float &alpha, float &twist) {
   if (sc.grid) {
     alpha = (float)sc.q * kQ22;
     twist = (float)(sc.twist2 * sc.q) * kQ23;
-    sc.q -= sc.aq;
-    sc.r -= sc.ar;
-    if (sc.r < 0) {
-      sc.r += sc.S;
-      sc.q -= 1;
-    }
+    const bool borrow = sc.r < sc.ar;
+    sc.r = sc.r - sc.ar + (borrow ? sc.S : 0u);
+    sc.q -= sc.aq + (borrow ? 1 : 0);
   } else {
-    alpha = (float)(uint32_t)(sc.S - t + 1) * sc.alpha_cont_per;
+    alpha = (float)sc.u * sc.alpha_cont_per;
     twist = sc.ratio * alpha;
+    sc.u -= 1u;
   }
+}
+
+// The device schedule after t_done sweeps (host side).
+SweepSchedule make_sweep_schedule(const Schedule &sc, int64_t t_done) {
+  SweepSchedule w{};
+  w.grid = sc.grid;
+  w.S = (uint32_t)sc.S;
+  const int64_t num = sc.a0_units * (sc.S - t_done) + sc.S / 2;  // numerator of sweep t_done + 1
+  w.q = (int32_t)(num / sc.S);
+  w.r = (uint32_t)(num % sc.S);
+  w.aq = (int32_t)(sc.a0_units / sc.S);
+  w.ar = (uint32_t)(sc.a0_units % sc.S);
+  w.u = (uint32_t)(sc.S - t_done);
+  w.alpha_cont_per = sc.alpha0_turns / (float)sc.S;
+  w.twist2 = sc.twist_num2;
+  w.ratio = sc.dwt_ratio;
+  w.period = sc.dwt_period;
+  w.phase = sc.dwt_period > 0 ? (int32_t)(t_done % sc.dwt_period) : 0;
+  w.win = sc.window;
+  w.win2 = sc.window2;
+  w.a0 = sc.a0_units;
+  return w;
 }
 
 // Fills table[q * nrep + k] with c = 2 theta - w for the twist at sweep
@@ -258,11 +312,11 @@ __device__ __forceinline__ void schedule_step(SweepSchedule &sc, int64_t t, floa
 // the top bit of word 1 of the same draw; used with bias fields).  Every thread
 // of the workgroup takes part; the caller synchronises.
 __device__ __forceinline__ void theta_fill(float *table, float *dirs, int nch, int nrep,
-                                           int64_t t_first, int32_t period, uint32_t rid_base,
+                                           uint32_t t_first, int32_t period, uint32_t rid_base,
                                            uint32_t k0, uint32_t k1, float win) {
   for (int i = threadIdx.x; i < nch * nrep; i += blockDim.x) {
     const int q = i / nrep, k = i - q * nrep;
-    const uint2 w = philox_words01(0u, (uint32_t)(t_first + (int64_t)q * period),
+    const uint2 w = philox_words01(0u, t_first + (uint32_t)(q * period),
                                    rid_base + (uint32_t)k, kTagDwt, k0, k1);
     table[i] = 2.0f * ((float)(w.x >> 9) * kQ23) - win;
     if (dirs != nullptr) dirs[i] = (w.y >> 31) ? -1.0f : 1.0f;

@@ -135,9 +135,15 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   __syncthreads();
 
   SweepSchedule sc = a.sch;
-  for (int64_t t = a.t0 + 1; t <= a.t0 + a.nsw; t++) {
+  // 32-bit sweep counters (at most 2^31 sweeps)
+  const uint32_t nsw = (uint32_t)a.nsw;
+  uint32_t t = (uint32_t)a.t0;
+  ScheduleChunk chunk;
+  for (uint32_t it = 0; it < nsw; it++) {
+    t++;
+    if ((it & 63u) == 0u) chunk.fill(sc, t);
     float alpha, twist;
-    schedule_step(sc, t, alpha, twist);
+    chunk.get(it & 63u, alpha, twist);
     // Sequential conflict-free search: classes in order, a barrier after each.
     if constexpr (FUSE) {
       // EMAX slots, one class each.  On a twist sweep the last class twists
@@ -146,6 +152,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       float cth[RW], tws[RW];
       if (fuse_now) {
         const int slot = tw % kThetaChunk;
+        tw++;
         if (slot == 0) {
           theta_fill(theta_buf, nullptr, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0,
                      a.k0, a.k1, sc.win);
@@ -223,10 +230,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     // directions) come from the LDS tables, refilled by the whole workgroup
     // every kThetaChunk twists.
     if constexpr (FUSE) {
-      if (++sc.phase == sc.period) {
-        sc.phase = 0;
-        tw++;  // done inside the last class
-      }
+      if (++sc.phase == sc.period) sc.phase = 0;  // the twist ran inside the last class
     } else if (sc.period > 0 && ++sc.phase == sc.period) {
       sc.phase = 0;
       const int slot = tw % kThetaChunk;
@@ -520,22 +524,7 @@ int sweeps_lds_st(cosm_state *s, int64_t n_sweeps) {
   }
   a.bar_mask = mask;
   a.fuse_k = s->lds.fuse_k;
-  const Schedule &sc = s->sched;
-  SweepSchedule &w = a.sch;
-  w.grid = sc.grid;
-  w.S = sc.S;
-  const int64_t num = sc.a0_units * (sc.S - s->t) + sc.S / 2;  // numerator at t0 + 1
-  w.q = (int32_t)(num / sc.S);
-  w.r = num % sc.S;
-  w.aq = (int32_t)(sc.a0_units / sc.S);
-  w.ar = sc.a0_units % sc.S;
-  w.alpha_cont_per = sc.alpha0_turns / (float)sc.S;
-  w.twist2 = sc.twist_num2;
-  w.ratio = sc.dwt_ratio;
-  w.period = sc.dwt_period;
-  w.phase = sc.dwt_period > 0 ? (int32_t)(s->t % sc.dwt_period) : 0;
-  w.win = sc.window;
-  w.win2 = sc.window2;
+  a.sch = make_sweep_schedule(s->sched, s->t);
   a.k0 = (uint32_t)(s->seed & 0xffffffffu);
   a.k1 = (uint32_t)(s->seed >> 32);
   a.rid0 = (uint32_t)s->rid0;
