@@ -128,9 +128,11 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
   __syncthreads();
 
   const uint32_t S = (uint32_t)g.S;  // at most 2^31 sweeps
+  ScheduleChunk chunk;
   for (uint32_t t = 1; t - 1 < S; t++) {
+    if (((t - 1) & 63u) == 0u) chunk.fill(sc, t);
     float alpha, twist;
-    schedule_step(sc, alpha, twist);
+    chunk.get((t - 1) & 63u, alpha, twist);
     if (g.total_slots > 0)
       stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
         edge_rows_sets<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, set_bytes,
@@ -145,24 +147,29 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
         __syncthreads();
       }
       tw++;
-      const float *cth = theta_buf + slot * nreps;
-      for (int s0 = tid; s0 < g.n * nsets; s0 += 2 * nth) {
-        uint32_t w[2][W];
+      // set by set (no per-row division), two rows per thread in flight
+      for (int k = 0; k < nsets; k++) {
+        const float *cth = theta_buf + slot * nreps + k * RW;
+        float ck[RW];
 #pragma unroll
-        for (int q = 0; q < 2; q++)
-          if (s0 + q * nth < g.n * nsets) lds_load<W>(lds, s0 + q * nth, w[q]);
+        for (int r = 0; r < RW; r++) ck[r] = cth[r];
+        uint32_t *set = lds + (size_t)k * g.n * W;
+        for (int s0 = tid; s0 < g.n; s0 += 2 * nth) {
+          uint32_t w[2][W];
 #pragma unroll
-        for (int q = 0; q < 2; q++) {
-          const int s = s0 + q * nth;
-          if (s < g.n * nsets) {
-            const int k = s / g.n;
-            float v[RW];
-            F::template unpack<W>(w[q], v);
+          for (int q = 0; q < 2; q++)
+            if (s0 + q * nth < g.n) lds_load<W>(set, s0 + q * nth, w[q]);
 #pragma unroll
-            for (int r = 0; r < RW; r++)
-              if (in_windows(v[r], cth[k * RW + r], sc.win2)) v[r] = F::wrap(v[r] + twist);
-            F::template pack<W>(v, w[q]);
-            lds_store<W>(lds, s, w[q]);
+          for (int q = 0; q < 2; q++) {
+            if (s0 + q * nth < g.n) {
+              float v[RW];
+              F::template unpack<W>(w[q], v);
+#pragma unroll
+              for (int r = 0; r < RW; r++)
+                if (in_windows(v[r], ck[r], sc.win2)) v[r] = F::wrap(v[r] + twist);
+              F::template pack<W>(v, w[q]);
+              lds_store<W>(set, s0 + q * nth, w[q]);
+            }
           }
         }
       }

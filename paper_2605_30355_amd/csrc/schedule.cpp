@@ -317,7 +317,24 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
       L.fuse_k = fk;
       const size_t base = (size_t)(L.total_slots + kStreamRepeat) * nth;
       L.desc.resize(base + (size_t)fk * nth, EdgeDesc{kEmptySlot, 0.0f});
-      for (size_t q = 0; q < rest.size(); q++) L.desc[base + q] = EdgeDesc{(uint32_t)rest[q], 0.0f};
+      // deal the rows by bank residue (row mod G): consecutive lanes take
+      // rows of distinct residues while every residue has rows left
+      std::vector<std::vector<int32_t>> bucket((size_t)G);
+      for (int32_t r : rest) bucket[(size_t)(r % G)].push_back(r);
+      std::vector<size_t> next((size_t)G, 0);
+      for (size_t q = 0; q < rest.size(); q++) {
+        size_t g = q % (size_t)G;
+        if (next[g] == bucket[g].size()) {  // residue exhausted: the fullest one
+          size_t best = 0, left = 0;
+          for (size_t h = 0; h < (size_t)G; h++)
+            if (bucket[h].size() - next[h] > left) {
+              left = bucket[h].size() - next[h];
+              best = h;
+            }
+          g = best;
+        }
+        L.desc[base + q] = EdgeDesc{(uint32_t)bucket[g][next[g]++], 0.0f};
+      }
     }
   }
   return COSM_OK;

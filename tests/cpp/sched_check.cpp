@@ -58,6 +58,7 @@ int main(int argc, char** argv) {
   // last class's rows, every row exactly once (without fuse the twist keeps
   // its own pass)
   int fuse_ok = 1;
+  long fuse_conflicts = 0;
   // the kStreamRepeat slots after the last repeat slots 0, 1, ... mod total
   const size_t rep = (size_t)(L.total_slots + cosm::kStreamRepeat) * L.nth;
   if (L.desc.size() < rep) fuse_ok = 0;
@@ -84,9 +85,21 @@ int main(int argc, char** argv) {
         hit[d.slots]++;
       }
     for (int r = 0; r < n; r++) if (hit[r] != 1) fuse_ok = 0;
+    // bank collisions of those rows within the lane groups of the model
+    for (int q = 0; q < L.fuse_k; q++)
+      for (int lanes : {rlanes, wlanes})
+        for (int g0 = 0; g0 < L.nth; g0 += lanes) {
+          int b[64] = {0};
+          for (int t = g0; t < g0 + lanes && t < L.nth; t++) {
+            auto d = L.desc[rep + (size_t)q * L.nth + t];
+            if (d.slots == cosm::kEmptySlot) continue;
+            for (int w = 0; w < W; w++) b[(d.slots * W + w) % 64]++;
+          }
+          for (int k = 0; k < 64; k++) fuse_conflicts += b[k] > 1 ? b[k] - 1 : 0;
+        }
   } else if (L.desc.size() != rep) {
     fuse_ok = 0;
   }
-  printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d fuse=%d fuse_k=%d fuse_ok=%d\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got), (int)L.fuse, L.fuse_k, fuse_ok);
+  printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d fuse=%d fuse_k=%d fuse_ok=%d fuse_conflicts=%ld\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got), (int)L.fuse, L.fuse_k, fuse_ok, fuse_conflicts);
   return 0;
 }
