@@ -26,6 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 SCHED_GRID = 0
 SCHED_CONTINUOUS = 1
+SCHED_GRID16 = 2  # 16-bit grid: phases on 360 * 2^-16 degrees, steps on 360 * 2^-15
 UPDATE_SCS = 0
 UPDATE_FULL_GRADIENT = 1
 
@@ -78,6 +79,9 @@ def lib():
                                       ctypes.c_int32, ctypes.c_int32, P]
         L.orc_theta_ref.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
         L.orc_theta_ref.restype = ctypes.c_double
+        L.orc_theta_ref_sched.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_int32]
+        L.orc_theta_ref_sched.restype = ctypes.c_double
         L.orc_twist_direction.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
         L.orc_twist_direction.restype = ctypes.c_int32
         L.orc_sweeps.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Params),
@@ -181,8 +185,8 @@ def bisector(params: Params, idx: int) -> float:
     return lib().orc_bisector(params.struct(), params.schedule, idx)
 
 
-def theta_ref(seed: int, t: int, rid: int) -> float:
-    return lib().orc_theta_ref(seed, t, rid)
+def theta_ref(seed: int, t: int, rid: int, schedule=SCHED_GRID) -> float:
+    return lib().orc_theta_ref_sched(seed, t, rid, schedule)
 
 
 def twist_direction(seed: int, t: int, rid: int) -> int:

@@ -139,10 +139,19 @@ int32_t orc_is_proper_colouring(int32_t n, int64_t m, const int32_t *eu, const i
  * still on the grid. */
 static const double TWO_POW_23 = 8388608.0;
 static const double TWO_POW_22 = 4194304.0;
+static const double TWO_POW_16 = 65536.0;
+static const double TWO_POW_15 = 32768.0;
+
+/* The 16-bit grid (ORC_SCHED_GRID16): phases and angles are multiples of
+ * 360 * 2^-16 degrees and steps of 360 * 2^-15, the same construction one
+ * level coarser, so that phases fit 16-bit fixed point exactly. */
+static double step_units_per_turn(int32_t schedule) {
+  return schedule == ORC_SCHED_GRID16 ? TWO_POW_15 : TWO_POW_22;
+}
 
 static int64_t alpha0_grid_units(const orc_params *p) {
-  /* alpha0 in units of 360 * 2^-22 degrees, nearest integer */
-  return (int64_t)floor(p->alpha0_deg / 360.0 * TWO_POW_22 + 0.5);
+  /* alpha0 in step units (360 * 2^-22 or 2^-15 degrees), nearest integer */
+  return (int64_t)floor(p->alpha0_deg / 360.0 * step_units_per_turn(p->schedule) + 0.5);
 }
 
 /* Linear ramp alpha0 -> 0, constant within a sweep (Sec. II-B, Appendix B):
@@ -151,10 +160,10 @@ static int64_t alpha0_grid_units(const orc_params *p) {
  * integer arithmetic. */
 double orc_alpha(const orc_params *p, int64_t t) {
   int64_t S = p->sweeps;
-  if (p->schedule == ORC_SCHED_GRID) {
+  if (p->schedule != ORC_SCHED_CONTINUOUS) {
     int64_t a0 = alpha0_grid_units(p);
     int64_t units = (a0 * (S - t + 1) + S / 2) / S;
-    return (double)units * 360.0 / TWO_POW_22;
+    return (double)units * 360.0 / step_units_per_turn(p->schedule);
   }
   return p->alpha0_deg * (double)(S - t + 1) / (double)S;
 }
@@ -163,7 +172,7 @@ double orc_alpha(const orc_params *p, int64_t t) {
  * 100 bisectors spaced by 1.8 degrees).  Grid schedule: rounded half-up to q. */
 double orc_bisector(const orc_params *p, int32_t schedule, int32_t idx) {
   int64_t B = p->n_bisectors;
-  if (schedule == ORC_SCHED_GRID) {
+  if (schedule != ORC_SCHED_CONTINUOUS) {
     int64_t units = ((int64_t)idx * (int64_t)TWO_POW_23 + B) / (2 * B);
     return (double)units * 360.0 / TWO_POW_23;
   }
@@ -181,6 +190,8 @@ void orc_init_phases(int32_t n, uint64_t seed, int64_t rid0, int32_t R, int32_t 
       double v;
       if (schedule == ORC_SCHED_GRID)
         v = (double)(w >> 9) * 360.0 / TWO_POW_23;
+      else if (schedule == ORC_SCHED_GRID16)
+        v = (double)(w >> 16) * 360.0 / TWO_POW_16;
       else
         v = (double)(w >> 8) * 360.0 / (2.0 * TWO_POW_23);
       x[(size_t)r * n + i] = v;
@@ -193,6 +204,12 @@ void orc_init_phases(int32_t n, uint64_t seed, int64_t rid0, int32_t R, int32_t 
 double orc_theta_ref(uint64_t seed, int64_t t, int64_t rid) {
   uint32_t w = philox_word0(seed, 0u, (uint32_t)t, (uint32_t)rid, ORC_TAG_DWT);
   return (double)(w >> 9) * 360.0 / TWO_POW_23;
+}
+
+double orc_theta_ref_sched(uint64_t seed, int64_t t, int64_t rid, int32_t schedule) {
+  if (schedule != ORC_SCHED_GRID16) return orc_theta_ref(seed, t, rid);
+  uint32_t w = philox_word0(seed, 0u, (uint32_t)t, (uint32_t)rid, ORC_TAG_DWT);
+  return (double)(w >> 16) * 360.0 / TWO_POW_16;
 }
 
 /* Direction of the twist.  Without bias fields one direction suffices
@@ -291,7 +308,7 @@ static void run_replica(const orc_problem *pb, const orc_params *p, uint64_t see
      * pre-twist phases) rotate by ratio * alpha_t, in the + direction without
      * bias fields and in a drawn direction with them. */
     if (p->dwt_period > 0 && t % p->dwt_period == 0) {
-      const double theta = orc_theta_ref(seed, t, rid);
+      const double theta = orc_theta_ref_sched(seed, t, rid, p->schedule);
       const double w = p->dwt_window_deg;
       const double dir = pb->h != NULL ? (double)orc_twist_direction(seed, t, rid) : 1.0;
       const double twist = dir * p->dwt_ratio * alpha;

@@ -26,7 +26,9 @@
  *
  * Phase unit: degrees, FP64.  "Grid" schedule: every phase, step and angle is a
  * multiple of q = 360 * 2^-23 degrees, so every operation below is exact in
- * FP64 (and, scaled to turns, in FP32).
+ * FP64 (and, scaled to turns, in FP32).  "Grid16" is the same construction on
+ * q16 = 360 * 2^-16 degrees (steps on 2 q16), for phases held in 16-bit fixed
+ * point; bisectors stay on the q grid.
  */
 #ifndef COSM_ORACLE_H
 #define COSM_ORACLE_H
@@ -36,7 +38,7 @@
 extern "C" {
 #endif
 
-enum { ORC_SCHED_GRID = 0, ORC_SCHED_CONTINUOUS = 1 };
+enum { ORC_SCHED_GRID = 0, ORC_SCHED_CONTINUOUS = 1, ORC_SCHED_GRID16 = 2 };
 enum { ORC_UPDATE_SCS = 0, ORC_UPDATE_FULL_GRADIENT = 1 };
 
 /* Counter words that separate the random streams (last Philox counter word). */
@@ -90,8 +92,10 @@ double orc_bisector(const orc_params *p, int32_t schedule, int32_t idx);
 void orc_init_phases(int32_t n, uint64_t seed, int64_t rid0, int32_t R, int32_t schedule,
                      double *x);
 
-/* DWT reference angle for (sweep t, replica rid), degrees. */
+/* DWT reference angle for (sweep t, replica rid), degrees (q grid). */
 double orc_theta_ref(uint64_t seed, int64_t t, int64_t rid);
+/* The same draw on the schedule's grid: the top 16 bits for ORC_SCHED_GRID16. */
+double orc_theta_ref_sched(uint64_t seed, int64_t t, int64_t rid, int32_t schedule);
 
 /* Twist direction (+1 / -1) for (sweep t, replica rid), used only with bias
  * fields; word 1 of the reference angle's Philox draw. */
