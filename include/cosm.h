@@ -56,14 +56,21 @@ enum {
 /* ---- enumerations ---------------------------------------------------------- */
 enum { COSM_COLOR_GREEDY = 0, COSM_COLOR_MISRA_GRIES = 1, COSM_COLOR_TORUS = 2,
        COSM_COLOR_BALANCED = 3, COSM_COLOR_MINIMUM = 4 };
-enum { COSM_STORE_FP32 = 0, COSM_STORE_FP16 = 1, COSM_STORE_BF16 = 2 };
+/* Phase storage.  FP32: x in [0, 1) turn.  FP16 / BF16: the centred value
+ * x - 1/2, FP32 arithmetic, rounded on every store.  FIX16: x in 16-bit fixed
+ * point (units of 2^-16 turn), wrapping by integer overflow; needs the GRID
+ * schedule, which it runs on the 2^-16 turn grid (steps on 2^-15, initial
+ * phases and twist angles the top 16 bits of the same draws), so trajectories
+ * are exact; the window must be a multiple of 2^-16 turn. */
+enum { COSM_STORE_FP32 = 0, COSM_STORE_FP16 = 1, COSM_STORE_BF16 = 2, COSM_STORE_FIX16 = 3 };
 /* Where a replica's phases live during a sweep.  LDS: a workgroup holds whole
  * replicas in LDS for all sweeps of a call.  HBM: phases stay in device memory,
  * one launch per colour class.  PLAIN: one replica per launch, one launch per
  * colour class (the unbatched baseline). */
 enum { COSM_RES_AUTO = 0, COSM_RES_LDS = 1, COSM_RES_HBM = 2, COSM_RES_PLAIN = 3 };
-/* GRID: every phase, step and angle is a multiple of 2^-23 turn, so FP32 sweeps
- * are exact.  CONTINUOUS: the literal ramp alpha0 (S - t + 1) / S in FP32. */
+/* GRID: every phase, step and angle is a multiple of 2^-23 turn (2^-16 with
+ * FIX16 storage), so sweeps are exact; the window must be a multiple of 2^-22
+ * turn.  CONTINUOUS: the literal ramp alpha0 (S - t + 1) / S in FP32. */
 enum { COSM_SCHED_GRID = 0, COSM_SCHED_CONTINUOUS = 1 };
 /* SCS: Eqs. (12)-(13), classes one after another.  FULL_GRADIENT: Eq. (8), all
  * edges read the same state (the "without SCS" variant of Table VII). */
@@ -87,7 +94,7 @@ typedef struct {
   int32_t n_bisectors;      /* B (100 in Table IX); forced to 1 when h is given */
   int64_t sweeps_per_trial; /* S: the schedule length */
   int32_t schedule;         /* COSM_SCHED_* */
-  int32_t storage;          /* COSM_STORE_*: phase storage; arithmetic is FP32 */
+  int32_t storage;          /* COSM_STORE_*: phase storage (FIX16: integer arithmetic) */
   int32_t residency;        /* COSM_RES_* */
   int32_t replicas_per_wg;  /* LDS form: replicas per workgroup; 0 = autotune */
   int32_t threads_per_wg;   /* LDS form: threads per workgroup; 0 = autotune */

@@ -22,7 +22,7 @@ void clear_error() { g_last_error.clear(); }
 
 namespace {
 
-int storage_bytes(int32_t storage) { return storage == COSM_STORE_FP32 ? 4 : 2; }
+int storage_bytes(int32_t storage) { return storage == COSM_STORE_FP32 ? 4 : 2; }  // FP16, BF16, FIX16: 2
 int per_word(int32_t storage) { return storage == COSM_STORE_FP32 ? 1 : 2; }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -100,7 +100,9 @@ int check_params(const cosm_params *p) {
   if (p->sweeps_per_trial < 1 || p->sweeps_per_trial > ((int64_t)1 << 31))
     return bad("sweeps_per_trial must be in [1, 2^31]");
   if (p->schedule != COSM_SCHED_GRID && p->schedule != COSM_SCHED_CONTINUOUS) return bad("bad schedule");
-  if (p->storage < COSM_STORE_FP32 || p->storage > COSM_STORE_BF16) return bad("bad storage");
+  if (p->storage < COSM_STORE_FP32 || p->storage > COSM_STORE_FIX16) return bad("bad storage");
+  if (p->storage == COSM_STORE_FIX16 && p->schedule != COSM_SCHED_GRID)
+    return bad("FIX16 storage needs the GRID schedule");
   if (p->residency < COSM_RES_AUTO || p->residency > COSM_RES_PLAIN) return bad("bad residency");
   if (p->update != COSM_UPDATE_SCS && p->update != COSM_UPDATE_FULL_GRADIENT) return bad("bad update");
   if (p->readout != COSM_READOUT_BISECTORS && p->readout != COSM_READOUT_OPTIMAL)
@@ -120,16 +122,28 @@ int make_schedule(const cosm_params &p, int32_t max_abs_J, Schedule *sc) {
   if (p.alpha0_deg * p.dwt_ratio >= 360.0)
     return set_error(COSM_ERANGE, "dwt_ratio * alpha0 must stay below a full turn");
   sc->grid = p.schedule == COSM_SCHED_GRID;
+  const bool fix16 = p.storage == COSM_STORE_FIX16;
+  // grid of the phases (2^-bits turn) and of the steps (twice as coarse)
+  const int bits = fix16 ? 16 : 23;
+  const double step_per_turn = std::ldexp(1.0, bits - 1);
+  sc->aunit = (float)std::ldexp(1.0, 1 - bits);
+  sc->tunit = (float)std::ldexp(1.0, -bits);
+  sc->tshift = 32 - bits;
+  sc->tscale = (float)std::ldexp(1.0, -bits);
+  sc->ishift = sc->grid ? 32 - bits : 8;
+  sc->iscale = sc->grid ? (float)std::ldexp(1.0, -bits) : (float)std::ldexp(1.0, -24);
   sc->S = p.sweeps_per_trial;
-  sc->a0_units = (int64_t)std::floor(p.alpha0_deg / 360.0 * kTwo22 + 0.5);
+  sc->a0_units = (int64_t)std::floor(p.alpha0_deg / 360.0 * step_per_turn + 0.5);
   const double r2 = 2.0 * p.dwt_ratio;
   sc->twist_num2 = (int32_t)std::llround(r2);
-  const double w_units = p.dwt_window_deg / 360.0 * kTwo23;
+  // the window on the step grid keeps the twist's membership test exact
+  const double w_units = p.dwt_window_deg / 360.0 * (fix16 ? std::ldexp(1.0, 16) : step_per_turn);
   if (sc->grid) {
     if (std::fabs(r2 - sc->twist_num2) > 1e-12)
       return set_error(COSM_ERANGE, "GRID schedule needs 2 * dwt_ratio to be an integer");
     if (std::fabs(w_units - std::round(w_units)) > 1e-6)
-      return set_error(COSM_ERANGE, "GRID schedule needs the window on the 2^-23 turn grid");
+      return set_error(COSM_ERANGE, fix16 ? "FIX16 needs the window on the 2^-16 turn grid"
+                                          : "GRID schedule needs the window on the 2^-22 turn grid");
   }
   sc->alpha0_turns = (float)(p.alpha0_deg / 360.0);
   sc->dwt_ratio = (float)p.dwt_ratio;

@@ -42,6 +42,8 @@ struct GraphDev {
   uint32_t k0, k1, rid0;
   ReadoutArgs ro;
   int32_t grid;
+  uint32_t ishift;            // initial phases: (draw >> ishift) * iscale
+  float iscale;
 };
 
 struct Item {
@@ -81,7 +83,7 @@ __global__ void __launch_bounds__(256) k_batch_init(const GraphDev *graphs, cons
     const int64_t loc = idx - phase_prefix[lo];
     const int32_t i = (int32_t)(loc / g.R), r = (int32_t)(loc % g.R);
     const uint32_t w = philox_first_word((uint32_t)i, 0u, g.rid0 + (uint32_t)r, kTagInit, g.k0, g.k1);
-    const float x = g.grid ? (float)(w >> 9) * kQ23 : (float)(w >> 8) * kQ24;
+    const float x = (float)(w >> g.ishift) * g.iscale;
     F::store_elem(g.phases, (size_t)loc, F::from_turn(x));
   }
 }
@@ -143,7 +145,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
       const int slot = tw % nch;
       if (slot == 0) {
         theta_fill(theta_buf, nullptr, nch, nreps, t, sc.period, g.rid0 + (uint32_t)it.r0, g.k0,
-                   g.k1, sc.win);
+                   g.k1, sc.win, sc.tshift, sc.tscale);
         __syncthreads();
       }
       tw++;
@@ -303,7 +305,7 @@ int cosm_batch_create(cosm_batch **out, int32_t storage, int32_t max_graphs, int
   clear_error();
   if (out == nullptr) return set_error(COSM_EINVAL, "out must not be NULL");
   *out = nullptr;
-  if (storage < COSM_STORE_FP32 || storage > COSM_STORE_BF16) return set_error(COSM_EINVAL, "bad storage");
+  if (storage < COSM_STORE_FP32 || storage > COSM_STORE_FIX16) return set_error(COSM_EINVAL, "bad storage");
   if (max_graphs < 1 || max_n < 1 || max_n > 65536 || max_bisectors < 1 || max_bisectors > 32767)
     return set_error(COSM_EINVAL, "bad batch limits");
   cosm_batch *b = new cosm_batch();
@@ -356,7 +358,8 @@ int cosm_batch_create(cosm_batch **out, int32_t storage, int32_t max_graphs, int
   switch (storage) {
     case COSM_STORE_FP32: set_attrs<COSM_STORE_FP32>(b); break;
     case COSM_STORE_FP16: set_attrs<COSM_STORE_FP16>(b); break;
-    default: set_attrs<COSM_STORE_BF16>(b); break;
+    case COSM_STORE_BF16: set_attrs<COSM_STORE_BF16>(b); break;
+    default: set_attrs<COSM_STORE_FIX16>(b); break;
   }
   *out = b;
   return COSM_OK;
@@ -478,6 +481,8 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
   d.k1 = (uint32_t)(seed >> 32);
   d.rid0 = 0;
   d.grid = sc.grid;
+  d.ishift = (uint32_t)sc.ishift;
+  d.iscale = sc.iscale;
   ReadoutArgs &ro = d.ro;
   ro.phases = d.phases;
   ro.eu = reinterpret_cast<const int32_t *>(base + o_eu);
@@ -615,7 +620,8 @@ int cosm_batch_run(cosm_batch *b, const int32_t *graph_ids, int32_t count) {
     switch (b->storage) {
       case COSM_STORE_FP32: enqueue_run<COSM_STORE_FP32>(b); break;
       case COSM_STORE_FP16: enqueue_run<COSM_STORE_FP16>(b); break;
-      default: enqueue_run<COSM_STORE_BF16>(b); break;
+      case COSM_STORE_BF16: enqueue_run<COSM_STORE_BF16>(b); break;
+      default: enqueue_run<COSM_STORE_FIX16>(b); break;
     }
     COSM_HIP_CHECK(hipStreamEndCapture(b->stream, &b->graph));
     COSM_HIP_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));

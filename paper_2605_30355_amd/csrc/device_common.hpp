@@ -166,6 +166,44 @@ struct Fmt<COSM_STORE_FP16> : Fmt16<COSM_STORE_FP16> {};
 template <>
 struct Fmt<COSM_STORE_BF16> : Fmt16<COSM_STORE_BF16> {};
 
+// 16-bit fixed point: the stored integer k is x = k 2^-16 turn.  As a value
+// x in [0, 1) is exact in FP32, so every FP32 form below works unchanged (on
+// the 2^-16 grid its adds, fract and comparisons are exact); the LDS sweep
+// also has an integer form (edge_rows_fix16).
+template <>
+struct Fmt<COSM_STORE_FIX16> {
+  static constexpr int kPerWord = 2;
+  __device__ __forceinline__ static float wrap(float v) { return fract1(v); }
+  __device__ __forceinline__ static float from_turn(float x) { return x; }
+  __device__ __forceinline__ static float to_turn(float v) { return v; }
+  __device__ __forceinline__ static float dec(uint32_t bits16) {
+    return (float)bits16 * (1.0f / 65536.0f);
+  }
+  // nearest grid point, 1 turn wrapping to 0
+  __device__ __forceinline__ static uint32_t enc(float v) {
+    return (uint32_t)__builtin_rintf(v * 65536.0f) & 0xffffu;
+  }
+  __device__ __forceinline__ static float load_elem(const void *p, size_t i) {
+    return dec(as_global(static_cast<const uint16_t *>(p))[i]);
+  }
+  __device__ __forceinline__ static void store_elem(void *p, size_t i, float v) {
+    as_global_mut(static_cast<uint16_t *>(p))[i] = (uint16_t)enc(v);
+  }
+  template <int W>
+  __device__ __forceinline__ static void unpack(const uint32_t (&w)[W], float (&v)[2 * W]) {
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      v[2 * k] = dec(w[k] & 0xffffu);
+      v[2 * k + 1] = dec(w[k] >> 16);
+    }
+  }
+  template <int W>
+  __device__ __forceinline__ static void pack(const float (&v)[2 * W], uint32_t (&w)[W]) {
+#pragma unroll
+    for (int k = 0; k < W; k++) w[k] = enc(v[2 * k]) | (enc(v[2 * k + 1]) << 16);
+  }
+};
+
 // LDS row access with the widest ds_read / ds_write for W words.
 template <int W>
 __device__ __forceinline__ void lds_load(const uint32_t *base, int slot, uint32_t (&w)[W]) {
@@ -215,11 +253,9 @@ __device__ __forceinline__ bool in_windows(float v, float c, float win2) {
   return fract1(__builtin_fmaf(2.0f, v, -c)) < win2;
 }
 
-__device__ __forceinline__ float theta_turns(uint32_t t, uint32_t rid, uint32_t k0, uint32_t k1) {
-  return (float)(philox_first_word(0u, t, rid, kTagDwt, k0, k1) >> 9) * kQ23;
-}
 
-// Per-sweep schedule evaluated on the device.  Grid: alpha = q * 2^-22 with
+// Per-sweep schedule evaluated on the device.  Grid: alpha = q * aunit (2^-22
+// turn; 2^-15 for FIX16) with
 // q = floor(num / S), num = a0 (S - t + 1) + S/2, stepped by subtraction with
 // a 32-bit remainder (S <= 2^31; q < 2^22 and 2 rho q < 2^23, so the int32
 // products and conversions are exact).  Few scalar instructions per sweep:
@@ -234,7 +270,10 @@ struct SweepSchedule {
   float ratio;           // continuous
   int32_t period, phase; // twist when ++phase == period
   float win, win2;
-  int64_t a0;            // grid: alpha0 in units of 2^-22 turn
+  int64_t a0;            // grid: alpha0 in step units
+  float aunit, tunit;    // grid: turns per step unit and per twist unit
+  uint32_t tshift;       // reference angle: (draw >> tshift) * tscale
+  float tscale;
 };
 
 // alpha_t and the twist of sweep t (1 <= t <= S) computed directly, as the
@@ -244,8 +283,8 @@ __device__ __forceinline__ void schedule_at(const SweepSchedule &sc, uint32_t t,
   const uint32_t u = sc.S - t + 1u;  // S - t + 1 >= 1
   if (sc.grid) {
     const int32_t q = (int32_t)((sc.a0 * (int64_t)u + (int64_t)(sc.S / 2u)) / (int64_t)sc.S);
-    alpha = (float)q * kQ22;
-    twist = (float)(sc.twist2 * q) * kQ23;
+    alpha = (float)q * sc.aunit;
+    twist = (float)(sc.twist2 * q) * sc.tunit;
   } else {
     alpha = (float)u * sc.alpha_cont_per;
     twist = sc.ratio * alpha;
@@ -272,8 +311,8 @@ struct ScheduleChunk {
 // ramp); advances to the sweep after it.
 __device__ __forceinline__ void schedule_step(SweepSchedule &sc, float &alpha, float &twist) {
   if (sc.grid) {
-    alpha = (float)sc.q * kQ22;
-    twist = (float)(sc.twist2 * sc.q) * kQ23;
+    alpha = (float)sc.q * sc.aunit;
+    twist = (float)(sc.twist2 * sc.q) * sc.tunit;
     const bool borrow = sc.r < sc.ar;
     sc.r = sc.r - sc.ar + (borrow ? sc.S : 0u);
     sc.q -= sc.aq + (borrow ? 1 : 0);
@@ -303,6 +342,10 @@ SweepSchedule make_sweep_schedule(const Schedule &sc, int64_t t_done) {
   w.win = sc.window;
   w.win2 = sc.window2;
   w.a0 = sc.a0_units;
+  w.aunit = sc.aunit;
+  w.tunit = sc.tunit;
+  w.tshift = (uint32_t)sc.tshift;
+  w.tscale = sc.tscale;
   return w;
 }
 
@@ -313,12 +356,13 @@ SweepSchedule make_sweep_schedule(const Schedule &sc, int64_t t_done) {
 // of the workgroup takes part; the caller synchronises.
 __device__ __forceinline__ void theta_fill(float *table, float *dirs, int nch, int nrep,
                                            uint32_t t_first, int32_t period, uint32_t rid_base,
-                                           uint32_t k0, uint32_t k1, float win) {
+                                           uint32_t k0, uint32_t k1, float win, uint32_t tshift,
+                                           float tscale) {
   for (int i = threadIdx.x; i < nch * nrep; i += blockDim.x) {
     const int q = i / nrep, k = i - q * nrep;
     const uint2 w = philox_words01(0u, t_first + (uint32_t)(q * period),
                                    rid_base + (uint32_t)k, kTagDwt, k0, k1);
-    table[i] = 2.0f * ((float)(w.x >> 9) * kQ23) - win;
+    table[i] = 2.0f * ((float)(w.x >> tshift) * tscale) - win;
     if (dirs != nullptr) dirs[i] = (w.y >> 31) ? -1.0f : 1.0f;
   }
 }

@@ -55,7 +55,7 @@ constexpr double kTwo22 = 4194304.0;
 struct Schedule {
   int32_t grid;          // COSM_SCHED_GRID ?
   int64_t S;             // schedule length
-  // grid: alpha_units(t) = floor((a0 * (S - t + 1) + S/2) / S), units of 2^-22 turn
+  // grid: alpha_units(t) = floor((a0 * (S - t + 1) + S/2) / S), units of aunit
   int64_t a0_units;
   int32_t twist_num2;    // 2 * dwt_ratio (grid)
   // continuous
@@ -64,6 +64,11 @@ struct Schedule {
   int32_t dwt_period;    // 0: never
   float window2;         // 2 * window width in turns (membership threshold)
   float window;          // window width in turns
+  // grid units: alpha = q * aunit, twist = twist_num2 * q * tunit; reference
+  // angles (w >> tshift) * tscale and initial phases (w >> ishift) * iscale
+  // from a 32-bit draw w (2^-23 grid; 2^-16 for FIX16; 24-bit continuous init)
+  float aunit, tunit, tscale, iscale;
+  int32_t tshift, ishift;
 };
 
 // EINVAL unless every field of *p is in range.

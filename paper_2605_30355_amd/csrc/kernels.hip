@@ -40,12 +40,13 @@ struct LdsArgs {
 // ---------------------------------------------------------------------------
 template <int ST>
 __global__ void __launch_bounds__(256) k_init(void *phases, int32_t n, int32_t R, uint32_t k0,
-                                              uint32_t k1, uint32_t rid0, int32_t grid) {
+                                              uint32_t k1, uint32_t rid0, uint32_t shift,
+                                              float scale) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * R) return;
   const int32_t i = (int32_t)(idx / R), r = (int32_t)(idx % R);
   const uint32_t w = philox_first_word((uint32_t)i, 0u, rid0 + (uint32_t)r, kTagInit, k0, k1);
-  const float x = grid ? (float)(w >> 9) * kQ23 : (float)(w >> 8) * kQ24;
+  const float x = (float)(w >> shift) * scale;  // the top 32 - shift bits
   Fmt<ST>::store_elem(phases, (size_t)idx, Fmt<ST>::from_turn(x));
 }
 
@@ -155,7 +156,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         tw++;
         if (slot == 0) {
           theta_fill(theta_buf, nullptr, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0,
-                     a.k0, a.k1, sc.win);
+                     a.k0, a.k1, sc.win, sc.tshift, sc.tscale);
           __syncthreads();
         }
 #pragma unroll
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       const int slot = tw % kThetaChunk;
       if (slot == 0) {
         theta_fill(theta_buf, a.h_slot != nullptr ? dir_buf : nullptr, kThetaChunk, RW, t,
-                   sc.period, a.rid0 + (uint32_t)r0, a.k0, a.k1, sc.win);
+                   sc.period, a.rid0 + (uint32_t)r0, a.k0, a.k1, sc.win, sc.tshift, sc.tscale);
         __syncthreads();
       }
       tw++;
@@ -313,7 +314,8 @@ template <int ST>
 __global__ void __launch_bounds__(256) k_dwt_hbm(void *phases, int32_t n, int32_t R, int32_t rbeg,
                                                  int32_t rcount, int32_t strip, uint32_t t,
                                                  float twist, float win, float win2, uint32_t k0,
-                                                 uint32_t k1, uint32_t rid0, int32_t drawn_dir) {
+                                                 uint32_t k1, uint32_t rid0, int32_t drawn_dir,
+                                                 uint32_t tshift, float tscale) {
   using F = Fmt<ST>;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t rchunks = (rcount + 63) / 64;
@@ -324,7 +326,7 @@ __global__ void __launch_bounds__(256) k_dwt_hbm(void *phases, int32_t n, int32_
   if (rloc >= rcount || i0 >= n) return;
   const int32_t r = rbeg + rloc;
   const uint2 wd = philox_words01(0u, t, rid0 + (uint32_t)r, kTagDwt, k0, k1);
-  const float c = 2.0f * ((float)(wd.x >> 9) * kQ23) - win;
+  const float c = 2.0f * ((float)(wd.x >> tshift) * tscale) - win;
   if (drawn_dir && (wd.y >> 31)) twist = -twist;  // with bias fields: drawn direction
   const int64_t i1 = min((int64_t)n, i0 + strip);
   for (int64_t i = i0; i < i1; i++) {
@@ -459,7 +461,7 @@ int launch_check(const char *what) {
 float host_alpha(const Schedule &sc, int64_t t) {
   if (sc.grid) {
     const int64_t q = (sc.a0_units * (sc.S - t + 1) + sc.S / 2) / sc.S;
-    return (float)q * kQ22;
+    return (float)q * sc.aunit;
   }
   return (float)(sc.S - t + 1) * (sc.alpha0_turns / (float)sc.S);
 }
@@ -467,7 +469,7 @@ float host_alpha(const Schedule &sc, int64_t t) {
 float host_twist(const Schedule &sc, int64_t t) {
   if (sc.grid) {
     const int64_t q = (sc.a0_units * (sc.S - t + 1) + sc.S / 2) / sc.S;
-    return (float)(sc.twist_num2 * q) * kQ23;
+    return (float)(sc.twist_num2 * q) * sc.tunit;
   }
   return sc.dwt_ratio * host_alpha(sc, t);
 }
@@ -546,7 +548,7 @@ int dwt_hbm_st(cosm_state *s, int64_t t, int32_t rbeg, int32_t rcount) {
   hipLaunchKernelGGL((k_dwt_hbm<ST>), grid, block, 0, s->stream, s->d.phases, s->n, s->R, rbeg,
                      rcount, strip, (uint32_t)t, host_twist(sc, t), sc.window, sc.window2,
                      (uint32_t)(s->seed & 0xffffffffu), (uint32_t)(s->seed >> 32),
-                     (uint32_t)s->rid0, (int32_t)s->has_h);
+                     (uint32_t)s->rid0, (int32_t)s->has_h, (uint32_t)sc.tshift, sc.tscale);
   return launch_check("k_dwt_hbm");
 }
 
@@ -643,7 +645,8 @@ int init_st(cosm_state *s) {
   const int64_t tot = (int64_t)s->n * s->R;
   hipLaunchKernelGGL((k_init<ST>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s->stream,
                      s->d.phases, s->n, s->R, (uint32_t)(s->seed & 0xffffffffu),
-                     (uint32_t)(s->seed >> 32), (uint32_t)s->rid0, s->sched.grid);
+                     (uint32_t)(s->seed >> 32), (uint32_t)s->rid0, (uint32_t)s->sched.ishift,
+                     s->sched.iscale);
   return launch_check("k_init");
 }
 
@@ -653,6 +656,7 @@ int dispatch_storage(int storage, A &&...args) {
     case COSM_STORE_FP32: return Fn<COSM_STORE_FP32>::run(args...);
     case COSM_STORE_FP16: return Fn<COSM_STORE_FP16>::run(args...);
     case COSM_STORE_BF16: return Fn<COSM_STORE_BF16>::run(args...);
+    case COSM_STORE_FIX16: return Fn<COSM_STORE_FIX16>::run(args...);
   }
   return set_error(COSM_EINVAL, "unknown storage format");
 }
