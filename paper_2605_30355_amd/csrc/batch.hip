@@ -152,9 +152,12 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
       // set by set (no per-row division), two rows per thread in flight
       for (int k = 0; k < nsets; k++) {
         const float *cth = theta_buf + slot * nreps + k * RW;
-        float ck[RW];
+        float ck[RW], tws[RW];
 #pragma unroll
-        for (int r = 0; r < RW; r++) ck[r] = cth[r];
+        for (int r = 0; r < RW; r++) {
+          ck[r] = cth[r];
+          tws[r] = twist;
+        }
         uint32_t *set = lds + (size_t)k * g.n * W;
         for (int s0 = tid; s0 < g.n; s0 += 2 * nth) {
           uint32_t w[2][W];
@@ -164,12 +167,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
 #pragma unroll
           for (int q = 0; q < 2; q++) {
             if (s0 + q * nth < g.n) {
-              float v[RW];
-              F::template unpack<W>(w[q], v);
-#pragma unroll
-              for (int r = 0; r < RW; r++)
-                if (in_windows(v[r], ck[r], sc.win2)) v[r] = F::wrap(v[r] + twist);
-              F::template pack<W>(v, w[q]);
+              twist_words<ST, W>(w[q], ck, tws, sc.win2);
               lds_store<W>(set, s0 + q * nth, w[q]);
             }
           }

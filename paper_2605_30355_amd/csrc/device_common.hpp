@@ -392,21 +392,47 @@ __device__ __forceinline__ void lds_store_at(uint32_t *base, uint32_t byte, cons
   }
 }
 
+// Eq. (6) on the W words of an edge's two rows (every replica they hold).
+// FIX16: two replicas per word in 16-bit lanes, packed integer arithmetic; the
+// lane difference u - v wraps to the signed difference in [-1/2, 1/2) turn,
+// whose sign bit selects -step or +step, and the updates wrap by overflow.
+// Other formats: unpack, the FP32 update, pack.
+template <int ST, int W>
+__device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
+  if constexpr (ST == COSM_STORE_FIX16) {
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    // aJ is a multiple of 2^-16 turn below one turn: the conversion is exact
+    const uint32_t st = (uint32_t)(int32_t)(aJ * 65536.0f) & 0xffffu;
+    const u16x2 step = __builtin_bit_cast(u16x2, st | (st << 16));
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      const u16x2 u = __builtin_bit_cast(u16x2, wu[k]), v = __builtin_bit_cast(u16x2, wv[k]);
+      const u16x2 m = (u16x2)((s16x2)(u - v) >> (short)15);  // 0xffff where negative
+      const u16x2 dl = (step ^ m) - m;                        // +step or -step
+      wu[k] = __builtin_bit_cast(uint32_t, (u16x2)(u - dl));
+      wv[k] = __builtin_bit_cast(uint32_t, (u16x2)(v + dl));
+    }
+  } else {
+    using F = Fmt<ST>;
+    constexpr int RW = W * F::kPerWord;
+    float xu[RW], xv[RW];
+    F::template unpack<W>(wu, xu);
+    F::template unpack<W>(wv, xv);
+#pragma unroll
+    for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
+    F::template pack<W>(xu, wu);
+    F::template pack<W>(xv, wv);
+  }
+}
+
 // Eq. (6) on every replica of one edge: rows at byte offsets bu, bv.
 template <int ST, int W>
 __device__ __forceinline__ void edge_rows(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ) {
-  using F = Fmt<ST>;
-  constexpr int RW = W * F::kPerWord;
   uint32_t wu[W], wv[W];
   lds_load_at<W>(lds, bu, wu);
   lds_load_at<W>(lds, bv, wv);
-  float xu[RW], xv[RW];
-  F::template unpack<W>(wu, xu);
-  F::template unpack<W>(wv, xv);
-#pragma unroll
-  for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
-  F::template pack<W>(xu, wu);
-  F::template pack<W>(xv, wv);
+  update_words<ST, W>(wu, wv, aJ);
   lds_store_at<W>(lds, bu, wu);
   lds_store_at<W>(lds, bv, wv);
 }
@@ -421,34 +447,62 @@ __device__ __forceinline__ void twist_values(float (&x)[RW], const float (&c)[RW
     if (in_windows(x[k], c[k], win2)) x[k] = Fmt<ST>::wrap(x[k] + tws[k]);
 }
 
+// The twist on the W words of one row.  FIX16: packed 16-bit integers; with
+// t = (2x - c) mod 1 turn in 16-bit lanes, a lane is in the windows iff
+// t < 2w: t is moved to signed range (top bit flipped) and compared with
+// 2w - 1/2 turn by a saturating subtraction, whose sign gives the mask.
+// Other formats: unpack, twist_values, pack.
+template <int ST, int W>
+__device__ __forceinline__ void twist_words(uint32_t (&w)[W],
+                                            const float (&c)[W * Fmt<ST>::kPerWord],
+                                            const float (&tws)[W * Fmt<ST>::kPerWord],
+                                            float win2) {
+  if constexpr (ST == COSM_STORE_FIX16) {
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    const uint32_t W2 = (uint32_t)(win2 * 65536.0f);  // 2w in 2^-16 turn, <= 2^16
+    const bool all = W2 >= 65536u;                    // w = 1/2 turn: every phase
+    const uint32_t k = (W2 - 32768u) & 0xffffu;
+    const s16x2 k2 = __builtin_bit_cast(s16x2, k | (k << 16));
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+      // c and the twist are multiples of 2^-16 turn: exact conversions
+      const uint32_t c2 = ((uint32_t)(int32_t)(c[2 * q] * 65536.0f) & 0xffffu) |
+                          ((uint32_t)(int32_t)(c[2 * q + 1] * 65536.0f) << 16);
+      const uint32_t t2 = ((uint32_t)(int32_t)(tws[2 * q] * 65536.0f) & 0xffffu) |
+                          ((uint32_t)(int32_t)(tws[2 * q + 1] * 65536.0f) << 16);
+      const u16x2 x = __builtin_bit_cast(u16x2, w[q]);
+      const u16x2 t = (u16x2)(x << (unsigned short)1) - __builtin_bit_cast(u16x2, c2);
+      const s16x2 sgn = __builtin_bit_cast(s16x2, __builtin_bit_cast(uint32_t, t) ^ 0x80008000u);
+      const s16x2 d = __builtin_elementwise_sub_sat(sgn, k2);
+      const u16x2 m = all ? (u16x2)(0xffff) : (u16x2)(d >> (short)15);
+      w[q] = __builtin_bit_cast(uint32_t, (u16x2)(x + (__builtin_bit_cast(u16x2, t2) & m)));
+    }
+  } else {
+    using F = Fmt<ST>;
+    constexpr int RW = W * F::kPerWord;
+    float x[RW];
+    F::template unpack<W>(w, x);
+    twist_values<ST, RW>(x, c, tws, win2);
+    F::template pack<W>(x, w);
+  }
+}
+
 // Eq. (6) on every replica of one edge of the last class, followed by the
 // twist of both endpoints: their phases are final for the sweep once the
-// update is done, so the twist needs no pass of its own for them.
+// update is done, so the twist needs no pass of its own for them.  The twist
+// sees the stored (rounded) phases, as a pass of its own would.
 template <int ST, int W>
 __device__ __forceinline__ void edge_rows_twist(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ,
                                                 const float (&c)[W * Fmt<ST>::kPerWord],
                                                 const float (&tws)[W * Fmt<ST>::kPerWord],
                                                 float win2) {
-  using F = Fmt<ST>;
-  constexpr int RW = W * F::kPerWord;
   uint32_t wu[W], wv[W];
   lds_load_at<W>(lds, bu, wu);
   lds_load_at<W>(lds, bv, wv);
-  float xu[RW], xv[RW];
-  F::template unpack<W>(wu, xu);
-  F::template unpack<W>(wv, xv);
-#pragma unroll
-  for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
-  // the twist sees the stored (rounded) phases, as a pass of its own would;
-  // a no-op for FP32
-  F::template pack<W>(xu, wu);
-  F::template pack<W>(xv, wv);
-  F::template unpack<W>(wu, xu);
-  F::template unpack<W>(wv, xv);
-  twist_values<ST, RW>(xu, c, tws, win2);
-  twist_values<ST, RW>(xv, c, tws, win2);
-  F::template pack<W>(xu, wu);
-  F::template pack<W>(xv, wv);
+  update_words<ST, W>(wu, wv, aJ);
+  twist_words<ST, W>(wu, c, tws, win2);
+  twist_words<ST, W>(wv, c, tws, win2);
   lds_store_at<W>(lds, bu, wu);
   lds_store_at<W>(lds, bv, wv);
 }
@@ -458,18 +512,11 @@ template <int ST, int W>
 __device__ __forceinline__ void row_twist(uint32_t *lds, uint32_t b,
                                           const float (&c)[W * Fmt<ST>::kPerWord],
                                           const float (&tws)[W * Fmt<ST>::kPerWord], float win2) {
-  using F = Fmt<ST>;
-  constexpr int RW = W * F::kPerWord;
   uint32_t w[W];
   lds_load_at<W>(lds, b, w);
-  float x[RW];
-  F::template unpack<W>(w, x);
-  twist_values<ST, RW>(x, c, tws, win2);
-  F::template pack<W>(x, w);
+  twist_words<ST, W>(w, c, tws, win2);
   lds_store_at<W>(lds, b, w);
 }
-
-
 
 // ---------------------------------------------------------------------------
 // Block reductions (wave64 shuffles, then one LDS slot per wave).
@@ -500,8 +547,6 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *scratch /* >= 1
 template <int ST, int W>
 __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint32_t bv,
                                                uint32_t set_bytes, int nsets, float aJ) {
-  using F = Fmt<ST>;
-  constexpr int RW = W * F::kPerWord;
   int k = 0;
   for (; k + 4 <= nsets; k += 4) {
     uint32_t wu[4][W], wv[4][W];
@@ -511,15 +556,7 @@ __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint3
       lds_load_at<W>(lds, bv + (uint32_t)(k + q) * set_bytes, wv[q]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      float xu[RW], xv[RW];
-      F::template unpack<W>(wu[q], xu);
-      F::template unpack<W>(wv[q], xv);
-#pragma unroll
-      for (int r = 0; r < RW; r++) pair_update<ST>(xu[r], xv[r], aJ);
-      F::template pack<W>(xu, wu[q]);
-      F::template pack<W>(xv, wv[q]);
-    }
+    for (int q = 0; q < 4; q++) update_words<ST, W>(wu[q], wv[q], aJ);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       lds_store_at<W>(lds, bu + (uint32_t)(k + q) * set_bytes, wu[q]);

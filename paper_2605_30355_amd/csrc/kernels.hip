@@ -256,12 +256,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           if (s0 + q * nth < a.n_rows) {
-            float v[RW];
-            F::template unpack<W>(w[q], v);
-#pragma unroll
-            for (int k = 0; k < RW; k++)
-              if (in_windows(v[k], cth[k], sc.win2)) v[k] = F::wrap(v[k] + tws[k]);
-            F::template pack<W>(v, w[q]);
+            twist_words<ST, W>(w[q], cth, tws, sc.win2);
             lds_store<W>(lds, s0 + q * nth, w[q]);
           }
         }
