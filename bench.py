@@ -525,6 +525,7 @@ def main():
         ttt = {"target_H": target, "target_cut": (int(-inst.J.sum()) - target) // 2}
         for name, over in (("batched_fp32", {}), ("batched_fp16", {"storage": cosm.STORE_FP16}),
                            ("batched_bf16", {"storage": cosm.STORE_BF16}),
+                           ("batched_fix16", {"storage": cosm.STORE_FIX16}),
                            ("batched_fp32_optimal_readout", {"readout": cosm.READOUT_OPTIMAL}),
                            ("batched_fp32_minimum_colouring", {"colouring": cosm.COLOR_MINIMUM})):
             col2, C2 = colour, C
@@ -536,7 +537,9 @@ def main():
             res, _ = s2.solve_to_target(target, 8 * R)
             ttt[name] = {"ps": res.ps, "ps_ci95": [res.ps_lo, res.ps_hi], "trials": res.trials,
                          "r99": res.r99, "t_trial_s": res.t_trial_s, "ttt_s": res.ttt_s,
-                         "best_H": res.best_H}
+                         "best_H": res.best_H,
+                         # whole trials (init, sweeps, readout) per second, as edge updates
+                         "edge_updates_per_s": round(m * S / res.t_trial_s, 1)}
             if col2 is not colour:
                 ttt[name]["classes"] = C2
             if s2 is not st:
