@@ -36,7 +36,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-ops per second, non-packed FP32
 # reads for a 256 MiB device copy (FETCH_SIZE 131087 KiB -> x2.0; WRITE_SIZE
 # 262144 KiB -> x1.0).  Valid only for the kernel sources they were taken on.
 TRAFFIC = dict(fetch_kib=4193.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
-               sources_sha256="b094c6625962d1c4b80c8e9012953d5c7f8c7e82cd38df97666adaa84f2421d0")
+               sources_sha256="fdcb870485e401cc2572e89309b6d42b3953735a2e0473fa6ceb9ff2485dd868")
 TRAFFIC_SOURCES = ("paper_2605_30355_amd/csrc/kernels.hip",
                    "paper_2605_30355_amd/csrc/device_common.hpp")
 
