@@ -216,7 +216,7 @@ int choose_shape(cosm_state *s) {
       sh.rw = chosen * pw;
       sh.blocks = (s->R + sh.rw - 1) / sh.rw;
       sh.lds_bytes = (int32_t)lds_sweep_bytes(s->n_slots, chosen, s->C);
-      if (int rc = build_lds_schedule(*s, chosen, p.threads_per_wg, &s->lds)) return rc;
+      if (int rc = build_lds_schedule(*s, chosen, p.threads_per_wg, &s->lds, true)) return rc;
       sh.threads = s->lds.nth;
     }
   }

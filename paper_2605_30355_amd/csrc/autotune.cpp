@@ -53,7 +53,7 @@ int upload_schedule(cosm_state *s) {
 }
 
 int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw) {
-  if (int rc = build_lds_schedule(*s, W, nth, &s->lds)) return rc;
+  if (int rc = build_lds_schedule(*s, W, nth, &s->lds, true)) return rc;
   s->shape.residency = COSM_RES_LDS;
   s->shape.rw = W * pw;
   s->shape.blocks = (s->R + s->shape.rw - 1) / s->shape.rw;

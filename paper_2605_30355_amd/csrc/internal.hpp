@@ -106,7 +106,9 @@ struct LdsSchedule {
   // would need more than kFuseRowsMax per thread.
   bool fuse = false;
   int32_t fuse_k = 0;
+  bool dummy_pairs = false;  // masked lanes carry dummy-row no-op edges
 };
+constexpr int32_t kRegisterSlotsMax = 16;  // schedules this short stay in registers
 constexpr int32_t kFuseRowsMax = 4;
 constexpr int32_t kStreamRepeat = 3;
 
@@ -197,7 +199,11 @@ int launch_energy(cosm_state *s);  // spins already in s->d.spins
 int launch_to_turns(cosm_state *s, float *turns_dev);
 int launch_from_turns(cosm_state *s, const float *turns_dev);
 int lds_capacity_bytes();
-int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out);
+// dummy_pairs: masked lanes of a register-resident schedule get conflict-free
+// no-op edges between dummy rows (only for the single-instance sweep kernel,
+// whose LDS holds the dummy rows).
+int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out,
+                       bool dummy_pairs = false);
 // Measure candidate LDS shapes (row widths in words) and keep the fastest.
 int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths);
 // Uploads the bias field in LDS-slot order (no-op without bias fields).

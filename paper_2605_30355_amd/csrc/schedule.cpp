@@ -96,7 +96,8 @@ int32_t bipartite_edge_colouring(int32_t G, const std::vector<int32_t> &left,
 
 }  // namespace
 
-int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out) {
+int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out,
+                       bool dummy_pairs) {
   const int32_t n = s.n, C = s.C, G = W == 1 ? 32 : 64 / W, H = 32 / W;
   const int64_t m = s.m;
   LdsSchedule &L = *out;
@@ -286,6 +287,41 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
   int64_t pad = 0;
   for (int32_t c = 0; c < C; c++) pad += L.padded[(size_t)c] - (int64_t)by_class[(size_t)c].size();
   L.pad_entries = pad;
+  // 3b. register-resident schedules: a masked lane gets a no-op edge (J = 0)
+  // between two dummy rows (after the n vertex rows) whose residues no other
+  // lane of its group uses, so that it costs no bank conflict.  u-dummies are
+  // dummy rows [0, 32), v-dummies [32, 64).
+  L.dummy_pairs = dummy_pairs && L.total_slots <= kRegisterSlotsMax && n + kDummyRows <= 65536;
+  if (L.dummy_pairs) {
+    std::vector<char> used_u((size_t)G), used_v((size_t)G);
+    for (int32_t jj = 0; jj < L.total_slots; jj++)
+      for (int32_t g0 = 0; g0 < nth; g0 += G) {
+        std::fill(used_u.begin(), used_u.end(), 0);
+        std::fill(used_v.begin(), used_v.end(), 0);
+        const size_t row = (size_t)jj * nth;
+        const int32_t g1 = std::min(nth, g0 + G);
+        for (int32_t t = g0; t < g1; t++) {
+          const EdgeDesc &d = L.desc[row + t];
+          if (d.slots == kEmptySlot) continue;
+          used_u[(size_t)((d.slots & 0xffffu) % (uint32_t)G)] = 1;
+          used_v[(size_t)((d.slots >> 16) % (uint32_t)G)] = 1;
+        }
+        int32_t ru = 0, rv = 0;
+        for (int32_t t = g0; t < g1; t++) {
+          EdgeDesc &d = L.desc[row + t];
+          if (d.slots != kEmptySlot) continue;
+          while (ru < G && used_u[(size_t)ru]) ru++;
+          while (rv < G && used_v[(size_t)rv]) rv++;
+          // a group has as many free residues as masked lanes
+          const int32_t q = n % G;
+          const uint32_t du = (uint32_t)(n + (ru - q + G) % G);
+          const uint32_t dv = (uint32_t)(n + 32 + (rv - q + G) % G);
+          d = EdgeDesc{du | (dv << 16), 0.0f};
+          ru++;
+          rv++;
+        }
+      }
+  }
   // 4. kStreamRepeat slots after the last repeat slots 0, 1, ... (mod
   // total), so that a schedule streamed one or two slots ahead never wraps.
   if (L.total_slots > 0) {

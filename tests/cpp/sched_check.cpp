@@ -22,7 +22,7 @@ int main(int argc, char** argv) {
   for (long k = 0; k < m; k++) { int u, v, J, c; if (scanf("%d %d %d %d", &u, &v, &J, &c) != 4) return 1;
     s.h_eu.push_back(u); s.h_ev.push_back(v); s.h_J.push_back(J); s.h_colour.push_back(c); }
   cosm::LdsSchedule L;
-  if (cosm::build_lds_schedule(s, W, 0, &L)) return 2;
+  if (cosm::build_lds_schedule(s, W, 0, &L, true)) return 2;
   // permutation
   std::vector<int> seen(n, 0); for (int sl = 0; sl < L.n_rows; sl++) { if (L.slot_vertex[sl] < 0 || L.slot_vertex[sl] >= n) { puts("BAD slot map"); return 3; } seen[L.slot_vertex[sl]]++; }
   for (int i = 0; i < n; i++) if (seen[i] != 1) { puts("BAD perm"); return 3; }
@@ -32,14 +32,20 @@ int main(int argc, char** argv) {
   std::multiset<std::tuple<int,int,int,float>> want, got;
   for (long k = 0; k < m; k++) want.insert({s.h_colour[k], vslot[s.h_eu[k]] , vslot[s.h_ev[k]], (float)s.h_J[k]});
   const int rlanes = W == 1 ? 32 : 256 / (4 * W), wlanes = 128 / (4 * W);
-  int j = 0; long conflicts = 0, active = 0;
+  int j = 0; long conflicts = 0, active = 0, dummies = 0, bad_dummy = 0;
   auto count = [&](int jj, int g0, int lanes, bool record) {
     int bu[64] = {0}, bv[64] = {0};
     for (int t = g0; t < g0 + lanes && t < L.nth; t++) {
       auto d = L.desc[(size_t)jj * L.nth + t];
       if (d.slots == cosm::kEmptySlot) continue;
       int su = d.slots & 0xffff, sv = d.slots >> 16;
-      if (record) { active++; got.insert({0, su, sv, d.J}); }
+      // dummy no-op edges of masked lanes: dummy rows only, J = 0, counted for
+      // bank conflicts like the edges
+      const bool dummy = su >= n || sv >= n;
+      if (dummy && !(su >= n && sv >= n && su < n + cosm::kDummyRows && sv < n + cosm::kDummyRows &&
+                     d.J == 0.0f && su != sv)) bad_dummy++;
+      if (record && !dummy) { active++; got.insert({0, su, sv, d.J}); }
+      if (record && dummy) dummies++;
       for (int w = 0; w < W; w++) { bu[(su * W + w) % 64]++; bv[(sv * W + w) % 64]++; }
     }
     for (int b = 0; b < 64; b++) conflicts += (bu[b] > 1 ? bu[b] - 1 : 0) + (bv[b] > 1 ? bv[b] - 1 : 0);
@@ -74,7 +80,7 @@ int main(int argc, char** argv) {
     for (int k = 0; k < L.K[C - 1]; k++)
       for (int t = 0; t < L.nth; t++) {
         auto d = L.desc[(size_t)(L.total_slots - L.K[C - 1] + k) * L.nth + t];
-        if (d.slots == cosm::kEmptySlot) continue;
+        if (d.slots == cosm::kEmptySlot || (int)(d.slots & 0xffff) >= n) continue;  // masked lane
         hit[d.slots & 0xffff]++; hit[d.slots >> 16]++;
       }
     for (int q = 0; q < L.fuse_k && fuse_ok; q++)
@@ -100,6 +106,6 @@ int main(int argc, char** argv) {
   } else if (L.desc.size() != rep) {
     fuse_ok = 0;
   }
-  printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d fuse=%d fuse_k=%d fuse_ok=%d fuse_conflicts=%ld\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got), (int)L.fuse, L.fuse_k, fuse_ok, fuse_conflicts);
+  printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d fuse=%d fuse_k=%d fuse_ok=%d fuse_conflicts=%ld dummies=%ld bad_dummy=%ld\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got), (int)L.fuse, L.fuse_k, fuse_ok, fuse_conflicts, dummies, bad_dummy);
   return 0;
 }

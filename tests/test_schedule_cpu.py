@@ -45,4 +45,5 @@ def test_schedule_conflict_free_and_complete(checker, case, W):
         f"{u} {v} {J} {c}" for u, v, J, c in zip(inst.eu, inst.ev, inst.J, colour))
     r = subprocess.run([checker, str(W)], input=txt, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert "conflicts=0" in r.stdout and "equal=1" in r.stdout and "fuse_ok=1" in r.stdout, r.stdout
+    assert "conflicts=0" in r.stdout and "equal=1" in r.stdout and "fuse_ok=1" in r.stdout \
+        and "bad_dummy=0" in r.stdout, r.stdout
