@@ -572,10 +572,11 @@ __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint3
 // Two descriptors are in flight: A holds slot j and B slot j + 1, and each is
 // refilled right after use, so a wait only ever covers the descriptor needed
 // next.  edge(d) applies Eq. (6) for descriptor d.
-template <typename EdgeFn>
+template <typename EdgeFn, typename LastFn, typename TailFn>
 __device__ __forceinline__ void stream_classes(const EdgeDesc *desc_any, const int32_t *Ks, int C,
                                                int total, EdgeDesc &A, EdgeDesc &B, int &j,
-                                               EdgeFn edge) {
+                                               EdgeFn edge, LastFn last, TailFn tail,
+                                               bool fuse_now) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const gptr<EdgeDesc> desc = as_global(desc_any) + tid;
   // slot x <= total + 1: the schedule repeats its first slots after the last,
@@ -584,24 +585,43 @@ __device__ __forceinline__ void stream_classes(const EdgeDesc *desc_any, const i
     const gptr<EdgeDesc> p = desc + (uint32_t)(x * nth);
     return EdgeDesc{p->slots, p->J};
   };
-  for (int c = 0; c < C; c++) {
-    const int kc = __builtin_amdgcn_readfirstlane(Ks[c]);
+  auto run = [&](int kc, auto &&fn) {
     int k = 0;
     for (; k + 2 <= kc; k += 2, j += 2) {
-      if (A.slots != kEmptySlot) edge(A);
+      if (A.slots != kEmptySlot) fn(A);
       A = at(j + 2);
-      if (B.slots != kEmptySlot) edge(B);
+      if (B.slots != kEmptySlot) fn(B);
       B = at(j + 3);
     }
     if (k < kc) {
-      if (A.slots != kEmptySlot) edge(A);
+      if (A.slots != kEmptySlot) fn(A);
       A = B;
       B = at(j + 2);
       j += 1;
     }
+  };
+  for (int c = 0; c < C - 1; c++) {
+    const int kc = __builtin_amdgcn_readfirstlane(Ks[c]);
+    run(kc, edge);
     if (kc > 0) __syncthreads();
   }
+  const int kl = __builtin_amdgcn_readfirstlane(Ks[C - 1]);
+  if (fuse_now) {  // the last class with its twist, and the rows it leaves out
+    run(kl, last);
+    tail();
+    __syncthreads();
+  } else {
+    run(kl, edge);
+    if (kl > 0) __syncthreads();
+  }
   j -= total;  // exactly one pass over the slots: keep j in [0, total)
+}
+
+template <typename EdgeFn>
+__device__ __forceinline__ void stream_classes(const EdgeDesc *desc_any, const int32_t *Ks, int C,
+                                               int total, EdgeDesc &A, EdgeDesc &B, int &j,
+                                               EdgeFn edge) {
+  stream_classes(desc_any, Ks, C, total, A, B, j, edge, edge, [] {}, false);
 }
 
 // Arguments of the readout of one instance (phases [n][R]).

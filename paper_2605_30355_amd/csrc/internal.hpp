@@ -103,7 +103,8 @@ struct LdsSchedule {
   // Rows that no edge of the last class touches, fuse_k per thread, stored in
   // desc after the repeated slots (slots = row, kEmptySlot for none).  They let
   // the twist run inside the last class's sub-sweep; fuse is false when they
-  // would need more than kFuseRowsMax per thread.
+  // would need more than kFuseRowsMax per thread (beyond that a pass of its own
+  // with four rows in flight is faster).
   bool fuse = false;
   int32_t fuse_k = 0;
   bool dummy_pairs = false;  // masked lanes carry dummy-row no-op edges

@@ -60,7 +60,8 @@ __global__ void __launch_bounds__(256) k_init(void *phases, int32_t n, int32_t R
 // ---------------------------------------------------------------------------
 template <int ST, int W, int EMAX, bool EXACT, bool FUSE>
 __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
-  static_assert(!FUSE || EXACT, "the fused twist needs the one-slot-per-class form");
+  static_assert(!FUSE || EXACT || EMAX == 0,
+                "the fused twist runs in the one-slot-per-class and the streamed forms");
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
@@ -115,8 +116,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     }
   }
   // rows outside the last class (twist only)
-  uint32_t fr[FUSE ? kFuseRowsMax : 1];
-  if constexpr (FUSE) {
+  uint32_t fr[FUSE && EXACT ? kFuseRowsMax : 1];
+  if constexpr (FUSE && EXACT) {
 #pragma unroll
     for (int q = 0; q < kFuseRowsMax; q++) {
       fr[q] = kEmptySlot;
@@ -146,7 +147,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     float alpha, twist;
     chunk.get(it & 63u, alpha, twist);
     // Sequential conflict-free search: classes in order, a barrier after each.
-    if constexpr (FUSE) {
+    if constexpr (FUSE && EXACT) {
       // EMAX slots, one class each.  On a twist sweep the last class twists
       // the rows it updates and, concurrently, the rows it leaves out.
       const bool fuse_now = sc.phase + 1 == sc.period;
@@ -196,9 +197,46 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         }
       }
     } else if (a.total_slots > 0) {
-      stream_classes(a.desc, Ks, a.C, a.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
+      auto edge = [&](const EdgeDesc &d) {
         edge_rows<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha * d.J);
-      });
+      };
+      if constexpr (FUSE) {
+        // streamed form: on a twist sweep the last class twists the rows it
+        // updates, then each thread twists its fuse_k rows outside that class
+        const bool fuse_now = sc.phase + 1 == sc.period;
+        float cth[RW], tws[RW];
+        if (fuse_now) {
+          const int slot = tw % kThetaChunk;
+          tw++;
+          if (slot == 0) {
+            theta_fill(theta_buf, nullptr, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0,
+                       a.k0, a.k1, sc.win, sc.tshift, sc.tscale);
+            __syncthreads();
+          }
+#pragma unroll
+          for (int k = 0; k < RW; k++) {
+            cth[k] = theta_buf[slot * RW + k];
+            tws[k] = twist;
+          }
+        }
+        const gptr<EdgeDesc> rest =
+            as_global(a.desc) + (size_t)(a.total_slots + kStreamRepeat) * nth + tid;
+        stream_classes(
+            a.desc, Ks, a.C, a.total_slots, dA, dB, jslot, edge,
+            [&](const EdgeDesc &d) {
+              edge_rows_twist<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
+                                     alpha * d.J, cth, tws, sc.win2);
+            },
+            [&] {
+              for (int q = 0; q < a.fuse_k; q++) {
+                const uint32_t row = rest[(size_t)q * nth].slots;
+                if (row != kEmptySlot) row_twist<ST, W>(lds, row * ROWB, cth, tws, sc.win2);
+              }
+            },
+            fuse_now);
+      } else {
+        stream_classes(a.desc, Ks, a.C, a.total_slots, dA, dB, jslot, edge);
+      }
     }
     // Bias fields: one more conflict-free sub-sweep against the virtual spin
     // at phase 0, after the classes (rows are final after the last barrier).
@@ -486,14 +524,15 @@ int launch_lds_w(cosm_state *s, const LdsArgs &a) {
   const bool one_each = slots == a.C && slots <= 32 && a.bar_mask == (uint32_t)((1ull << slots) - 1);
   // the twist inside the last class: a twist period, no field pass after the
   // classes, and the rows outside the last class few enough for registers
-  const bool fuse = one_each && a.sch.period > 0 && a.h_slot == nullptr && s->lds.fuse;
-  if (fuse && slots == 4) return launch_lds<ST, W, 4, true, true>(s, a);
-  if (fuse && slots == 8) return launch_lds<ST, W, 8, true, true>(s, a);
+  const bool fuse = a.sch.period > 0 && a.h_slot == nullptr && s->lds.fuse;
+  if (fuse && one_each && slots == 4) return launch_lds<ST, W, 4, true, true>(s, a);
+  if (fuse && one_each && slots == 8) return launch_lds<ST, W, 8, true, true>(s, a);
   if (one_each && slots == 4) return launch_lds<ST, W, 4, true>(s, a);
   if (one_each && slots == 8) return launch_lds<ST, W, 8, true>(s, a);
   if (slots <= 4) return launch_lds<ST, W, 4, false>(s, a);
   if (slots <= 8) return launch_lds<ST, W, 8, false>(s, a);
   if (slots <= 16) return launch_lds<ST, W, 16, false>(s, a);
+  if (fuse) return launch_lds<ST, W, 0, false, true>(s, a);
   return launch_lds<ST, W, 0, false>(s, a);
 }
 
