@@ -22,6 +22,7 @@ from scipy import stats
 import cosm_inputs as ci
 import oracle
 import paper_2605_30355_amd as cosm
+from stats_util import newcombe_diff
 
 pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -30,23 +31,6 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def wilson(k, n, z=1.959963984540054):
-    p = k / n
-    den = 1 + z * z / n
-    c = (p + z * z / (2 * n)) / den
-    h = z * np.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / den
-    return c - h, c + h
-
-
-def newcombe_diff(k1, n1, k2, n2):
-    """95% interval of p1 - p2 (Newcombe 1998, method 10)."""
-    p1, p2 = k1 / n1, k2 / n2
-    l1, u1 = wilson(k1, n1)
-    l2, u2 = wilson(k2, n2)
-    d = p1 - p2
-    return d - np.sqrt((p1 - l1) ** 2 + (u2 - p2) ** 2), d + np.sqrt((u1 - p1) ** 2 + (p2 - l2) ** 2)
 
 
 def target(name):
