@@ -2,9 +2,10 @@
 // Philox, the storage formats, LDS row access, the pair update of Eq. (6), the
 // dual-window membership test and the per-sweep schedule.
 //
-// Phase arithmetic is FP32 in turns (1 turn = 360 degrees).  FP32 storage keeps
-// x in [0, 1) and wraps with v_fract_f32; FP16 / BF16 storage keeps the centred
-// value y = x - 1/2 in [-1/2, 1/2] and wraps with y - rint(y).
+// Phases are turns (1 turn = 360 degrees).  FP32 storage keeps x in [0, 1) and
+// wraps with v_fract_f32; FP16 / BF16 storage keeps the centred value
+// y = x - 1/2 in [-1/2, 1/2] and wraps with y - rint(y); FIX16 keeps x in 16-bit
+// fixed point and wraps by integer overflow (update_words, twist_words).
 #pragma once
 
 #include <hip/hip_runtime.h>

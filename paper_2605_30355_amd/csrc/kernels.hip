@@ -1,10 +1,13 @@
 // kernels.hip -- gfx950 kernels of libcosm and their launchers.
 //
-// Phase arithmetic is FP32 in turns (1 turn = 360 degrees).  FP32 storage keeps
-// x in [0, 1) and wraps with v_fract_f32; FP16 / BF16 storage keeps the centred
-// value y = x - 1/2 in [-1/2, 1/2] and wraps with y - rint(y) (one more bit of
-// resolution than storing x).  On the 2^-23 turn grid every add, subtract, fma
-// by 2 and fract below is exact, so grid-schedule trajectories are bit-exact.
+// Phases are turns (1 turn = 360 degrees).  FP32 storage keeps x in [0, 1) and
+// wraps with v_fract_f32; FP16 / BF16 storage keeps the centred value
+// y = x - 1/2 in [-1/2, 1/2] and wraps with y - rint(y) (one more bit of
+// resolution than storing x); arithmetic is FP32.  FIX16 storage keeps x as a
+// 16-bit integer k (x = k 2^-16) and the LDS sweep updates it with packed
+// 16-bit integer ops (other forms go through FP32, exact on that grid).  On
+// the 2^-23 turn grid (2^-16 for FIX16) every add, subtract, fma by 2 and
+// fract below is exact, so grid-schedule trajectories are bit-exact.
 //
 // The pair update of Eq. (6), with the biased sign of Eq. (4) taken on the
 // minimum angular difference:  f = fract(x_u - x_v); s = +1 iff f < 1/2;
@@ -57,6 +60,8 @@ __global__ void __launch_bounds__(256) k_init(void *phases, int32_t n, int32_t R
 // t-th entry of each slot of the lane schedule (consecutive lanes touch rows in
 // distinct LDS bank groups).  EMAX > 0: the schedule (at most EMAX slots) is
 // loaded into registers once; EMAX == 0: it streams from memory, one slot ahead.
+// EXACT: one slot per class (EMAX of them), no bounds checks.  FUSE (EXACT or
+// streamed, no bias fields): the twist runs inside the last class's sub-sweep.
 // ---------------------------------------------------------------------------
 template <int ST, int W, int EMAX, bool EXACT, bool FUSE>
 __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
