@@ -56,6 +56,12 @@ enum {
 /* ---- enumerations ---------------------------------------------------------- */
 enum { COSM_COLOR_GREEDY = 0, COSM_COLOR_MISRA_GRIES = 1, COSM_COLOR_TORUS = 2,
        COSM_COLOR_BALANCED = 3, COSM_COLOR_MINIMUM = 4 };
+/* Class-order flag, ORed into the method of cosm_build_partitions: the labels of
+ * the largest class and of the last one are swapped, so that the class applied
+ * last covers the most vertices (the sweep then folds the twist into it,
+ * dropping a pass).  The order is part of the dynamics (Sec. V-A); the flag is
+ * deterministic and the returned colouring records it. */
+enum { COSM_ORDER_LARGEST_LAST = 0x100 };
 /* Phase storage.  FP32: x in [0, 1) turn.  FP16 / BF16: the centred value
  * x - 1/2, FP32 arithmetic, rounded on every store.  FIX16: x in 16-bit fixed
  * point (units of 2^-16 turn), wrapping by integer overflow; needs the GRID
@@ -128,6 +134,7 @@ typedef struct cosm_state cosm_state;
  *     colouring, as the paper's greedy heuristic reached on its non-lattice
  *     graphs, Sec. III-B); Delta + 1 colours otherwise (class-2 graphs); then
  *     equalised as BALANCED.  Deterministic for a given input.
+ * method may carry COSM_ORDER_LARGEST_LAST.
  * colour_out[m] (caller-owned) receives the class of every edge; class indices
  * are also the order in which a sweep applies them.  *num_colours_out = C.
  * Errors: EINVAL (NULL, n < 1, endpoint out of range, self-loop, TORUS edge that

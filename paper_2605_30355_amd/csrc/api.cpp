@@ -275,6 +275,8 @@ int cosm_build_partitions(int32_t n, int64_t m, const int32_t *eu, const int32_t
   if (num_colours_out == nullptr || (m > 0 && colour_out == nullptr))
     return set_error(COSM_EINVAL, "output pointers must not be NULL");
   if (int rc = validate_graph(n, m, eu, ev, nullptr)) return rc;
+  const bool largest_last = (method & COSM_ORDER_LARGEST_LAST) != 0;
+  method &= ~COSM_ORDER_LARGEST_LAST;
   int32_t C = 0;
   switch (method) {
     case COSM_COLOR_GREEDY: C = colour_greedy(n, m, eu, ev, colour_out); break;
@@ -293,6 +295,19 @@ int cosm_build_partitions(int32_t n, int64_t m, const int32_t *eu, const int32_t
       if (C < 0) return C;
       break;
     default: return set_error(COSM_EINVAL, "unknown colouring method");
+  }
+  if (largest_last && C > 1) {
+    // swap the labels of the largest class (lowest index on ties) and the last
+    std::vector<int64_t> size((size_t)C, 0);
+    for (int64_t k = 0; k < m; k++) size[(size_t)colour_out[k]]++;
+    int32_t big = 0;
+    for (int32_t c = 1; c < C; c++)
+      if (size[(size_t)c] > size[(size_t)big]) big = c;
+    if (size[(size_t)big] > size[(size_t)C - 1])
+      for (int64_t k = 0; k < m; k++) {
+        if (colour_out[k] == big) colour_out[k] = C - 1;
+        else if (colour_out[k] == C - 1) colour_out[k] = big;
+      }
   }
   if (validate_colouring(n, m, eu, ev, colour_out, C) != COSM_OK)
     return set_error(COSM_ECOLOR, "internal error: colouring is not proper: " + g_last_error);

@@ -134,3 +134,23 @@ def test_minimum_colouring():
     E = np.array(outer + spokes + inner, np.int32)
     c, C = cosm.build_partitions(10, E[:, 0], E[:, 1], cosm.COLOR_MINIMUM)
     assert C == 4 and oracle.is_proper_colouring(10, E[:, 0], E[:, 1], c, C)
+
+
+@pytest.mark.parametrize("case", [("torus141", cosm.COLOR_TORUS), ("er", cosm.COLOR_GREEDY),
+                                  ("rr3", cosm.COLOR_BALANCED)])
+def test_largest_class_last(case):
+    """COSM_ORDER_LARGEST_LAST swaps two labels only: the same classes, the
+    largest one applied last, still a proper colouring."""
+    name, method = case
+    inst = {"torus141": ci.torus(141, seed=4), "er": ci.erdos_renyi_capped(3000, 4, 8, seed=7),
+            "rr3": ci.random_regular(2000, 3, seed=2)}[name]
+    sides = [141, 141] if name == "torus141" else None
+    c0, C0 = cosm.build_partitions(inst.n, inst.eu, inst.ev, method, sides)
+    c1, C1 = cosm.build_partitions(inst.n, inst.eu, inst.ev, method | cosm.ORDER_LARGEST_LAST, sides)
+    assert C1 == C0 and oracle.is_proper_colouring(inst.n, inst.eu, inst.ev, c1, C1)
+    s0, s1 = np.bincount(c0, minlength=C0), np.bincount(c1, minlength=C1)
+    assert s1[-1] == s0.max()
+    big = int(np.argmax(s0)) if s0.max() > s0[-1] else C0 - 1
+    relabel = np.arange(C0)
+    relabel[[big, C0 - 1]] = [C0 - 1, big]
+    assert np.array_equal(c1, relabel[c0])

@@ -173,10 +173,12 @@ def test_c2_full_size_sampled():
     assert info["residency"] == cosm.RES_LDS
 
 
-def test_large_torus_odd_side_sampled():
-    """141x141 torus (N=19881, 6 classes): the largest LDS-resident replica block."""
+@pytest.mark.parametrize("order", [0, cosm.ORDER_LARGEST_LAST])
+def test_large_torus_odd_side_sampled(order):
+    """141x141 torus (N=19881, 6 classes): the largest LDS-resident replica block;
+    with the largest class last the streamed sweep folds the twist into it."""
     inst = ci.torus(141, seed=4)
-    colour, C, prob = make(inst, cosm.COLOR_TORUS, [141, 141])
+    colour, C, prob = make(inst, cosm.COLOR_TORUS | order, [141, 141])
     p = cosm.Params(sweeps_per_trial=200, dwt_ratio=0.5, dwt_period=3)
     info = check_trial(inst, colour, C, prob, p, seed=3, R=96, sweeps=200, sample=[0, 95])
     assert info["residency"] == cosm.RES_LDS
