@@ -322,33 +322,92 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Device-memory forms: one launch per colour class.  HBM form: a wave covers 64
-// consecutive replicas of one edge (coalesced rows of the [n][R] layout).
-// PLAIN form: one replica, a thread per edge.
+// VEC consecutive replicas of one vertex row in one access (8 or 16 bytes for
+// FP32, 4 or 8 for the 16-bit formats); idx is a multiple of VEC.
+typedef float hbm_f32x2 __attribute__((ext_vector_type(2)));
+typedef float hbm_f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t hbm_u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+using gvec = T __attribute__((address_space(1))) *;
+
+template <int ST, int VEC>
+__device__ __forceinline__ void load_vec(const void *p, size_t idx, float (&x)[VEC]) {
+  using F = Fmt<ST>;
+  if constexpr (VEC == 1) {
+    x[0] = F::load_elem(p, idx);
+  } else if constexpr (ST == COSM_STORE_FP32) {
+    const float *q = static_cast<const float *>(p) + idx;
+    if constexpr (VEC == 4) {
+      const hbm_f32x4 v = *(gvec<const hbm_f32x4>)(q);
+      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else {
+      const hbm_f32x2 v = *(gvec<const hbm_f32x2>)(q);
+      x[0] = v.x; x[1] = v.y;
+    }
+  } else {
+    const uint16_t *q = static_cast<const uint16_t *>(p) + idx;
+    if constexpr (VEC == 4) {
+      const hbm_u32x2 v = *(gvec<const hbm_u32x2>)(q);
+      x[0] = F::dec(v.x & 0xffffu); x[1] = F::dec(v.x >> 16);
+      x[2] = F::dec(v.y & 0xffffu); x[3] = F::dec(v.y >> 16);
+    } else {
+      const uint32_t v = *(gvec<const uint32_t>)(q);
+      x[0] = F::dec(v & 0xffffu); x[1] = F::dec(v >> 16);
+    }
+  }
+}
+template <int ST, int VEC>
+__device__ __forceinline__ void store_vec(void *p, size_t idx, const float (&x)[VEC]) {
+  using F = Fmt<ST>;
+  if constexpr (VEC == 1) {
+    F::store_elem(p, idx, x[0]);
+  } else if constexpr (ST == COSM_STORE_FP32) {
+    float *q = static_cast<float *>(p) + idx;
+    if constexpr (VEC == 4) {
+      *(gvec<hbm_f32x4>)(q) = hbm_f32x4{x[0], x[1], x[2], x[3]};
+    } else {
+      *(gvec<hbm_f32x2>)(q) = hbm_f32x2{x[0], x[1]};
+    }
+  } else {
+    uint16_t *q = static_cast<uint16_t *>(p) + idx;
+    if constexpr (VEC == 4) {
+      *(gvec<hbm_u32x2>)(q) = hbm_u32x2{F::enc(x[0]) | (F::enc(x[1]) << 16),
+                                        F::enc(x[2]) | (F::enc(x[3]) << 16)};
+    } else {
+      *(gvec<uint32_t>)(q) = F::enc(x[0]) | (F::enc(x[1]) << 16);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
-template <int ST>
+// Device-memory forms: one launch per colour class.  HBM form: a wave covers
+// 64 VEC consecutive replicas of one edge (coalesced rows of the [n][R]
+// layout, VEC per lane).  PLAIN form: one replica, a thread per edge.
+// ---------------------------------------------------------------------------
+template <int ST, int VEC>
 __global__ void __launch_bounds__(256) k_class_hbm(void *phases, const int32_t *peu,
                                                    const int32_t *pev, const float *pJ,
                                                    int32_t beg, int32_t cnt, int32_t R,
                                                    int32_t rchunks, float alpha) {
-  using F = Fmt<ST>;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t e = wave / rchunks;
-  const int32_t r = (int32_t)(wave % rchunks) * 64 + lane;
+  const int32_t r = ((int32_t)(wave % rchunks) * 64 + lane) * VEC;
   if (e >= cnt || r >= R) return;
   const int32_t u = peu[beg + e], v = pev[beg + e];
   const float aJ = alpha * pJ[beg + e];
-  float xu = F::load_elem(phases, (size_t)u * R + r);
-  float xv = F::load_elem(phases, (size_t)v * R + r);
-  pair_update<ST>(xu, xv, aJ);
-  F::store_elem(phases, (size_t)u * R + r, xu);
-  F::store_elem(phases, (size_t)v * R + r, xv);
+  float xu[VEC], xv[VEC];
+  load_vec<ST, VEC>(phases, (size_t)u * R + r, xu);
+  load_vec<ST, VEC>(phases, (size_t)v * R + r, xv);
+#pragma unroll
+  for (int k = 0; k < VEC; k++) pair_update<ST>(xu[k], xv[k], aJ);
+  store_vec<ST, VEC>(phases, (size_t)u * R + r, xu);
+  store_vec<ST, VEC>(phases, (size_t)v * R + r, xv);
 }
 
-// Twist for replicas [rbeg, rbeg + rcount): thread = one replica x a strip of
-// `strip` vertices, so the reference angle is drawn once per strip.
-template <int ST>
+// Twist for replicas [rbeg, rbeg + rcount): thread = VEC replicas x a strip of
+// `strip` vertices, so the reference angles are drawn once per strip.
+template <int ST, int VEC>
 __global__ void __launch_bounds__(256) k_dwt_hbm(void *phases, int32_t n, int32_t R, int32_t rbeg,
                                                  int32_t rcount, int32_t strip, uint32_t t,
                                                  float twist, float win, float win2, uint32_t k0,
@@ -356,21 +415,34 @@ __global__ void __launch_bounds__(256) k_dwt_hbm(void *phases, int32_t n, int32_
                                                  uint32_t tshift, float tscale) {
   using F = Fmt<ST>;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t rchunks = (rcount + 63) / 64;
+  const int32_t rchunks = (rcount + 64 * VEC - 1) / (64 * VEC);
   const int64_t wave = g >> 6;
   const int lane = threadIdx.x & 63;
-  const int32_t rloc = (int32_t)(wave % rchunks) * 64 + lane;
+  const int32_t rloc = ((int32_t)(wave % rchunks) * 64 + lane) * VEC;
   const int64_t i0 = (wave / rchunks) * strip;
   if (rloc >= rcount || i0 >= n) return;
   const int32_t r = rbeg + rloc;
-  const uint2 wd = philox_words01(0u, t, rid0 + (uint32_t)r, kTagDwt, k0, k1);
-  const float c = 2.0f * ((float)(wd.x >> tshift) * tscale) - win;
-  if (drawn_dir && (wd.y >> 31)) twist = -twist;  // with bias fields: drawn direction
+  float c[VEC], tw[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; k++) {
+    const uint2 wd = philox_words01(0u, t, rid0 + (uint32_t)(r + k), kTagDwt, k0, k1);
+    c[k] = 2.0f * ((float)(wd.x >> tshift) * tscale) - win;
+    tw[k] = (drawn_dir && (wd.y >> 31)) ? -twist : twist;  // with bias fields: drawn direction
+  }
   const int64_t i1 = min((int64_t)n, i0 + strip);
   for (int64_t i = i0; i < i1; i++) {
     const size_t idx = (size_t)i * R + r;
-    const float v = F::load_elem(phases, idx);
-    if (in_windows(v, c, win2)) F::store_elem(phases, idx, F::wrap(v + twist));
+    float v[VEC];
+    load_vec<ST, VEC>(phases, idx, v);
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < VEC; k++) {
+      if (in_windows(v[k], c[k], win2)) {
+        v[k] = F::wrap(v[k] + tw[k]);
+        any = true;
+      }
+    }
+    if (any) store_vec<ST, VEC>(phases, idx, v);
   }
 }
 
@@ -576,19 +648,36 @@ int sweeps_lds_st(cosm_state *s, int64_t n_sweeps) {
   return set_error(COSM_EINVAL, "unsupported replicas per workgroup");
 }
 
-template <int ST>
-int dwt_hbm_st(cosm_state *s, int64_t t, int32_t rbeg, int32_t rcount) {
+// Replicas per lane of the HBM kernels: the widest of 4, 2, 1 that keeps every
+// access aligned (R, the first replica and the count all multiples of it).
+int hbm_vec(int32_t R, int32_t rbeg, int32_t rcount) {
+  for (int v : {4, 2})
+    if (R % v == 0 && rbeg % v == 0 && rcount % v == 0) return v;
+  return 1;
+}
+
+template <int ST, int VEC>
+int dwt_hbm_vec(cosm_state *s, int64_t t, int32_t rbeg, int32_t rcount) {
   const Schedule &sc = s->sched;
   const int32_t strip = 64;
-  const int32_t rchunks = (rcount + 63) / 64;
+  const int32_t rchunks = (rcount + 64 * VEC - 1) / (64 * VEC);
   const int64_t strips = ((int64_t)s->n + strip - 1) / strip;
   const int64_t threads = strips * rchunks * 64;
   const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
-  hipLaunchKernelGGL((k_dwt_hbm<ST>), grid, block, 0, s->stream, s->d.phases, s->n, s->R, rbeg,
-                     rcount, strip, (uint32_t)t, host_twist(sc, t), sc.window, sc.window2,
+  hipLaunchKernelGGL((k_dwt_hbm<ST, VEC>), grid, block, 0, s->stream, s->d.phases, s->n, s->R,
+                     rbeg, rcount, strip, (uint32_t)t, host_twist(sc, t), sc.window, sc.window2,
                      (uint32_t)(s->seed & 0xffffffffu), (uint32_t)(s->seed >> 32),
                      (uint32_t)s->rid0, (int32_t)s->has_h, (uint32_t)sc.tshift, sc.tscale);
   return launch_check("k_dwt_hbm");
+}
+
+template <int ST>
+int dwt_hbm_st(cosm_state *s, int64_t t, int32_t rbeg, int32_t rcount) {
+  switch (hbm_vec(s->R, rbeg, rcount)) {
+    case 4: return dwt_hbm_vec<ST, 4>(s, t, rbeg, rcount);
+    case 2: return dwt_hbm_vec<ST, 2>(s, t, rbeg, rcount);
+    default: return dwt_hbm_vec<ST, 1>(s, t, rbeg, rcount);
+  }
 }
 
 template <int ST>
@@ -599,10 +688,20 @@ int field_hbm_st(cosm_state *s, float alpha, int32_t rbeg, int32_t rcount) {
   return launch_check("k_field_hbm");
 }
 
+template <int ST, int VEC>
+int class_hbm_vec(cosm_state *s, int32_t beg, int32_t cnt, float alpha) {
+  const int32_t rchunks = (s->R + 64 * VEC - 1) / (64 * VEC);
+  const int64_t threads = (int64_t)cnt * rchunks * 64;
+  hipLaunchKernelGGL((k_class_hbm<ST, VEC>), dim3((unsigned)((threads + 255) / 256)), dim3(256),
+                     0, s->stream, s->d.phases, s->d.peu, s->d.pev, s->d.pJ, beg, cnt, s->R,
+                     rchunks, alpha);
+  return launch_check("k_class_hbm");
+}
+
 template <int ST>
 int sweeps_hbm_st(cosm_state *s, int64_t n_sweeps) {
   const Schedule &sc = s->sched;
-  const int32_t rchunks = (s->R + 63) / 64;
+  const int vec = hbm_vec(s->R, 0, s->R);
   for (int64_t t = s->t + 1; t <= s->t + n_sweeps; t++) {
     const float alpha = host_alpha(sc, t);
     if (s->p.update == COSM_UPDATE_FULL_GRADIENT) {
@@ -616,11 +715,10 @@ int sweeps_hbm_st(cosm_state *s, int64_t n_sweeps) {
       for (int c = 0; c < s->C; c++) {
         const int32_t beg = s->class_begin[c], cnt = s->class_sizes[c];
         if (cnt == 0) continue;
-        const int64_t threads = (int64_t)cnt * rchunks * 64;
-        hipLaunchKernelGGL((k_class_hbm<ST>), dim3((unsigned)((threads + 255) / 256)), dim3(256),
-                           0, s->stream, s->d.phases, s->d.peu, s->d.pev, s->d.pJ, beg, cnt, s->R,
-                           rchunks, alpha);
-        if (int rc = launch_check("k_class_hbm")) return rc;
+        const int rc = vec == 4   ? class_hbm_vec<ST, 4>(s, beg, cnt, alpha)
+                       : vec == 2 ? class_hbm_vec<ST, 2>(s, beg, cnt, alpha)
+                                  : class_hbm_vec<ST, 1>(s, beg, cnt, alpha);
+        if (rc) return rc;
       }
       if (s->has_h)
         if (int rc = field_hbm_st<ST>(s, alpha, 0, s->R)) return rc;
