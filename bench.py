@@ -36,7 +36,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-ops per second, non-packed FP32
 # reads for a 256 MiB device copy (FETCH_SIZE 131087 KiB -> x2.0; WRITE_SIZE
 # 262144 KiB -> x1.0).  Valid only for the kernel sources they were taken on.
 TRAFFIC = dict(fetch_kib=4196.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
-               sources_sha256="a9c1600efcb97720eca61e1911306f72a7259bbc095c23b41f8421a37e902923")
+               sources_sha256="2dbfaafa043e8f0dac78fa7a9fac309f23099a7cfe76c665cb5a28d05f68faee")
 TRAFFIC_SOURCES = ("paper_2605_30355_amd/csrc/kernels.hip",
                    "paper_2605_30355_amd/csrc/device_common.hpp")
 
