@@ -175,3 +175,29 @@ def test_validation():
         st.set_phases(x, cosm.UNIT_TURNS, 0)
         y = st.get_phases(cosm.UNIT_TURNS)
     assert np.array_equal(y, np.round(0.3 * 65536) / 65536 * np.ones_like(x))
+
+
+def test_resume_across_calls_and_degenerate():
+    """Sweeps split over several calls (the schedule resumes mid-ramp and
+    mid-twist-period), an edgeless instance (twist only) and a single edge."""
+    inst = ci.random_regular(300, 3, seed=8, weights="pm1")
+    colour, C, prob = make(inst, cosm.COLOR_MISRA_GRIES)
+    p = fix16(sweeps_per_trial=500, dwt_ratio=1.5, dwt_period=3, residency=cosm.RES_LDS,
+              replicas_per_wg=4)
+    say("[gpu] fix16 resume")
+    with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=9, replicas=36) as st:
+        for step in (1, 2, 97, 100, 300):
+            st.sweep(step)
+        x = st.get_phases(cosm.UNIT_TURNS)
+    op = oparams(p)
+    xr = oracle.init_phases(inst.n, 9, 0, 36, G16)
+    oracle.sweeps(prob, op, 9, 0, xr, 0, 500)
+    assert np.array_equal(x * 360.0, xr)
+    none = ci.Instance("no_edges", 17, np.zeros(0, np.int32), np.zeros(0, np.int32),
+                       np.zeros(0, np.int32))
+    c, C, prob = make(none)
+    check(none, c, C, prob, fix16(sweeps_per_trial=30, dwt_period=1, dwt_ratio=1.0), 2, 10, 30)
+    one = ci.Instance("one_edge", 2, np.array([0], np.int32), np.array([1], np.int32),
+                      np.array([-2], np.int32))
+    c, C, prob = make(one)
+    check(one, c, C, prob, fix16(sweeps_per_trial=50, dwt_period=2), 1, 6, 50)
