@@ -255,17 +255,13 @@ __device__ __forceinline__ bool in_windows(float v, float c, float win2) {
 }
 
 
-// Per-sweep schedule evaluated on the device.  Grid: alpha = q * aunit (2^-22
-// turn; 2^-15 for FIX16) with
-// q = floor(num / S), num = a0 (S - t + 1) + S/2, stepped by subtraction with
-// a 32-bit remainder (S <= 2^31; q < 2^22 and 2 rho q < 2^23, so the int32
-// products and conversions are exact).  Few scalar instructions per sweep:
-// every wave of the CU shares one scalar unit.
+// The step-size ramp and the twist angle, evaluated on the device.  Grid:
+// alpha = q * aunit (2^-22 turn; 2^-15 for FIX16) with
+// q = floor((a0 (S - t + 1) + S/2) / S) (q < 2^22 and 2 rho q < 2^23, so the
+// int32 products and conversions are exact).  Continuous: the literal ramp.
 struct SweepSchedule {
   int32_t grid;
-  uint32_t S, r, ar;     // grid: remainder of num / S and of a0 / S
-  int32_t q, aq;         // grid: quotients
-  uint32_t u;            // continuous: S - t + 1 of the next sweep t
+  uint32_t S;            // schedule length (<= 2^31)
   float alpha_cont_per;  // alpha0 / S in turns (continuous)
   int32_t twist2;        // 2 * ratio (grid)
   float ratio;           // continuous
@@ -277,8 +273,8 @@ struct SweepSchedule {
   float tscale;
 };
 
-// alpha_t and the twist of sweep t (1 <= t <= S) computed directly, as the
-// host does: the same values schedule_step produces by stepping.
+// alpha_t and the twist of sweep t (1 <= t <= S), exactly as the host
+// evaluates them for the device-memory forms.
 __device__ __forceinline__ void schedule_at(const SweepSchedule &sc, uint32_t t, float &alpha,
                                             float &twist) {
   const uint32_t u = sc.S - t + 1u;  // S - t + 1 >= 1
@@ -308,33 +304,11 @@ struct ScheduleChunk {
   }
 };
 
-// alpha_t and the twist angle rho * alpha_t of the next sweep (Algorithm 1's
-// ramp); advances to the sweep after it.
-__device__ __forceinline__ void schedule_step(SweepSchedule &sc, float &alpha, float &twist) {
-  if (sc.grid) {
-    alpha = (float)sc.q * sc.aunit;
-    twist = (float)(sc.twist2 * sc.q) * sc.tunit;
-    const bool borrow = sc.r < sc.ar;
-    sc.r = sc.r - sc.ar + (borrow ? sc.S : 0u);
-    sc.q -= sc.aq + (borrow ? 1 : 0);
-  } else {
-    alpha = (float)sc.u * sc.alpha_cont_per;
-    twist = sc.ratio * alpha;
-    sc.u -= 1u;
-  }
-}
-
 // The device schedule after t_done sweeps (host side).
 SweepSchedule make_sweep_schedule(const Schedule &sc, int64_t t_done) {
   SweepSchedule w{};
   w.grid = sc.grid;
   w.S = (uint32_t)sc.S;
-  const int64_t num = sc.a0_units * (sc.S - t_done) + sc.S / 2;  // numerator of sweep t_done + 1
-  w.q = (int32_t)(num / sc.S);
-  w.r = (uint32_t)(num % sc.S);
-  w.aq = (int32_t)(sc.a0_units / sc.S);
-  w.ar = (uint32_t)(sc.a0_units % sc.S);
-  w.u = (uint32_t)(sc.S - t_done);
   w.alpha_cont_per = sc.alpha0_turns / (float)sc.S;
   w.twist2 = sc.twist_num2;
   w.ratio = sc.dwt_ratio;
