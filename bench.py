@@ -35,8 +35,8 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-ops per second, non-packed FP32
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the counter
 # reads for a 256 MiB device copy (FETCH_SIZE 131087 KiB -> x2.0; WRITE_SIZE
 # 262144 KiB -> x1.0).  Valid only for the kernel sources they were taken on.
-TRAFFIC = dict(fetch_kib=4196.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
-               sources_sha256="2dbfaafa043e8f0dac78fa7a9fac309f23099a7cfe76c665cb5a28d05f68faee")
+TRAFFIC = dict(fetch_kib=4191.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
+               sources_sha256="638b17d54047e9538b5b3a15b478bf47c730f66a540fbb820ae5ed0766db8cf2")
 TRAFFIC_SOURCES = ("paper_2605_30355_amd/csrc/kernels.hip",
                    "paper_2605_30355_amd/csrc/device_common.hpp")
 
