@@ -291,17 +291,23 @@ __device__ __forceinline__ void schedule_at(const SweepSchedule &sc, uint32_t t,
 // One wave's table of 64 sweeps: lane i holds alpha and the twist of sweep
 // t_next + i (clamped to S); a sweep then reads its pair with two readlanes
 // instead of stepping the ramp on the scalar and vector units every sweep.
+// Bit i of twists is set when sweep t_next + i ends with a twist
+// (t % period == 0), so a sweep tests one bit instead of stepping a counter.
 struct ScheduleChunk {
   float alpha, twist;
+  uint64_t twists;
   __device__ __forceinline__ void fill(const SweepSchedule &sc, uint32_t t_next) {
     const uint32_t lane = __lane_id();
     const uint32_t t = min(t_next + lane, sc.S);
     schedule_at(sc, t, alpha, twist);
+    const uint32_t tl = t_next + lane;
+    twists = __ballot(sc.period > 0 && tl <= sc.S && tl % (uint32_t)sc.period == 0u);
   }
   __device__ __forceinline__ void get(uint32_t i, float &a, float &tw) const {
     a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(alpha), i));
     tw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(twist), i));
   }
+  __device__ __forceinline__ bool twist_at(uint32_t i) const { return (twists >> i) & 1u; }
 };
 
 // The device schedule after t_done sweeps (host side).

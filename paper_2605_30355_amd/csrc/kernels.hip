@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   int32_t *Ks = reinterpret_cast<int32_t *>(dir_buf + kThetaFloats);          // [C]
   if constexpr (EMAX == 0)
     for (int c = tid; c < a.C; c += nth) Ks[c] = a.Kc[c];
-  int tw = 0;  // twists done in this call
+  uint32_t tw = 0;  // twists done in this call
 
   // register-resident lane schedule; a masked lane updates two dummy rows
   // with J = 0 (a no-op), so the slots need no branches
@@ -155,10 +155,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     if constexpr (FUSE && EXACT) {
       // EMAX slots, one class each.  On a twist sweep the last class twists
       // the rows it updates and, concurrently, the rows it leaves out.
-      const bool fuse_now = sc.phase + 1 == sc.period;
+      const bool fuse_now = chunk.twist_at(it & 63u);
       float cth[RW], tws[RW];
       if (fuse_now) {
-        const int slot = tw % kThetaChunk;
+        const int slot = (int)(tw % (uint32_t)kThetaChunk);
         tw++;
         if (slot == 0) {
           theta_fill(theta_buf, nullptr, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0,
@@ -208,10 +208,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       if constexpr (FUSE) {
         // streamed form: on a twist sweep the last class twists the rows it
         // updates, then each thread twists its fuse_k rows outside that class
-        const bool fuse_now = sc.phase + 1 == sc.period;
+        const bool fuse_now = chunk.twist_at(it & 63u);
         float cth[RW], tws[RW];
         if (fuse_now) {
-          const int slot = tw % kThetaChunk;
+          const int slot = (int)(tw % (uint32_t)kThetaChunk);
           tw++;
           if (slot == 0) {
             theta_fill(theta_buf, nullptr, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0,
@@ -274,10 +274,9 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     // directions) come from the LDS tables, refilled by the whole workgroup
     // every kThetaChunk twists.
     if constexpr (FUSE) {
-      if (++sc.phase == sc.period) sc.phase = 0;  // the twist ran inside the last class
-    } else if (sc.period > 0 && ++sc.phase == sc.period) {
-      sc.phase = 0;
-      const int slot = tw % kThetaChunk;
+      // the twist ran inside the last class
+    } else if (chunk.twist_at(it & 63u)) {
+      const int slot = (int)(tw % (uint32_t)kThetaChunk);
       if (slot == 0) {
         theta_fill(theta_buf, a.h_slot != nullptr ? dir_buf : nullptr, kThetaChunk, RW, t,
                    sc.period, a.rid0 + (uint32_t)r0, a.k0, a.k1, sc.win, sc.tshift, sc.tscale);
