@@ -67,8 +67,13 @@ enum { COSM_ORDER_LARGEST_LAST = 0x100 };
  * point (units of 2^-16 turn), wrapping by integer overflow; needs the GRID
  * schedule, which it runs on the 2^-16 turn grid (steps on 2^-15, initial
  * phases and twist angles the top 16 bits of the same draws), so trajectories
- * are exact; the window must be a multiple of 2^-16 turn. */
-enum { COSM_STORE_FP32 = 0, COSM_STORE_FP16 = 1, COSM_STORE_BF16 = 2, COSM_STORE_FIX16 = 3 };
+ * are exact; the window must be a multiple of 2^-16 turn.  FIX32: x in 32-bit
+ * fixed point (units of 2^-32 turn), wrapping by integer overflow; needs the
+ * GRID schedule, on the same 2^-23 turn grid as FP32, and gives the FP32
+ * trajectory bit for bit with integer instead of floating-point arithmetic
+ * (phases set from outside are rounded to 2^-32 turn). */
+enum { COSM_STORE_FP32 = 0, COSM_STORE_FP16 = 1, COSM_STORE_BF16 = 2, COSM_STORE_FIX16 = 3,
+       COSM_STORE_FIX32 = 4 };
 /* Where a replica's phases live during a sweep.  LDS: a workgroup holds whole
  * replicas in LDS for all sweeps of a call.  HBM: phases stay in device memory,
  * one launch per colour class.  PLAIN: one replica per launch, one launch per
@@ -78,6 +83,19 @@ enum { COSM_RES_AUTO = 0, COSM_RES_LDS = 1, COSM_RES_HBM = 2, COSM_RES_PLAIN = 3
  * FIX16 storage), so sweeps are exact; the window must be a multiple of 2^-22
  * turn.  CONTINUOUS: the literal ramp alpha0 (S - t + 1) / S in FP32. */
 enum { COSM_SCHED_GRID = 0, COSM_SCHED_CONTINUOUS = 1 };
+/* Layout of the LDS form.  PAIR: every edge update reads and writes both
+ * endpoint rows in LDS.  REGISTER: an independent set of vertices stays in
+ * registers, a few per thread; each edge with an endpoint there is applied by
+ * that endpoint's thread, which touches LDS only for the other endpoint (the
+ * even tori: every edge), the remaining edges as in PAIR.  The same updates in
+ * the same class order: trajectories are identical.  REGISTER needs FP32,
+ * FIX32 or FIX16 storage, at most 8 classes, no bias fields, and few enough
+ * edges outside the register set (COSM_ERANGE otherwise when requested).
+ * REGISTER moves far fewer LDS bytes but needs more vector and scalar
+ * instructions per update (the u / v roles of each edge, the dummy lanes of
+ * vertices without an edge in a class); on gfx950 the pair layout, limited by
+ * both, measured faster in every configuration tried, so AUTO means PAIR. */
+enum { COSM_LDS_FORM_AUTO = 0, COSM_LDS_FORM_PAIR = 1, COSM_LDS_FORM_REGISTER = 2 };
 /* SCS: Eqs. (12)-(13), classes one after another.  FULL_GRADIENT: Eq. (8), all
  * edges read the same state (the "without SCS" variant of Table VII). */
 enum { COSM_UPDATE_SCS = 0, COSM_UPDATE_FULL_GRADIENT = 1 };
@@ -106,6 +124,7 @@ typedef struct {
   int32_t threads_per_wg;   /* LDS form: threads per workgroup; 0 = autotune */
   int32_t update;           /* COSM_UPDATE_* */
   int32_t readout;          /* COSM_READOUT_* */
+  int32_t lds_form;         /* COSM_LDS_FORM_*: layout of the LDS form (AUTO: measured) */
 } cosm_params;
 
 /* Fill *p with Table IX/X defaults: alpha0 14, ratio 0.5, period 3, window 90,
@@ -295,6 +314,8 @@ typedef struct {
   int32_t max_class_edges;
   int64_t sweep_launches;  /* sweep kernels launched so far */
   double sweep_kernel_ms;  /* their summed duration (HIP events), when timing is on */
+  int32_t lds_form;        /* resolved COSM_LDS_FORM_* (0 outside the LDS form) */
+  int32_t register_rows;   /* REGISTER: register vertices per thread */
 } cosm_info;
 int cosm_get_info(const cosm_state *s, cosm_info *out);
 

@@ -8,11 +8,12 @@ and the HIP stream.  Importing the package does not touch the GPU; creating a
 """
 from .cosm import (  # noqa: F401
     COLOR_BALANCED, COLOR_GREEDY, COLOR_MINIMUM, COLOR_MISRA_GRIES, COLOR_TORUS,
+    LDS_FORM_AUTO, LDS_FORM_PAIR, LDS_FORM_REGISTER,
     ORDER_LARGEST_LAST,
     RES_AUTO, RES_HBM, RES_LDS, RES_PLAIN,
     READOUT_BISECTORS, READOUT_OPTIMAL,
     SCHED_CONTINUOUS, SCHED_GRID,
-    STORE_BF16, STORE_FIX16, STORE_FP16, STORE_FP32,
+    STORE_BF16, STORE_FIX16, STORE_FIX32, STORE_FP16, STORE_FP32,
     UNIT_DEGREES, UNIT_RADIANS, UNIT_TURNS,
     UPDATE_FULL_GRADIENT, UPDATE_SCS,
     Batch, CosmError, Params, State, TTSResult,

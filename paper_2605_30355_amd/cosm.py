@@ -14,13 +14,14 @@ COSM_OK = 0
 STATUS_NAMES = {0: "COSM_OK", -1: "COSM_EINVAL", -2: "COSM_EDUP", -3: "COSM_ECOLOR",
                 -4: "COSM_ERANGE", -5: "COSM_ENOMEM", -6: "COSM_EDEVICE", -7: "COSM_ESTATE"}
 COLOR_GREEDY, COLOR_MISRA_GRIES, COLOR_TORUS, COLOR_BALANCED, COLOR_MINIMUM = 0, 1, 2, 3, 4
-STORE_FP32, STORE_FP16, STORE_BF16, STORE_FIX16 = 0, 1, 2, 3
+STORE_FP32, STORE_FP16, STORE_BF16, STORE_FIX16, STORE_FIX32 = 0, 1, 2, 3, 4
 ORDER_LARGEST_LAST = 0x100  # OR into a colouring method: the largest class goes last
 RES_AUTO, RES_LDS, RES_HBM, RES_PLAIN = 0, 1, 2, 3
 SCHED_GRID, SCHED_CONTINUOUS = 0, 1
 UPDATE_SCS, UPDATE_FULL_GRADIENT = 0, 1
 READOUT_BISECTORS, READOUT_OPTIMAL = 0, 1
 UNIT_TURNS, UNIT_DEGREES, UNIT_RADIANS = 0, 1, 2
+LDS_FORM_AUTO, LDS_FORM_PAIR, LDS_FORM_REGISTER = 0, 1, 2
 
 # Every function declared in include/cosm.h.
 ABI_FUNCTIONS = (
@@ -46,7 +47,7 @@ class _CParams(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("residency", ctypes.c_int32), ("replicas_per_wg", ctypes.c_int32),
                 ("threads_per_wg", ctypes.c_int32), ("update", ctypes.c_int32),
-                ("readout", ctypes.c_int32)]
+                ("readout", ctypes.c_int32), ("lds_form", ctypes.c_int32)]
 
 
 class _CTTS(ctypes.Structure):
@@ -64,7 +65,8 @@ class _CInfo(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("replicas_per_wg", ctypes.c_int32),
                 ("threads_per_wg", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("max_class_edges", ctypes.c_int32),
-                ("sweep_launches", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double)]
+                ("sweep_launches", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double),
+                ("lds_form", ctypes.c_int32), ("register_rows", ctypes.c_int32)]
 
 
 _lib = None
@@ -192,12 +194,13 @@ class Params:
     threads_per_wg: int = 0
     update: int = UPDATE_SCS
     readout: int = READOUT_BISECTORS
+    lds_form: int = LDS_FORM_AUTO
 
     def _c(self) -> _CParams:
         return _CParams(self.alpha0_deg, self.dwt_ratio, self.dwt_period, self.dwt_window_deg,
                         self.n_bisectors, self.sweeps_per_trial, self.schedule, self.storage,
                         self.residency, self.replicas_per_wg, self.threads_per_wg, self.update,
-                        self.readout)
+                        self.readout, self.lds_form)
 
 
 def default_params() -> Params:

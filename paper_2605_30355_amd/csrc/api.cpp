@@ -22,14 +22,17 @@ void clear_error() { g_last_error.clear(); }
 
 namespace {
 
-int storage_bytes(int32_t storage) { return storage == COSM_STORE_FP32 ? 4 : 2; }  // FP16, BF16, FIX16: 2
-int per_word(int32_t storage) { return storage == COSM_STORE_FP32 ? 1 : 2; }
+bool wide_storage(int32_t storage) {
+  return storage == COSM_STORE_FP32 || storage == COSM_STORE_FIX32;
+}
+int storage_bytes(int32_t storage) { return wide_storage(storage) ? 4 : 2; }  // FP16, BF16, FIX16: 2
+int per_word(int32_t storage) { return wide_storage(storage) ? 1 : 2; }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every device buffer inside one allocation.
 struct MemPlan {
-  size_t phases, desc, class_off, slot_vertex, h_slot, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
+  size_t phases, desc, class_off, slot_vertex, reg_vertex, h_slot, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
       inc_off, inc_nbr, inc_J, phases_alt, opt_keys, opt_keys2, opt_vals, opt_vals2, opt_off,
       opt_temp, opt_temp_bytes, codes, total;
 };
@@ -46,10 +49,14 @@ MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_param
   mp.phases = take(nr * storage_bytes(p.storage));
   // lane schedule: at most 32 lanes per edge group plus one partial pass per
   // class, the repeated slots, then the rows outside the last class
-  mp.desc = take(((size_t)32 * m + (size_t)1024 * C + 1024 +
-                  (size_t)(kStreamRepeat + kFuseRowsMax) * 1024) * sizeof(EdgeDesc));
+  // (or the register-owner form's [C][K + 1][nth])
+  const size_t pair_desc = (size_t)32 * m + (size_t)1024 * C + 1024 +
+                           (size_t)(kStreamRepeat + kFuseRowsMax) * 1024;
+  const size_t reg_desc = (size_t)std::min(C, kRegClassesMax) * (kRegKMax + 1) * 1024;
+  mp.desc = take(std::max(pair_desc, reg_desc) * sizeof(EdgeDesc));
   mp.class_off = take(((size_t)C + 1) * 4);
-  mp.slot_vertex = take(((size_t)n + 1) * 4);
+  mp.slot_vertex = take(((size_t)n + kRegRowsSlack) * 4);
+  mp.reg_vertex = take((size_t)kRegKMax * 1024 * 4);
   mp.h_slot = take(((size_t)n + 1) * 4);
   mp.eu = take((size_t)m * 4);
   mp.ev = take((size_t)m * 4);
@@ -100,11 +107,15 @@ int check_params(const cosm_params *p) {
   if (p->sweeps_per_trial < 1 || p->sweeps_per_trial > ((int64_t)1 << 31))
     return bad("sweeps_per_trial must be in [1, 2^31]");
   if (p->schedule != COSM_SCHED_GRID && p->schedule != COSM_SCHED_CONTINUOUS) return bad("bad schedule");
-  if (p->storage < COSM_STORE_FP32 || p->storage > COSM_STORE_FIX16) return bad("bad storage");
+  if (p->storage < COSM_STORE_FP32 || p->storage > COSM_STORE_FIX32) return bad("bad storage");
   if (p->storage == COSM_STORE_FIX16 && p->schedule != COSM_SCHED_GRID)
     return bad("FIX16 storage needs the GRID schedule");
+  if (p->storage == COSM_STORE_FIX32 && p->schedule != COSM_SCHED_GRID)
+    return bad("FIX32 storage needs the GRID schedule");
   if (p->residency < COSM_RES_AUTO || p->residency > COSM_RES_PLAIN) return bad("bad residency");
   if (p->update != COSM_UPDATE_SCS && p->update != COSM_UPDATE_FULL_GRADIENT) return bad("bad update");
+  if (p->lds_form < COSM_LDS_FORM_AUTO || p->lds_form > COSM_LDS_FORM_REGISTER)
+    return bad("bad lds_form");
   if (p->readout != COSM_READOUT_BISECTORS && p->readout != COSM_READOUT_OPTIMAL)
     return bad("bad readout");
   if (p->replicas_per_wg < 0 || p->threads_per_wg < 0 || p->threads_per_wg > 1024)
@@ -119,6 +130,9 @@ int check_params(const cosm_params *p) {
 int make_schedule(const cosm_params &p, int32_t max_abs_J, Schedule *sc) {
   if (p.alpha0_deg * max_abs_J >= 360.0)
     return set_error(COSM_ERANGE, "alpha0 * |J| must stay below a full turn");
+  // FIX32 steps are signed 32-bit integers of 2^-32 turn
+  if (p.storage == COSM_STORE_FIX32 && p.alpha0_deg * max_abs_J >= 180.0)
+    return set_error(COSM_ERANGE, "FIX32 needs alpha0 * |J| below half a turn");
   if (p.alpha0_deg * p.dwt_ratio >= 360.0)
     return set_error(COSM_ERANGE, "dwt_ratio * alpha0 must stay below a full turn");
   sc->grid = p.schedule == COSM_SCHED_GRID;
@@ -218,6 +232,12 @@ int choose_shape(cosm_state *s) {
       sh.lds_bytes = (int32_t)lds_sweep_bytes(s->n_slots, chosen, s->C);
       if (int rc = build_lds_schedule(*s, chosen, p.threads_per_wg, &s->lds, true)) return rc;
       sh.threads = s->lds.nth;
+      if (p.lds_form == COSM_LDS_FORM_REGISTER) {
+        // the autotuner, when it runs, chooses among register shapes only
+        if (int rc = pick_reg_schedule(s, chosen, p.threads_per_wg)) return rc;
+        sh.threads = s->lds.nth;
+        sh.lds_bytes = (int32_t)lds_sweep_bytes(s->lds.n_rows, chosen, s->C);
+      }
     }
   }
   if (sh.residency != COSM_RES_LDS) {
@@ -266,6 +286,7 @@ void cosm_default_params(cosm_params *p) {
   p->threads_per_wg = 0;
   p->update = COSM_UPDATE_SCS;
   p->readout = COSM_READOUT_BISECTORS;
+  p->lds_form = COSM_LDS_FORM_AUTO;
 }
 
 int cosm_build_partitions(int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
@@ -466,6 +487,7 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
   d.desc = at<EdgeDesc>(s->base, mp.desc);
   d.class_off = at<int32_t>(s->base, mp.class_off);
   d.slot_vertex = at<int32_t>(s->base, mp.slot_vertex);
+  d.reg_vertex = at<int32_t>(s->base, mp.reg_vertex);
   d.h_slot = at<int32_t>(s->base, mp.h_slot);
   d.eu = at<int32_t>(s->base, mp.eu);
   d.ev = at<int32_t>(s->base, mp.ev);
@@ -502,6 +524,7 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
     rc = rc ? rc : up(d.desc, s->lds.desc.data(), s->lds.desc.size() * sizeof(EdgeDesc));
     rc = rc ? rc : up(d.class_off, s->lds.K.data(), s->lds.K.size() * 4);
     rc = rc ? rc : up(d.slot_vertex, s->lds.slot_vertex.data(), s->lds.slot_vertex.size() * 4);
+    rc = rc ? rc : up(d.reg_vertex, s->lds.reg_vertex.data(), s->lds.reg_vertex.size() * 4);
     rc = rc ? rc : upload_h_slot(s);
   }
   rc = rc ? rc : up(d.eu, eu, (size_t)m * 4);
@@ -723,6 +746,10 @@ int cosm_get_info(const cosm_state *s, cosm_info *out) {
   out->max_class_edges = s->max_class;
   out->sweep_launches = s->launches;
   out->sweep_kernel_ms = s->kernel_ms;
+  out->lds_form = s->shape.residency != COSM_RES_LDS ? 0
+                  : s->lds.reg_k > 0                 ? COSM_LDS_FORM_REGISTER
+                                                     : COSM_LDS_FORM_PAIR;
+  out->register_rows = s->shape.residency == COSM_RES_LDS ? s->lds.reg_k : 0;
   return COSM_OK;
 }
 

@@ -1,7 +1,9 @@
 // autotune.cpp -- picks the LDS sweep kernel's shape by measurement.
 //
 // Candidates: every LDS row width that fits (1, 2 or 4 words per row, i.e. 1-4
-// FP32 or 2-8 16-bit replicas per workgroup) crossed with a few thread counts.
+// FP32 or 2-8 16-bit replicas per workgroup) crossed with a few thread counts
+// (pair layout), or with 1, 2 or 4 register rows per thread when the register
+// layout is requested.
 // Each candidate runs a short timed probe on the state's own phases (which are
 // re-drawn afterwards, so the probe leaves no trace in the trajectory), and the
 // fastest shape is kept.  Results are cached per process, keyed by the
@@ -19,9 +21,10 @@ namespace cosm {
 
 namespace {
 
-using Key = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t, int32_t, int64_t>;
+using Key = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t, int32_t, int64_t, int32_t>;
+using Shape = std::tuple<int32_t, int32_t, int32_t>;  // (W, threads, register rows or 0)
 std::mutex g_cache_mu;
-std::map<Key, std::pair<int32_t, int32_t>> g_cache;  // -> (W, threads)
+std::map<Key, Shape> g_cache;
 
 Key make_key(const cosm_state &s) {
   int64_t h = 1469598103934665603LL;  // FNV-1a over the class sizes
@@ -35,7 +38,7 @@ Key make_key(const cosm_state &s) {
     }
     for (int32_t d : deg) delta = std::max(delta, d);
   }
-  return Key{s.n, s.m, s.C, delta, s.R, s.p.storage, h};
+  return Key{s.n, s.m, s.C, delta, s.R, s.p.storage, h, s.p.lds_form};
 }
 
 int upload_schedule(cosm_state *s) {
@@ -47,17 +50,24 @@ int upload_schedule(cosm_state *s) {
                                   hipMemcpyHostToDevice, s->stream));
   COSM_HIP_CHECK(hipMemcpyAsync(s->d.slot_vertex, L.slot_vertex.data(),
                                 L.slot_vertex.size() * 4, hipMemcpyHostToDevice, s->stream));
+  if (L.reg_k > 0)
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.reg_vertex, L.reg_vertex.data(), L.reg_vertex.size() * 4,
+                                  hipMemcpyHostToDevice, s->stream));
   if (int rc = upload_h_slot(s)) return rc;
   COSM_HIP_CHECK(hipStreamSynchronize(s->stream));  // host vectors may change next
   return COSM_OK;
 }
 
-int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw) {
-  if (int rc = build_lds_schedule(*s, W, nth, &s->lds, true)) return rc;
+int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw, int32_t K) {
+  if (K > 0) {
+    if (int rc = reg_schedule_for(*s, W, K, nth, &s->lds)) return rc;
+  } else {
+    if (int rc = build_lds_schedule(*s, W, nth, &s->lds, true)) return rc;
+  }
   s->shape.residency = COSM_RES_LDS;
   s->shape.rw = W * pw;
   s->shape.blocks = (s->R + s->shape.rw - 1) / s->shape.rw;
-  s->shape.lds_bytes = (int32_t)lds_sweep_bytes(s->n_slots, W, s->C);
+  s->shape.lds_bytes = (int32_t)lds_sweep_bytes(K > 0 ? s->lds.n_rows : s->n_slots, W, s->C);
   s->shape.threads = s->lds.nth;
   return upload_schedule(s);
 }
@@ -74,63 +84,112 @@ int upload_h_slot(cosm_state *s) {
   return COSM_OK;
 }
 
+bool reg_form_supported(const cosm_state &s) {
+  const int32_t st = s.p.storage;
+  return (st == COSM_STORE_FP32 || st == COSM_STORE_FIX32 || st == COSM_STORE_FIX16) && !s.has_h &&
+         s.C <= kRegClassesMax && s.m > 0 && s.p.update == COSM_UPDATE_SCS;
+}
+
+int reg_schedule_for(const cosm_state &s, int32_t W, int32_t K, int32_t nth, LdsSchedule *out) {
+  if (!reg_form_supported(s))
+    return set_error(COSM_ERANGE, "the register form needs FP32, FIX32 or FIX16 storage, at most "
+                                  "8 classes, edges and no bias fields");
+  if (K == 4 && s.C > 4) return set_error(COSM_ERANGE, "4 register rows need at most 4 classes");
+  LdsSchedule L;
+  if (int rc = build_reg_schedule(s, W, K, nth, &L)) return rc;
+  if (lds_sweep_bytes(L.n_rows, W, s.C) > (size_t)lds_capacity_bytes())
+    return set_error(COSM_ERANGE, "register form: rows do not fit in LDS");
+  *out = std::move(L);
+  return COSM_OK;
+}
+
+// The register form for a fixed row width: the fewest register rows per
+// thread that give a schedule.
+int pick_reg_schedule(cosm_state *s, int32_t W, int32_t nth) {
+  int rc = COSM_ERANGE;
+  for (int32_t K : {1, 2, 4}) {
+    rc = reg_schedule_for(*s, W, K, nth, &s->lds);
+    if (rc == COSM_OK) {
+      clear_error();
+      return COSM_OK;
+    }
+  }
+  return rc;
+}
+
 int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
-  const int32_t pw = s->p.storage == COSM_STORE_FP32 ? 1 : 2;
+  const int32_t pw = (s->p.storage == COSM_STORE_FP32 || s->p.storage == COSM_STORE_FIX32) ? 1 : 2;
   const Key key = make_key(*s);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find(key);
-    if (it != g_cache.end()) return apply_shape(s, it->second.first, it->second.second, pw);
+    if (it != g_cache.end())
+      return apply_shape(s, std::get<0>(it->second), std::get<1>(it->second), pw,
+                         std::get<2>(it->second));
   }
   const int64_t probe = std::min<int64_t>(256, s->p.sweeps_per_trial);
   hipEvent_t e0, e1;
   COSM_HIP_CHECK(hipEventCreate(&e0));
   COSM_HIP_CHECK(hipEventCreate(&e1));
   float best_ms = 0.0f;
-  int32_t best_W = 0, best_nth = 0;
+  int32_t best_W = 0, best_nth = 0, best_K = 0;
   int rc = COSM_OK;
   const bool timing = s->timing;
   s->timing = false;
-  std::vector<std::pair<int32_t, int32_t>> tried;
-  for (int32_t W : widths) {
-    int32_t auto_nth = 0;
-    for (int32_t req : {0, 512, 768, 1024}) {
-      if (req > 0 && req < auto_nth / 2) continue;  // far too few threads for one pass
-      rc = apply_shape(s, W, req, pw);
-      if (rc) break;
-      if (req == 0) auto_nth = s->lds.nth;
-      if (std::find(tried.begin(), tried.end(), std::make_pair(W, s->lds.nth)) != tried.end())
-        continue;
-      tried.emplace_back(W, s->lds.nth);
-      const int64_t t_saved = s->t;
-      rc = launch_sweeps(s, probe);  // warm-up
-      s->t = t_saved;
-      if (rc) break;
-      // the faster of two timed probes (single probes of a few hundred
-      // microseconds vary by several per cent)
-      float ms = 0.0f;
-      for (int rep = 0; rep < 2 && rc == COSM_OK; rep++) {
-        if (hipEventRecord(e0, s->stream) != hipSuccess) { rc = set_error(COSM_EDEVICE, "event"); break; }
-        rc = launch_sweeps(s, probe);
-        s->t = t_saved;
-        if (rc) break;
-        if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-          rc = set_error(COSM_EDEVICE, "event");
-          break;
-        }
-        float one = 0.0f;
-        (void)hipEventElapsedTime(&one, e0, e1);
-        ms = rep == 0 ? one : std::min(ms, one);
-      }
-      if (rc) break;
-      if (best_W == 0 || ms < best_ms) {
-        best_ms = ms;
-        best_W = W;
-        best_nth = s->lds.nth;
-      }
+  // candidates: (W, requested threads, register rows); pair form first
+  std::vector<Shape> cands;
+  if (s->p.lds_form != COSM_LDS_FORM_REGISTER)
+    for (int32_t W : widths)
+      for (int32_t req : {0, 512, 768, 1024}) cands.emplace_back(W, req, 0);
+  if (s->p.lds_form == COSM_LDS_FORM_REGISTER && reg_form_supported(*s))
+    for (int32_t W : widths)
+      for (int32_t K : {1, 2, 4}) cands.emplace_back(W, 0, K);
+  std::vector<Shape> tried;
+  int32_t auto_nth = 0;
+  for (const Shape &cand : cands) {
+    const int32_t W = std::get<0>(cand), req = std::get<1>(cand), K = std::get<2>(cand);
+    if (K == 0 && req > 0 && req < auto_nth / 2) continue;  // far too few threads for one pass
+    rc = apply_shape(s, W, req, pw, K);
+    if (rc && K > 0) {  // the register form does not apply to this shape
+      rc = COSM_OK;
+      clear_error();
+      continue;
     }
     if (rc) break;
+    if (K == 0 && req == 0) auto_nth = s->lds.nth;
+    const Shape got{W, s->lds.nth, K};
+    if (std::find(tried.begin(), tried.end(), got) != tried.end()) continue;
+    tried.push_back(got);
+    const int64_t t_saved = s->t;
+    rc = launch_sweeps(s, probe);  // warm-up
+    s->t = t_saved;
+    if (rc) break;
+    // the faster of two timed probes (single probes of a few hundred
+    // microseconds vary by several per cent)
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2 && rc == COSM_OK; rep++) {
+      if (hipEventRecord(e0, s->stream) != hipSuccess) { rc = set_error(COSM_EDEVICE, "event"); break; }
+      rc = launch_sweeps(s, probe);
+      s->t = t_saved;
+      if (rc) break;
+      if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = set_error(COSM_EDEVICE, "event");
+        break;
+      }
+      float one = 0.0f;
+      (void)hipEventElapsedTime(&one, e0, e1);
+      ms = rep == 0 ? one : std::min(ms, one);
+    }
+    if (rc) break;
+    if (best_W == 0 || ms < best_ms) {
+      best_ms = ms;
+      best_W = W;
+      best_nth = s->lds.nth;
+      best_K = K;
+    }
   }
+  if (rc == COSM_OK && best_W == 0)
+    rc = set_error(COSM_ERANGE, "no LDS shape applies (register form requested)");
   s->timing = timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -139,9 +198,9 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
   s->kernel_ms = 0.0;
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    g_cache[key] = {best_W, best_nth};
+    g_cache[key] = Shape{best_W, best_nth, best_K};
   }
-  rc = apply_shape(s, best_W, best_nth, pw);
+  rc = apply_shape(s, best_W, best_nth, pw, best_K);
   if (rc) return rc;
   return launch_init(s);  // the probes moved the phases: draw them again
 }

@@ -135,10 +135,11 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
     if (((t - 1) & 63u) == 0u) chunk.fill(sc, t);
     float alpha, twist;
     chunk.get((t - 1) & 63u, alpha, twist);
+    const float alpha_s = alpha * F::kStepScale;
     if (g.total_slots > 0)
       stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
         edge_rows_sets<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, set_bytes,
-                              nsets, alpha * d.J);
+                              nsets, alpha_s * d.J);
       });
     if (sc.period > 0 && ++sc.phase == sc.period) {
       sc.phase = 0;
@@ -303,7 +304,7 @@ int cosm_batch_create(cosm_batch **out, int32_t storage, int32_t max_graphs, int
   clear_error();
   if (out == nullptr) return set_error(COSM_EINVAL, "out must not be NULL");
   *out = nullptr;
-  if (storage < COSM_STORE_FP32 || storage > COSM_STORE_FIX16) return set_error(COSM_EINVAL, "bad storage");
+  if (storage < COSM_STORE_FP32 || storage > COSM_STORE_FIX32) return set_error(COSM_EINVAL, "bad storage");
   if (max_graphs < 1 || max_n < 1 || max_n > 65536 || max_bisectors < 1 || max_bisectors > 32767)
     return set_error(COSM_EINVAL, "bad batch limits");
   cosm_batch *b = new cosm_batch();
@@ -357,7 +358,8 @@ int cosm_batch_create(cosm_batch **out, int32_t storage, int32_t max_graphs, int
     case COSM_STORE_FP32: set_attrs<COSM_STORE_FP32>(b); break;
     case COSM_STORE_FP16: set_attrs<COSM_STORE_FP16>(b); break;
     case COSM_STORE_BF16: set_attrs<COSM_STORE_BF16>(b); break;
-    default: set_attrs<COSM_STORE_FIX16>(b); break;
+    case COSM_STORE_FIX16: set_attrs<COSM_STORE_FIX16>(b); break;
+    default: set_attrs<COSM_STORE_FIX32>(b); break;
   }
   *out = b;
   return COSM_OK;
@@ -420,7 +422,7 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
   s.n_slots = n;
   int rc = make_schedule(s.p, max_abs_J, &s.sched);
   // row width: the widest that leaves room for at least one replica set
-  const int32_t pw = b->storage == COSM_STORE_FP32 ? 1 : 2;
+  const int32_t pw = (b->storage == COSM_STORE_FP32 || b->storage == COSM_STORE_FIX32) ? 1 : 2;
   int32_t W = 0;
   for (int32_t w : {4, 2, 1})
     if (W == 0 && (size_t)n * w * 4 + 2 * kMaxSetReplicas * 4 + (size_t)num_colours * 4 <= b->lds_budget) W = w;
@@ -533,7 +535,7 @@ int cosm_batch_run(cosm_batch *b, const int32_t *graph_ids, int32_t count) {
   // shrinking the sets while the run would leave CUs without an item
   std::vector<int32_t> sets(ids.size());
   for (size_t k = 0; k < ids.size(); k++) sets[k] = b->graphs[(size_t)ids[k]]->sets_max;
-  const int32_t pw = b->storage == COSM_STORE_FP32 ? 1 : 2;
+  const int32_t pw = (b->storage == COSM_STORE_FP32 || b->storage == COSM_STORE_FIX32) ? 1 : 2;
   auto count_items = [&]() {
     int64_t total = 0;
     for (size_t k = 0; k < ids.size(); k++) {
@@ -619,7 +621,8 @@ int cosm_batch_run(cosm_batch *b, const int32_t *graph_ids, int32_t count) {
       case COSM_STORE_FP32: enqueue_run<COSM_STORE_FP32>(b); break;
       case COSM_STORE_FP16: enqueue_run<COSM_STORE_FP16>(b); break;
       case COSM_STORE_BF16: enqueue_run<COSM_STORE_BF16>(b); break;
-      default: enqueue_run<COSM_STORE_FIX16>(b); break;
+      case COSM_STORE_FIX16: enqueue_run<COSM_STORE_FIX16>(b); break;
+      default: enqueue_run<COSM_STORE_FIX32>(b); break;
     }
     COSM_HIP_CHECK(hipStreamEndCapture(b->stream, &b->graph));
     COSM_HIP_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));

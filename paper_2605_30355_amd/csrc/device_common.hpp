@@ -81,10 +81,14 @@ __device__ __forceinline__ float fract1(float v) { return __builtin_amdgcn_fract
 template <int ST>
 struct Fmt;
 
+// kStepScale: the factor from turns to the step argument of update_words
+// (1 for the FP32-arithmetic formats; the fixed-point formats take the step in
+// their own integer units, scaled once per sweep instead of once per edge).
 template <>
 struct Fmt<COSM_STORE_FP32> {
   using elem_t = float;
   static constexpr int kPerWord = 1;
+  static constexpr float kStepScale = 1.0f;
   __device__ __forceinline__ static float wrap(float v) { return fract1(v); }
   __device__ __forceinline__ static float from_turn(float x) { return x; }
   __device__ __forceinline__ static float to_turn(float v) { return v; }
@@ -109,6 +113,7 @@ struct Fmt<COSM_STORE_FP32> {
 template <int ST>
 struct Fmt16 {
   static constexpr int kPerWord = 2;
+  static constexpr float kStepScale = 1.0f;
   __device__ __forceinline__ static float wrap(float v) { return v - __builtin_rintf(v); }
   __device__ __forceinline__ static float from_turn(float x) { return x - 0.5f; }
   __device__ __forceinline__ static float to_turn(float v) { return fract1(v + 0.5f); }
@@ -174,6 +179,7 @@ struct Fmt<COSM_STORE_BF16> : Fmt16<COSM_STORE_BF16> {};
 template <>
 struct Fmt<COSM_STORE_FIX16> {
   static constexpr int kPerWord = 2;
+  static constexpr float kStepScale = 65536.0f;
   __device__ __forceinline__ static float wrap(float v) { return fract1(v); }
   __device__ __forceinline__ static float from_turn(float x) { return x; }
   __device__ __forceinline__ static float to_turn(float v) { return v; }
@@ -204,6 +210,50 @@ struct Fmt<COSM_STORE_FIX16> {
     for (int k = 0; k < W; k++) w[k] = enc(v[2 * k]) | (enc(v[2 * k + 1]) << 16);
   }
 };
+
+// 32-bit fixed point: the stored integer k is x = k 2^-32 turn.  Under the
+// GRID schedule every phase is a multiple of 2^-23 turn, so the value x is
+// exact in FP32 and the FP32 forms below work unchanged; the LDS sweep updates
+// the integers directly, where the wrap to [0, 1) turn is the overflow of the
+// 32-bit add.  The trajectory is the FP32 one bit for bit.
+template <>
+struct Fmt<COSM_STORE_FIX32> {
+  static constexpr int kPerWord = 1;
+  static constexpr float kStepScale = 4294967296.0f;
+  __device__ __forceinline__ static float wrap(float v) { return fract1(v); }
+  __device__ __forceinline__ static float from_turn(float x) { return x; }
+  __device__ __forceinline__ static float to_turn(float v) { return v; }
+  __device__ __forceinline__ static float dec(uint32_t bits) {
+    return (float)bits * (1.0f / 4294967296.0f);
+  }
+  // nearest multiple of 2^-32 turn (v in [0, 1) as FP32: below 2^32 - 2^8
+  // after scaling, so no wrap is needed)
+  __device__ __forceinline__ static uint32_t enc(float v) {
+    return (uint32_t)__builtin_rintf(v * 4294967296.0f);
+  }
+  __device__ __forceinline__ static float load_elem(const void *p, size_t i) {
+    return dec(as_global(static_cast<const uint32_t *>(p))[i]);
+  }
+  __device__ __forceinline__ static void store_elem(void *p, size_t i, float v) {
+    as_global_mut(static_cast<uint32_t *>(p))[i] = enc(v);
+  }
+  template <int W>
+  __device__ __forceinline__ static void unpack(const uint32_t (&w)[W], float (&v)[W]) {
+#pragma unroll
+    for (int k = 0; k < W; k++) v[k] = dec(w[k]);
+  }
+  template <int W>
+  __device__ __forceinline__ static void pack(const float (&v)[W], uint32_t (&w)[W]) {
+#pragma unroll
+    for (int k = 0; k < W; k++) w[k] = enc(v[k]);
+  }
+};
+
+// A value in turns (any sign) as a 32-bit fixed-point angle mod 1 turn; exact
+// for multiples of 2^-32 turn whose fraction FP32 holds.
+__device__ __forceinline__ uint32_t turns_fix32(float v) {
+  return (uint32_t)(fract1(v) * 4294967296.0f);
+}
 
 // LDS row access with the widest ds_read / ds_write for W words.
 template <int W>
@@ -373,18 +423,30 @@ __device__ __forceinline__ void lds_store_at(uint32_t *base, uint32_t byte, cons
   }
 }
 
-// Eq. (6) on the W words of an edge's two rows (every replica they hold).
+// Eq. (6) on the W words of an edge's two rows (every replica they hold); aJ
+// is alpha_t J in turns times Fmt<ST>::kStepScale.
 // FIX16: two replicas per word in 16-bit lanes, packed integer arithmetic; the
 // lane difference u - v wraps to the signed difference in [-1/2, 1/2) turn,
 // whose sign bit selects -step or +step, and the updates wrap by overflow.
+// FIX32: the same on one 32-bit integer per replica.
 // Other formats: unpack, the FP32 update, pack.
 template <int ST, int W>
 __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
-  if constexpr (ST == COSM_STORE_FIX16) {
+  if constexpr (ST == COSM_STORE_FIX32) {
+    // aJ is an integer of magnitude below 2^31 (|alpha J| < 1/2 turn on the
+    // grid): the conversion is exact
+    const uint32_t st = (uint32_t)(int32_t)aJ, nst = 0u - st;
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      const uint32_t dl = (int32_t)(wu[k] - wv[k]) >= 0 ? st : nst;
+      wu[k] -= dl;
+      wv[k] += dl;
+    }
+  } else if constexpr (ST == COSM_STORE_FIX16) {
     typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
     typedef short s16x2 __attribute__((ext_vector_type(2)));
-    // aJ is a multiple of 2^-16 turn below one turn: the conversion is exact
-    const uint32_t st = (uint32_t)(int32_t)(aJ * 65536.0f) & 0xffffu;
+    // aJ is an integer (2^-16 turn units) below one turn: the conversion is exact
+    const uint32_t st = (uint32_t)(int32_t)aJ & 0xffffu;
     const u16x2 step = __builtin_bit_cast(u16x2, st | (st << 16));
 #pragma unroll
     for (int k = 0; k < W; k++) {
@@ -404,6 +466,61 @@ __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W
     for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
     F::template pack<W>(xu, wu);
     F::template pack<W>(xv, wv);
+  }
+}
+
+// Eq. (6) between a row held in registers (r) and one in LDS (w), for every
+// replica they hold; flip says that the register vertex is the edge's v (the
+// sign of Eq. (4) is taken on x_u - x_v, so the roles matter on ties).  With
+// the change written r <- r - D, w <- w + D, the result is the pair update's
+// bit for bit: D = delta when r is u, -delta when r is v.
+// FIX32 / FIX16: d = r - w - flip (integer units) is >= 0 exactly when D is
+// +step: for r = u that is the sign of u - v; for r = v, u - v = -(r - w) has
+// the sign bit clear exactly when r - w is not in [1, 1/2 turn].
+// FP32 arithmetic: the pair update on (w, r) when flipped, with -(r - w)
+// standing for w - r (IEEE subtraction is antisymmetric).
+template <int ST, int W>
+__device__ __forceinline__ void update_reg_words(uint32_t (&r)[W], uint32_t (&w)[W], float aJ,
+                                                 uint32_t flip) {
+  if constexpr (ST == COSM_STORE_FIX32) {
+    const uint32_t st = (uint32_t)(int32_t)aJ, nst = 0u - st;
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      const uint32_t D = (int32_t)(r[k] - w[k] - flip) >= 0 ? st : nst;
+      r[k] -= D;
+      w[k] += D;
+    }
+  } else if constexpr (ST == COSM_STORE_FIX16) {
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    const uint32_t st = (uint32_t)(int32_t)aJ & 0xffffu;
+    const u16x2 step = __builtin_bit_cast(u16x2, st | (st << 16));
+    const u16x2 f2 = __builtin_bit_cast(u16x2, flip * 0x00010001u);
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      const u16x2 a = __builtin_bit_cast(u16x2, r[k]), b = __builtin_bit_cast(u16x2, w[k]);
+      const u16x2 m = (u16x2)((s16x2)(a - b - f2) >> (short)15);  // 0xffff where negative
+      const u16x2 D = (step ^ m) - m;
+      r[k] = __builtin_bit_cast(uint32_t, (u16x2)(a - D));
+      w[k] = __builtin_bit_cast(uint32_t, (u16x2)(b + D));
+    }
+  } else {
+    using F = Fmt<ST>;
+    constexpr int RW = W * F::kPerWord;
+    float xr[RW], xw[RW];
+    F::template unpack<W>(r, xr);
+    F::template unpack<W>(w, xw);
+#pragma unroll
+    for (int k = 0; k < RW; k++) {
+      const float e = xr[k] - xw[k];
+      const float f = fract1(flip ? -e : e);
+      const float dl = (f < 0.5f) ? aJ : -aJ;
+      const float D = flip ? -dl : dl;
+      xr[k] = F::wrap(xr[k] - D);
+      xw[k] = F::wrap(xw[k] + D);
+    }
+    F::template pack<W>(xr, r);
+    F::template pack<W>(xw, w);
   }
 }
 
@@ -438,7 +555,16 @@ __device__ __forceinline__ void twist_words(uint32_t (&w)[W],
                                             const float (&c)[W * Fmt<ST>::kPerWord],
                                             const float (&tws)[W * Fmt<ST>::kPerWord],
                                             float win2) {
-  if constexpr (ST == COSM_STORE_FIX16) {
+  if constexpr (ST == COSM_STORE_FIX32) {
+    // t = (2x - c) mod 1 turn in 2^-32 units; in the windows iff t < 2w
+    const bool all = win2 >= 1.0f;
+    const uint32_t W2 = all ? 0u : (uint32_t)(win2 * 4294967296.0f);
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+      const uint32_t t = (w[q] << 1) - turns_fix32(c[q]);
+      if (all || t < W2) w[q] += turns_fix32(tws[q]);
+    }
+  } else if constexpr (ST == COSM_STORE_FIX16) {
     typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
     typedef short s16x2 __attribute__((ext_vector_type(2)));
     const uint32_t W2 = (uint32_t)(win2 * 65536.0f);  // 2w in 2^-16 turn, <= 2^16

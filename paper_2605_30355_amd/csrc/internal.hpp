@@ -108,7 +108,24 @@ struct LdsSchedule {
   bool fuse = false;
   int32_t fuse_k = 0;
   bool dummy_pairs = false;  // masked lanes carry dummy-row no-op edges
+  // Register-owner form (reg_k > 0): an independent set of vertices lives in
+  // registers, reg_k per thread (reg_vertex [reg_k][nth], -1 for none); every
+  // edge with an endpoint there is updated by that endpoint's thread, touching
+  // LDS for the other endpoint only.  desc is [C][reg_k + 1][nth]: per class
+  // the reg_k register slots (row of the LDS endpoint | flip << 16, where flip
+  // = the register vertex is the edge's v), then one slot of an edge between
+  // two LDS rows (the pair form's encoding), used when reg_free is 1.  Lanes
+  // without an edge carry a dummy row with J = 0.  Rows: slot_vertex, -1 for
+  // padding; n_rows is a multiple of 64 and the dummy rows follow it.
+  int32_t reg_k = 0;
+  int32_t reg_free = 0;
+  std::vector<int32_t> reg_vertex;
+  int64_t reg_edges = 0;        // edges with an endpoint in registers
+  int64_t reg_conflicts = 0;    // lane groups whose rows share a bank (extra LDS cycles)
 };
+constexpr int32_t kRegKMax = 4;
+constexpr int32_t kRegClassesMax = 8;
+constexpr int32_t kRegRowsSlack = 4096;  // slot_vertex capacity beyond n
 constexpr int32_t kRegisterSlotsMax = 16;  // schedules this short stay in registers
 constexpr int32_t kFuseRowsMax = 4;
 constexpr int32_t kStreamRepeat = 3;
@@ -118,6 +135,7 @@ struct DeviceBuffers {
   EdgeDesc *desc = nullptr;     // LDS-form descriptors, grouped by class
   int32_t *class_off = nullptr; // [C+1] offsets into desc
   int32_t *slot_vertex = nullptr; // [n_slots] vertex held by each LDS slot
+  int32_t *reg_vertex = nullptr;  // [kRegKMax * 1024] register-owner form
   int32_t *h_slot = nullptr;    // [n_slots] bias field of the vertex in each slot (with h)
   int32_t *eu = nullptr;        // [m] (original ids)
   int32_t *ev = nullptr;
@@ -205,6 +223,19 @@ int lds_capacity_bytes();
 // whose LDS holds the dummy rows).
 int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out,
                        bool dummy_pairs = false);
+// Register-owner schedule (see LdsSchedule) for rows of W words, K register
+// vertices per thread and nth_request threads (0: as many as the register
+// vertices need).  COSM_ERANGE when the form does not apply (more than
+// kRegClassesMax classes, bias fields, more edges outside the register set
+// than one slot per class holds, too many rows).
+int build_reg_schedule(const cosm_state &s, int32_t W, int32_t K, int32_t nth_request,
+                       LdsSchedule *out);
+// Whether the register form applies (storage, classes, fields, update), a
+// register schedule checked against the LDS capacity, and the fewest register
+// rows per thread that give one for row width W.
+bool reg_form_supported(const cosm_state &s);
+int reg_schedule_for(const cosm_state &s, int32_t W, int32_t K, int32_t nth, LdsSchedule *out);
+int pick_reg_schedule(cosm_state *s, int32_t W, int32_t nth);
 // Measure candidate LDS shapes (row widths in words) and keep the fastest.
 int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths);
 // Uploads the bias field in LDS-slot order (no-op without bias fields).

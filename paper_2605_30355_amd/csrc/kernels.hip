@@ -36,6 +36,10 @@ struct LdsArgs {
   // rows per thread (after the repeated slots in desc) that no edge of that
   // class touches
   int32_t fuse_k;
+  // register-owner form: [K][nth] register vertices, and whether the slot of
+  // edges between two LDS rows is in use
+  const int32_t *reg_vertex;
+  int32_t reg_free;
 };
 
 // ---------------------------------------------------------------------------
@@ -151,6 +155,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     if ((it & 63u) == 0u) chunk.fill(sc, t);
     float alpha, twist;
     chunk.get(it & 63u, alpha, twist);
+    const float alpha_s = alpha * F::kStepScale;  // the step in storage units
     // Sequential conflict-free search: classes in order, a barrier after each.
     if constexpr (FUSE && EXACT) {
       // EMAX slots, one class each.  On a twist sweep the last class twists
@@ -173,37 +178,37 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       }
 #pragma unroll
       for (int j = 0; j < EMAX - 1; j++) {
-        edge_rows<ST, W>(lds, ua[j], va[j], alpha * jr[j]);
+        edge_rows<ST, W>(lds, ua[j], va[j], alpha_s * jr[j]);
         __syncthreads();
       }
       if (fuse_now) {
-        edge_rows_twist<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha * jr[EMAX - 1], cth, tws,
+        edge_rows_twist<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1], cth, tws,
                                sc.win2);
 #pragma unroll
         for (int q = 0; q < kFuseRowsMax; q++)
           if (q < a.fuse_k && fr[q] != kEmptySlot) row_twist<ST, W>(lds, fr[q], cth, tws, sc.win2);
       } else {
-        edge_rows<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha * jr[EMAX - 1]);
+        edge_rows<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1]);
       }
       __syncthreads();
     } else if constexpr (EXACT) {
       // EMAX slots, one class each
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
-        edge_rows<ST, W>(lds, ua[j], va[j], alpha * jr[j]);
+        edge_rows<ST, W>(lds, ua[j], va[j], alpha_s * jr[j]);
         __syncthreads();
       }
     } else if constexpr (EMAX > 0) {
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
         if (j < a.total_slots) {
-          edge_rows<ST, W>(lds, ua[j], va[j], alpha * jr[j]);
+          edge_rows<ST, W>(lds, ua[j], va[j], alpha_s * jr[j]);
           if ((a.bar_mask >> j) & 1u) __syncthreads();
         }
       }
     } else if (a.total_slots > 0) {
       auto edge = [&](const EdgeDesc &d) {
-        edge_rows<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha * d.J);
+        edge_rows<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha_s * d.J);
       };
       if constexpr (FUSE) {
         // streamed form: on a twist sweep the last class twists the rows it
@@ -230,7 +235,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
             a.desc, Ks, a.C, a.total_slots, dA, dB, jslot, edge,
             [&](const EdgeDesc &d) {
               edge_rows_twist<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
-                                     alpha * d.J, cth, tws, sc.win2);
+                                     alpha_s * d.J, cth, tws, sc.win2);
             },
             [&] {
               for (int q = 0; q < a.fuse_k; q++) {
@@ -321,11 +326,173 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// The register-owner form of the LDS sweep: thread t keeps K vertices of an
+// independent set in registers (RW replicas each, as W words) and applies
+// every edge incident to them, reading and writing only the other endpoint's
+// LDS row; edges between two LDS rows take one pair-form slot per class.  The
+// classes (at most CM) run in order with a barrier after each, as in
+// k_sweep_lds (CLASSES > 0: exactly that many, else a.C); the schedule is held
+// in registers; lanes without an edge use dummy rows with J = 0.  The twist visits the LDS rows (all threads) and the
+// register rows (their owner), after the last class.
+// ---------------------------------------------------------------------------
+template <int ST, int W, int K, int CM, int CLASSES>
+__global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
+  extern __shared__ uint32_t lds[];
+  using F = Fmt<ST>;
+  constexpr int RW = W * F::kPerWord;
+  constexpr uint32_t ROWB = 4 * W;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int32_t r0 = xcd_block(blockIdx.x, gridDim.x) * RW;
+  const int32_t nvalid = min(RW, a.R - r0);
+
+  // HBM [n][R] -> LDS rows (padding rows and dummy rows zero)
+  for (int s = tid; s < a.n_rows + kDummyRows; s += nth) {
+    const int32_t v = s < a.n_rows ? a.slot_vertex[s] : -1;
+    float x[RW];
+#pragma unroll
+    for (int k = 0; k < RW; k++)
+      x[k] = (v >= 0 && k < nvalid) ? F::load_elem(a.phases, (size_t)v * a.R + r0 + k) : 0.0f;
+    uint32_t w[W];
+    F::template pack<W>(x, w);
+    lds_store<W>(lds, s, w);
+  }
+  float *theta_buf = reinterpret_cast<float *>(lds + (size_t)(a.n_rows + kDummyRows) * W);
+  // HBM -> register rows
+  uint32_t reg[K][W];
+  int32_t rv[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    rv[k] = a.reg_vertex[k * nth + tid];
+    float x[RW];
+#pragma unroll
+    for (int q = 0; q < RW; q++)
+      x[q] = (rv[k] >= 0 && q < nvalid) ? F::load_elem(a.phases, (size_t)rv[k] * a.R + r0 + q) : 0.0f;
+    F::template pack<W>(x, reg[k]);
+  }
+  // the schedule: [C][K + 1][nth]
+  uint32_t row[CM][K], flip[CM][K], fu[CM], fv[CM];
+  float jr[CM][K], jf[CM];
+#pragma unroll
+  for (int c = 0; c < CM; c++) {
+    const bool on = c < a.C;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const EdgeDesc d = on ? a.desc[(size_t)(c * (K + 1) + k) * nth + tid] : EdgeDesc{0u, 0.0f};
+      row[c][k] = (d.slots & 0xffffu) * ROWB;
+      flip[c][k] = (d.slots >> 16) & 1u;
+      jr[c][k] = d.J;
+    }
+    const EdgeDesc d = on ? a.desc[(size_t)(c * (K + 1) + K) * nth + tid] : EdgeDesc{0u, 0.0f};
+    fu[c] = (d.slots & 0xffffu) * ROWB;
+    fv[c] = (d.slots >> 16) * ROWB;
+    jf[c] = d.J;
+  }
+  // the pair slot's edges sit in the first lanes: a wave with none of them in
+  // a class skips that slot (its other lanes hold no-op dummy edges)
+  uint32_t wave_free = 0;
+#pragma unroll
+  for (int c = 0; c < CM; c++)
+    if (__ballot(a.reg_free && jf[c] != 0.0f) != 0ull) wave_free |= 1u << c;
+  __syncthreads();
+
+  SweepSchedule sc = a.sch;
+  const uint32_t nsw = (uint32_t)a.nsw;
+  uint32_t t = (uint32_t)a.t0;
+  uint32_t tw = 0;
+  ScheduleChunk chunk;
+  for (uint32_t it = 0; it < nsw; it++) {
+    t++;
+    if ((it & 63u) == 0u) chunk.fill(sc, t);
+    float alpha, twist;
+    chunk.get(it & 63u, alpha, twist);
+    const float alpha_s = alpha * F::kStepScale;
+#pragma unroll
+    for (int c = 0; c < CM; c++) {
+      if (c < CLASSES || (CLASSES == 0 && c < a.C)) {
+        const bool fon = (wave_free >> c) & 1u;  // uniform over the wave
+        uint32_t w[K][W], pu[W], pv[W];
+#pragma unroll
+        for (int k = 0; k < K; k++) lds_load_at<W>(lds, row[c][k], w[k]);
+        if (fon) {
+          lds_load_at<W>(lds, fu[c], pu);
+          lds_load_at<W>(lds, fv[c], pv);
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+          update_reg_words<ST, W>(reg[k], w[k], alpha_s * jr[c][k], flip[c][k]);
+          lds_store_at<W>(lds, row[c][k], w[k]);
+        }
+        if (fon) {
+          update_words<ST, W>(pu, pv, alpha_s * jf[c]);
+          lds_store_at<W>(lds, fu[c], pu);
+          lds_store_at<W>(lds, fv[c], pv);
+        }
+        __syncthreads();
+      }
+    }
+    if (chunk.twist_at(it & 63u)) {
+      const int slot = (int)(tw % (uint32_t)kThetaChunk);
+      if (slot == 0) {
+        theta_fill(theta_buf, nullptr, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0,
+                   a.k0, a.k1, sc.win, sc.tshift, sc.tscale);
+        __syncthreads();
+      }
+      tw++;
+      float cth[RW], tws[RW];
+#pragma unroll
+      for (int k = 0; k < RW; k++) {
+        cth[k] = theta_buf[slot * RW + k];
+        tws[k] = twist;
+      }
+#pragma unroll
+      for (int k = 0; k < K; k++) twist_words<ST, W>(reg[k], cth, tws, sc.win2);
+      for (int s0 = tid; s0 < a.n_rows; s0 += 4 * nth) {
+        uint32_t w[4][W];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          if (s0 + q * nth < a.n_rows) lds_load<W>(lds, s0 + q * nth, w[q]);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          if (s0 + q * nth < a.n_rows) {
+            twist_words<ST, W>(w[q], cth, tws, sc.win2);
+            lds_store<W>(lds, s0 + q * nth, w[q]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // register rows and LDS rows -> HBM
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    if (rv[k] < 0) continue;
+    float x[RW];
+    F::template unpack<W>(reg[k], x);
+#pragma unroll
+    for (int q = 0; q < RW; q++)
+      if (q < nvalid) F::store_elem(a.phases, (size_t)rv[k] * a.R + r0 + q, x[q]);
+  }
+  for (int s = tid; s < a.n_rows; s += nth) {
+    const int32_t v = a.slot_vertex[s];
+    if (v < 0) continue;
+    uint32_t w[W];
+    lds_load<W>(lds, s, w);
+    float x[RW];
+    F::template unpack<W>(w, x);
+#pragma unroll
+    for (int k = 0; k < RW; k++)
+      if (k < nvalid) F::store_elem(a.phases, (size_t)v * a.R + r0 + k, x[k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // VEC consecutive replicas of one vertex row in one access (8 or 16 bytes for
-// FP32, 4 or 8 for the 16-bit formats); idx is a multiple of VEC.
+// FP32 and FIX32, 4 or 8 for the 16-bit formats); idx is a multiple of VEC.
 typedef float hbm_f32x2 __attribute__((ext_vector_type(2)));
 typedef float hbm_f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t hbm_u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t hbm_u32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 using gvec = T __attribute__((address_space(1))) *;
 
@@ -342,6 +509,15 @@ __device__ __forceinline__ void load_vec(const void *p, size_t idx, float (&x)[V
     } else {
       const hbm_f32x2 v = *(gvec<const hbm_f32x2>)(q);
       x[0] = v.x; x[1] = v.y;
+    }
+  } else if constexpr (ST == COSM_STORE_FIX32) {
+    const uint32_t *q = static_cast<const uint32_t *>(p) + idx;
+    if constexpr (VEC == 4) {
+      const hbm_u32x4 v = *(gvec<const hbm_u32x4>)(q);
+      x[0] = F::dec(v.x); x[1] = F::dec(v.y); x[2] = F::dec(v.z); x[3] = F::dec(v.w);
+    } else {
+      const hbm_u32x2 v = *(gvec<const hbm_u32x2>)(q);
+      x[0] = F::dec(v.x); x[1] = F::dec(v.y);
     }
   } else {
     const uint16_t *q = static_cast<const uint16_t *>(p) + idx;
@@ -366,6 +542,13 @@ __device__ __forceinline__ void store_vec(void *p, size_t idx, const float (&x)[
       *(gvec<hbm_f32x4>)(q) = hbm_f32x4{x[0], x[1], x[2], x[3]};
     } else {
       *(gvec<hbm_f32x2>)(q) = hbm_f32x2{x[0], x[1]};
+    }
+  } else if constexpr (ST == COSM_STORE_FIX32) {
+    uint32_t *q = static_cast<uint32_t *>(p) + idx;
+    if constexpr (VEC == 4) {
+      *(gvec<hbm_u32x4>)(q) = hbm_u32x4{F::enc(x[0]), F::enc(x[1]), F::enc(x[2]), F::enc(x[3])};
+    } else {
+      *(gvec<hbm_u32x2>)(q) = hbm_u32x2{F::enc(x[0]), F::enc(x[1])};
     }
   } else {
     uint16_t *q = static_cast<uint16_t *>(p) + idx;
@@ -593,8 +776,46 @@ int launch_lds(cosm_state *s, const LdsArgs &a) {
   return launch_check("k_sweep_lds");
 }
 
+template <int ST, int W, int K, int CM, int CLASSES = 0>
+int launch_reg(cosm_state *s, const LdsArgs &a) {
+  const size_t lds = s->shape.lds_bytes;
+  (void)hipFuncSetAttribute((const void *)k_sweep_reg<ST, W, K, CM, CLASSES>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_sweep_reg<ST, W, K, CM, CLASSES>), dim3(s->shape.blocks),
+                     dim3(s->shape.threads), lds, s->stream, a);
+  return launch_check("k_sweep_reg");
+}
+
+// The register-owner form exists for the formats whose update is exact for
+// any input (FP32, and the fixed-point formats), with up to 8 classes (4 and
+// 2 register rows per thread) or 4 classes (4 rows).
+template <int ST, int W>
+int launch_reg_w(cosm_state *s, const LdsArgs &a) {
+  if constexpr (ST == COSM_STORE_FP32 || ST == COSM_STORE_FIX32 || ST == COSM_STORE_FIX16) {
+    const int K = s->lds.reg_k;
+    if (a.C == 4) {
+      if (K == 1) return launch_reg<ST, W, 1, 4, 4>(s, a);
+      if (K == 2) return launch_reg<ST, W, 2, 4, 4>(s, a);
+      if (K == 4) return launch_reg<ST, W, 4, 4, 4>(s, a);
+    } else if (a.C < 4) {
+      if (K == 1) return launch_reg<ST, W, 1, 4>(s, a);
+      if (K == 2) return launch_reg<ST, W, 2, 4>(s, a);
+      if (K == 4) return launch_reg<ST, W, 4, 4>(s, a);
+    } else if (a.C <= 8) {
+      if (K == 1) return launch_reg<ST, W, 1, 8>(s, a);
+      if (K == 2) return launch_reg<ST, W, 2, 8>(s, a);
+    }
+    return set_error(COSM_EINVAL, "register form: unsupported register count or classes");
+  } else {
+    (void)s;
+    (void)a;
+    return set_error(COSM_EINVAL, "register form: unsupported storage");
+  }
+}
+
 template <int ST, int W>
 int launch_lds_w(cosm_state *s, const LdsArgs &a) {
+  if (s->lds.reg_k > 0) return launch_reg_w<ST, W>(s, a);
   const int slots = a.total_slots;
   // one slot per class and exactly 4 / 8 slots: the unconditional form
   const bool one_each = slots == a.C && slots <= 32 && a.bar_mask == (uint32_t)((1ull << slots) - 1);
@@ -636,6 +857,8 @@ int sweeps_lds_st(cosm_state *s, int64_t n_sweeps) {
   }
   a.bar_mask = mask;
   a.fuse_k = s->lds.fuse_k;
+  a.reg_vertex = s->d.reg_vertex;
+  a.reg_free = s->lds.reg_free;
   a.sch = make_sweep_schedule(s->sched, s->t);
   a.k0 = (uint32_t)(s->seed & 0xffffffffu);
   a.k1 = (uint32_t)(s->seed >> 32);
@@ -793,6 +1016,7 @@ int dispatch_storage(int storage, A &&...args) {
     case COSM_STORE_FP16: return Fn<COSM_STORE_FP16>::run(args...);
     case COSM_STORE_BF16: return Fn<COSM_STORE_BF16>::run(args...);
     case COSM_STORE_FIX16: return Fn<COSM_STORE_FIX16>::run(args...);
+    case COSM_STORE_FIX32: return Fn<COSM_STORE_FIX32>::run(args...);
   }
   return set_error(COSM_EINVAL, "unknown storage format");
 }

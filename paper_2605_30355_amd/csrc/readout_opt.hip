@@ -207,8 +207,12 @@ int launch_readout_optimal(cosm_state *s) {
       hipLaunchKernelGGL((k_opt_keys<COSM_STORE_BF16>), dim3((unsigned)((nr + 255) / 256)), blk, 0,
                          s->stream, d.phases, n, R, d.opt_keys, d.opt_vals);
       break;
-    default:
+    case COSM_STORE_FIX16:
       hipLaunchKernelGGL((k_opt_keys<COSM_STORE_FIX16>), dim3((unsigned)((nr + 255) / 256)), blk, 0,
+                         s->stream, d.phases, n, R, d.opt_keys, d.opt_vals);
+      break;
+    default:
+      hipLaunchKernelGGL((k_opt_keys<COSM_STORE_FIX32>), dim3((unsigned)((nr + 255) / 256)), blk, 0,
                          s->stream, d.phases, n, R, d.opt_keys, d.opt_vals);
   }
   COSM_HIP_CHECK(hipGetLastError());

@@ -1,0 +1,453 @@
+// reg_schedule.cpp -- the register-owner form of the LDS-resident sweep.
+//
+// In the pair form every edge update reads and writes both endpoint rows in
+// LDS.  Here an independent set I of vertices is held in registers: thread t
+// owns up to K of them, and every edge with an endpoint in I is updated by
+// that endpoint's owner, which reads and writes only the other endpoint's row
+// (no two vertices of I are adjacent, so each edge has at most one register
+// endpoint).  Edges with no endpoint in I keep the pair form, one slot per
+// class.  On a bipartite graph (the even tori) one side is I and every update
+// touches LDS once instead of twice; on a random 3-regular graph about 0.43 n
+// vertices cover about 86 % of the edges.
+//
+// Bank layout (the gfx950 LDS model of schedule.cpp): in each aligned group of
+// G lanes (G = 64 / W, 32 for W = 1) the rows of one access must be distinct
+// mod G, and in each aligned half of H = 32 / W lanes distinct mod H.  Rows
+// are numbered residue-major (row = rho + G i), and the residue rho of each
+// LDS vertex is chosen while the register vertices are packed into groups:
+// a vertex joins a group only if, class by class, its neighbours' residues are
+// still free there (unassigned neighbours take a free residue).  Lanes without
+// an edge get dummy rows n_rows + rho with residues free in their group, so
+// every access is conflict-free and needs no branch.
+//
+// The class order and the edge set per class are unchanged: only which thread
+// applies an update, and in which register or LDS row the phases sit, differ.
+#include <algorithm>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace cosm {
+
+namespace {
+
+struct Adj {
+  int32_t other;
+  int32_t edge;
+  int32_t cls;
+};
+
+// Vertices of one side of a 2-colouring per connected component (the side
+// with fewer vertices), or an empty result when the graph has an odd cycle.
+bool bipartite_side(int32_t n, const std::vector<std::vector<Adj>> &adj,
+                    std::vector<uint8_t> *in_set) {
+  std::vector<int8_t> side((size_t)n, -1);
+  std::vector<int32_t> queue, comp;
+  in_set->assign((size_t)n, 0);
+  for (int32_t s0 = 0; s0 < n; s0++) {
+    if (side[(size_t)s0] >= 0 || adj[(size_t)s0].empty()) continue;
+    side[(size_t)s0] = 0;
+    queue.assign(1, s0);
+    comp.clear();
+    int32_t count[2] = {0, 0};
+    for (size_t h = 0; h < queue.size(); h++) {
+      const int32_t v = queue[h];
+      comp.push_back(v);
+      count[side[(size_t)v]]++;
+      for (const Adj &a : adj[(size_t)v]) {
+        if (side[(size_t)a.other] < 0) {
+          side[(size_t)a.other] = (int8_t)(1 - side[(size_t)v]);
+          queue.push_back(a.other);
+        } else if (side[(size_t)a.other] == side[(size_t)v]) {
+          return false;
+        }
+      }
+    }
+    const int8_t pick = count[1] < count[0] ? 1 : 0;
+    for (int32_t v : comp)
+      if (side[(size_t)v] == pick) (*in_set)[(size_t)v] = 1;
+  }
+  return true;
+}
+
+// Greedy independent set: repeatedly take a vertex of minimum remaining
+// degree (isolated vertices excluded: they have nothing to cover).
+void greedy_independent(int32_t n, const std::vector<std::vector<Adj>> &adj,
+                        std::vector<uint8_t> *in_set) {
+  in_set->assign((size_t)n, 0);
+  std::vector<int32_t> deg((size_t)n);
+  int32_t dmax = 0;
+  for (int32_t v = 0; v < n; v++) {
+    deg[(size_t)v] = (int32_t)adj[(size_t)v].size();
+    dmax = std::max(dmax, deg[(size_t)v]);
+  }
+  std::vector<std::vector<int32_t>> bucket((size_t)dmax + 1);
+  for (int32_t v = n - 1; v >= 0; v--)
+    if (deg[(size_t)v] > 0) bucket[(size_t)deg[(size_t)v]].push_back(v);
+  std::vector<uint8_t> gone((size_t)n, 0);
+  for (int32_t v = 0; v < n; v++)
+    if (deg[(size_t)v] == 0) gone[(size_t)v] = 1;
+  int32_t d = 0;
+  while (true) {
+    while (d <= dmax && bucket[(size_t)d].empty()) d++;
+    if (d > dmax) break;
+    const int32_t v = bucket[(size_t)d].back();
+    bucket[(size_t)d].pop_back();
+    if (gone[(size_t)v] || deg[(size_t)v] != d) continue;  // stale entry
+    (*in_set)[(size_t)v] = 1;
+    gone[(size_t)v] = 1;
+    for (const Adj &a : adj[(size_t)v]) {
+      const int32_t w = a.other;
+      if (gone[(size_t)w]) continue;
+      gone[(size_t)w] = 1;
+      for (const Adj &b : adj[(size_t)w]) {
+        const int32_t x = b.other;
+        if (gone[(size_t)x]) continue;
+        deg[(size_t)x]--;
+        bucket[(size_t)deg[(size_t)x]].push_back(x);
+        d = std::min(d, deg[(size_t)x]);
+      }
+    }
+  }
+}
+
+inline uint64_t bit(int32_t r) { return 1ull << r; }
+
+// One attempt.  pre: every LDS vertex takes residue (its rank among the LDS
+// vertices, in vertex order) mod G before the packing, which keeps lattice
+// neighbourhoods aligned; otherwise residues are chosen during the packing.
+int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_request, bool pre,
+                   LdsSchedule *out) {
+  const int32_t n = s.n, C = s.C;
+  const int64_t m = s.m;
+  if (W != 1 && W != 2 && W != 4) return set_error(COSM_EINVAL, "bad row width");
+  if (K < 1 || K > kRegKMax) return set_error(COSM_EINVAL, "bad register count");
+  if (C > kRegClassesMax) return set_error(COSM_ERANGE, "too many classes for the register form");
+  if (s.has_h) return set_error(COSM_ERANGE, "the register form runs without bias fields");
+  if (m == 0) return set_error(COSM_ERANGE, "no edges");
+  const int32_t G = W == 1 ? 32 : 64 / W;  // lanes and residues of a read group
+  const int32_t H = 32 / W;                // lanes and residues of a write half
+
+  std::vector<std::vector<Adj>> adj((size_t)n);
+  for (int64_t k = 0; k < m; k++) {
+    const int32_t u = s.h_eu[(size_t)k], v = s.h_ev[(size_t)k], c = s.h_colour[(size_t)k];
+    adj[(size_t)u].push_back({v, (int32_t)k, c});
+    adj[(size_t)v].push_back({u, (int32_t)k, c});
+  }
+
+  // 1. the register set
+  std::vector<uint8_t> inI;
+  if (!bipartite_side(n, adj, &inI)) greedy_independent(n, adj, &inI);
+  std::vector<int32_t> cand;
+  for (int32_t v = 0; v < n; v++)
+    if (inI[(size_t)v]) cand.push_back(v);
+  int32_t nth = nth_request;
+  if (nth <= 0) {
+    const int64_t need = ((int64_t)cand.size() + K - 1) / K;
+    nth = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(64, (need + 63) / 64 * 64));
+  }
+  if (nth % 64 != 0 || nth < 64 || nth > 1024) return set_error(COSM_EINVAL, "bad thread count");
+  const int64_t cap = (int64_t)K * nth;
+  if ((int64_t)cand.size() > cap) {
+    // keep the vertices that cover the most edges
+    std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+      return adj[(size_t)a].size() > adj[(size_t)b].size();
+    });
+    for (size_t i = (size_t)cap; i < cand.size(); i++) inI[(size_t)cand[i]] = 0;
+    cand.resize((size_t)cap);
+    std::sort(cand.begin(), cand.end());
+  }
+
+  // 2. pack the register vertices into lane groups, choosing residues
+  const int32_t groups_per_k = nth / G;
+  const int32_t ngroups = groups_per_k * K;
+  std::vector<int32_t> res((size_t)n, -1);
+  std::vector<int64_t> load((size_t)G, 0);
+  std::vector<uint64_t> usedG((size_t)ngroups * C, 0);
+  std::vector<uint64_t> usedH((size_t)ngroups * 2 * C, 0);
+  std::vector<int32_t> pos_vertex((size_t)K * nth, -1);  // [k][t]
+  auto pick_free = [&](uint64_t gmask, uint64_t hmask) {
+    int32_t best = -1;
+    for (int32_t r = 0; r < G; r++) {
+      if ((gmask >> r) & 1u) continue;
+      if ((hmask >> (r % H)) & 1u) continue;
+      if (best < 0 || load[(size_t)r] < load[(size_t)best]) best = r;
+    }
+    return best;
+  };
+  if (pre) {
+    int32_t rank = 0;
+    for (int32_t v = 0; v < n; v++) {
+      if (inI[(size_t)v]) continue;
+      res[(size_t)v] = rank++ % G;
+      load[(size_t)res[(size_t)v]]++;
+    }
+  }
+  std::vector<uint8_t> placed((size_t)n, 0);
+  size_t first_open = 0;  // cand[0 .. first_open) are all placed
+  for (int32_t gi = 0; gi < ngroups && first_open < cand.size(); gi++) {
+    const int32_t k = gi / groups_per_k, tg = gi % groups_per_k;
+    for (int32_t p = 0; p < G; p++) {
+      const int32_t half = p / H;
+      int32_t chosen = -1;
+      int32_t scanned = 0;
+      for (size_t i = first_open; i < cand.size() && scanned < 2048; i++) {
+        const int32_t v = cand[i];
+        if (placed[(size_t)v]) continue;
+        scanned++;
+        bool ok = true;
+        for (const Adj &a : adj[(size_t)v]) {
+          const uint64_t gm = usedG[(size_t)gi * C + a.cls];
+          const uint64_t hm = usedH[((size_t)gi * 2 + half) * C + a.cls];
+          const int32_t r = res[(size_t)a.other];
+          if (r >= 0 ? (((gm >> r) & 1u) || ((hm >> (r % H)) & 1u)) : pick_free(gm, hm) < 0) {
+            ok = false;
+            break;
+          }
+        }
+        if (ok) {
+          chosen = v;
+          break;
+        }
+      }
+      if (chosen < 0) break;  // nothing fits this group any more
+      placed[(size_t)chosen] = 1;
+      pos_vertex[(size_t)k * nth + tg * G + p] = chosen;
+      for (const Adj &a : adj[(size_t)chosen]) {
+        uint64_t &gm = usedG[(size_t)gi * C + a.cls];
+        uint64_t &hm = usedH[((size_t)gi * 2 + half) * C + a.cls];
+        int32_t &r = res[(size_t)a.other];
+        if (r < 0) {
+          r = pick_free(gm, hm);
+          load[(size_t)r]++;
+        }
+        gm |= bit(r);
+        hm |= bit(r % H);
+      }
+      while (first_open < cand.size() && placed[(size_t)cand[first_open]]) first_open++;
+    }
+  }
+  // register vertices that found no place go back to LDS
+  int64_t reg_edges = 0;
+  for (int32_t v : cand) {
+    if (!placed[(size_t)v]) inI[(size_t)v] = 0;
+    else reg_edges += (int64_t)adj[(size_t)v].size();
+  }
+
+  // 3. edges between two LDS rows: one slot per class
+  std::vector<std::vector<int32_t>> free_edges((size_t)C);
+  for (int64_t k = 0; k < m; k++) {
+    const int32_t u = s.h_eu[(size_t)k], v = s.h_ev[(size_t)k];
+    if (!inI[(size_t)u] && !inI[(size_t)v]) free_edges[(size_t)s.h_colour[(size_t)k]].push_back((int32_t)k);
+  }
+  int32_t reg_free = 0;
+  for (int32_t c = 0; c < C; c++) {
+    if ((int64_t)free_edges[(size_t)c].size() > nth)
+      return set_error(COSM_ERANGE, "too many edges outside the register set");
+    if (!free_edges[(size_t)c].empty()) reg_free = 1;
+  }
+  // per class: lane of each free edge; u-rows and v-rows conflict-free per group
+  std::vector<int32_t> free_at((size_t)C * nth, -1);
+  std::vector<uint64_t> fG((size_t)C * groups_per_k * 2, 0), fH((size_t)C * groups_per_k * 4, 0);
+  int64_t conflicts = 0;
+  for (int32_t c = 0; c < C; c++) {
+    std::vector<int32_t> &list = free_edges[(size_t)c];
+    std::vector<uint8_t> done(list.size(), 0);
+    size_t left = list.size();
+    for (int32_t tg = 0; tg < groups_per_k && left > 0; tg++) {
+      for (int32_t p = 0; p < G && left > 0; p++) {
+        const int32_t half = p / H;
+        uint64_t *gU = &fG[((size_t)c * groups_per_k + tg) * 2], *gV = gU + 1;
+        uint64_t *hU = &fH[(((size_t)c * groups_per_k + tg) * 2 + half) * 2], *hV = hU + 1;
+        int32_t chosen = -1;
+        for (size_t i = 0; i < list.size(); i++) {
+          if (done[i]) continue;
+          const int32_t e = list[i];
+          const int32_t u = s.h_eu[(size_t)e], v = s.h_ev[(size_t)e];
+          const int32_t ru = res[(size_t)u], rv = res[(size_t)v];
+          const bool uok = ru >= 0 ? !(((*gU >> ru) & 1u) || ((*hU >> (ru % H)) & 1u))
+                                   : pick_free(*gU, *hU) >= 0;
+          const bool vok = rv >= 0 ? !(((*gV >> rv) & 1u) || ((*hV >> (rv % H)) & 1u))
+                                   : pick_free(*gV, *hV) >= 0;
+          if (uok && vok) {
+            chosen = (int32_t)i;
+            break;
+          }
+        }
+        if (chosen < 0) continue;  // leave this lane for a dummy
+        done[(size_t)chosen] = 1;
+        left--;
+        const int32_t e = list[(size_t)chosen];
+        free_at[(size_t)c * nth + tg * G + p] = e;
+        int32_t &ru = res[(size_t)s.h_eu[(size_t)e]];
+        if (ru < 0) { ru = pick_free(*gU, *hU); load[(size_t)ru]++; }
+        *gU |= bit(ru); *hU |= bit(ru % H);
+        int32_t &rv = res[(size_t)s.h_ev[(size_t)e]];
+        if (rv < 0) { rv = pick_free(*gV, *hV); load[(size_t)rv]++; }
+        *gV |= bit(rv); *hV |= bit(rv % H);
+      }
+    }
+    // edges no conflict-free lane took: any empty lane, counted as conflicts
+    for (size_t i = 0; i < list.size(); i++) {
+      if (done[i]) continue;
+      int32_t t = 0;
+      while (free_at[(size_t)c * nth + t] >= 0) t++;  // fits: at most nth edges
+      const int32_t e = list[i];
+      free_at[(size_t)c * nth + t] = e;
+      const int32_t tg = t / G, half = (t % G) / H;
+      uint64_t *gU = &fG[((size_t)c * groups_per_k + tg) * 2], *gV = gU + 1;
+      uint64_t *hU = &fH[(((size_t)c * groups_per_k + tg) * 2 + half) * 2], *hV = hU + 1;
+      for (int q = 0; q < 2; q++) {
+        int32_t &r = res[(size_t)(q == 0 ? s.h_eu[(size_t)e] : s.h_ev[(size_t)e])];
+        uint64_t *gm = q == 0 ? gU : gV, *hm = q == 0 ? hU : hV;
+        if (r < 0) {
+          r = pick_free(*gm, *hm);
+          if (r < 0) r = 0;
+          load[(size_t)r]++;
+        }
+        if (((*gm >> r) & 1u) || ((*hm >> (r % H)) & 1u)) conflicts++;
+        *gm |= bit(r);
+        *hm |= bit(r % H);
+      }
+    }
+  }
+
+  // 4. residues of the remaining LDS vertices, then rows residue-major
+  for (int32_t v = 0; v < n; v++) {
+    if (inI[(size_t)v] || res[(size_t)v] >= 0) continue;
+    int32_t r = 0;
+    for (int32_t q = 1; q < G; q++)
+      if (load[(size_t)q] < load[(size_t)r]) r = q;
+    res[(size_t)v] = r;
+    load[(size_t)r]++;
+  }
+  int64_t per = 0;
+  for (int32_t r = 0; r < G; r++) per = std::max(per, load[(size_t)r]);
+  const int64_t n_rows = ((int64_t)G * per + 63) / 64 * 64;
+  if (n_rows + kDummyRows > 65535 || n_rows > (int64_t)n + kRegRowsSlack - kDummyRows)
+    return set_error(COSM_ERANGE, "too many rows for the register form");
+  std::vector<int32_t> row((size_t)n, -1), fill((size_t)G, 0);
+  LdsSchedule L;
+  L.G = G;
+  L.nth = nth;
+  L.n_rows = (int32_t)n_rows;
+  L.slot_vertex.assign((size_t)n_rows, -1);
+  for (int32_t v = 0; v < n; v++) {
+    if (inI[(size_t)v]) continue;
+    const int32_t r = res[(size_t)v];
+    row[(size_t)v] = r + G * fill[(size_t)r]++;
+    L.slot_vertex[(size_t)row[(size_t)v]] = v;
+  }
+
+  // 5. descriptors: [C][K + 1][nth]
+  const int32_t per_class = K + 1;
+  L.total_slots = C * per_class;
+  L.desc.assign((size_t)L.total_slots * nth, EdgeDesc{0u, 0.0f});
+  L.K.assign((size_t)C, per_class);
+  L.padded.assign((size_t)C, per_class * nth);
+  for (int32_t k = 0; k < K; k++) {
+    for (int32_t tg = 0; tg < groups_per_k; tg++) {
+      const int32_t gi = k * groups_per_k + tg;
+      for (int32_t c = 0; c < C; c++) {
+        uint64_t gm = usedG[(size_t)gi * C + c];
+        uint64_t hm[2] = {usedH[((size_t)gi * 2) * C + c], usedH[((size_t)gi * 2 + 1) * C + c]};
+        for (int32_t p = 0; p < G; p++) {
+          const int32_t t = tg * G + p;
+          const int32_t v = pos_vertex[(size_t)k * nth + t];
+          int32_t e = -1;
+          if (v >= 0)
+            for (const Adj &a : adj[(size_t)v])
+              if (a.cls == c) e = a.edge;
+          EdgeDesc &d = L.desc[((size_t)c * per_class + k) * nth + t];
+          if (e >= 0) {
+            const bool flip = s.h_ev[(size_t)e] == v;
+            const int32_t w = flip ? s.h_eu[(size_t)e] : s.h_ev[(size_t)e];
+            d.slots = (uint32_t)row[(size_t)w] | (flip ? 1u << 16 : 0u);
+            d.J = (float)s.h_J[(size_t)e];
+          }
+        }
+        // dummy rows: residues free in the group and the half
+        for (int32_t half = 0; half < 2 && half * H < G; half++) {
+          for (int32_t p = half * H; p < (half + 1) * H && p < G; p++) {
+            const int32_t t = tg * G + p;
+            const int32_t v = pos_vertex[(size_t)k * nth + t];
+            bool active = false;
+            if (v >= 0)
+              for (const Adj &a : adj[(size_t)v])
+                if (a.cls == c) active = true;
+            if (active) continue;
+            int32_t r = -1;
+            for (int32_t q = 0; q < G && r < 0; q++)
+              if (!((gm >> q) & 1u) && !((hm[half] >> (q % H)) & 1u)) r = q;
+            if (r < 0) return set_error(COSM_ERANGE, "no free dummy row");
+            gm |= bit(r);
+            hm[half] |= bit(r % H);
+            EdgeDesc &d = L.desc[((size_t)c * per_class + k) * nth + t];
+            d.slots = (uint32_t)(n_rows + r);
+            d.J = 0.0f;
+          }
+        }
+      }
+    }
+  }
+  for (int32_t c = 0; c < C; c++) {
+    for (int32_t tg = 0; tg < groups_per_k; tg++) {
+      uint64_t gU = fG[((size_t)c * groups_per_k + tg) * 2], gV = fG[((size_t)c * groups_per_k + tg) * 2 + 1];
+      for (int32_t p = 0; p < G; p++) {
+        const int32_t t = tg * G + p, half = p / H;
+        uint64_t &hU = fH[(((size_t)c * groups_per_k + tg) * 2 + half) * 2];
+        uint64_t &hV = fH[(((size_t)c * groups_per_k + tg) * 2 + half) * 2 + 1];
+        EdgeDesc &d = L.desc[((size_t)c * per_class + K) * nth + t];
+        const int32_t e = free_at[(size_t)c * nth + t];
+        if (e >= 0) {
+          d.slots = (uint32_t)row[(size_t)s.h_eu[(size_t)e]] |
+                    ((uint32_t)row[(size_t)s.h_ev[(size_t)e]] << 16);
+          d.J = (float)s.h_J[(size_t)e];
+          continue;
+        }
+        int32_t ru = -1, rv = -1;
+        for (int32_t q = 0; q < G && ru < 0; q++)
+          if (!((gU >> q) & 1u) && !((hU >> (q % H)) & 1u)) ru = q;
+        for (int32_t q = 0; q < G && rv < 0; q++)
+          if (!((gV >> q) & 1u) && !((hV >> (q % H)) & 1u)) rv = q;
+        if (ru < 0 || rv < 0) {  // a group with conflicts: any dummy row
+          ru = ru < 0 ? 0 : ru;
+          rv = rv < 0 ? 0 : rv;
+        }
+        gU |= bit(ru); hU |= bit(ru % H);
+        gV |= bit(rv); hV |= bit(rv % H);
+        d.slots = (uint32_t)(n_rows + ru) | ((uint32_t)(n_rows + rv) << 16);
+        d.J = 0.0f;
+      }
+    }
+  }
+  L.reg_k = K;
+  L.reg_free = reg_free;
+  L.reg_vertex = pos_vertex;
+  L.reg_edges = reg_edges;
+  L.reg_conflicts = conflicts;
+  L.fuse = false;
+  L.fuse_k = 0;
+  L.dummy_pairs = true;
+  *out = std::move(L);
+  return COSM_OK;
+}
+
+}  // namespace
+
+int build_reg_schedule(const cosm_state &s, int32_t W, int32_t K, int32_t nth_request,
+                       LdsSchedule *out) {
+  LdsSchedule a, b;
+  const int ra = build_reg_impl(s, W, K, nth_request, true, &a);
+  const int rb = build_reg_impl(s, W, K, nth_request, false, &b);
+  if (ra && rb) return ra;
+  clear_error();
+  // more edges in registers first, then fewer bank conflicts
+  const bool take_a = rb || (ra == 0 && (a.reg_edges > b.reg_edges ||
+                                         (a.reg_edges == b.reg_edges &&
+                                          a.reg_conflicts <= b.reg_conflicts)));
+  *out = std::move(take_a ? a : b);
+  return COSM_OK;
+}
+
+}  // namespace cosm

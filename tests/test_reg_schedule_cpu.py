@@ -1,0 +1,75 @@
+"""Host checks of the register-owner schedule (reg_schedule.cpp), compiled with
+g++ and run on the CPU (tests/cpp/reg_check.cpp): every edge exactly once, in
+its class, with its own u / v roles; the register vertices independent and
+each held once; every other vertex in exactly one LDS row; lanes without an
+edge on dummy rows with J = 0; and, for the 3-regular benchmark graph, no LDS
+bank touched twice within a lane group on the gfx950 model."""
+import os
+import subprocess
+
+import pytest
+
+import cosm_inputs as ci
+import paper_2605_30355_amd as cosm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+BIN = os.path.join(ROOT, "tests", "cpp", "reg_check")
+
+
+@pytest.fixture(scope="module")
+def checker():
+    src = os.path.join(ROOT, "tests", "cpp", "reg_check.cpp")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_2605_30355_amd", "csrc"),
+                           "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", src,
+                           os.path.join(ROOT, "paper_2605_30355_amd", "csrc", "reg_schedule.cpp"),
+                           "-o", BIN])
+    return BIN
+
+
+def run(checker, inst, method, sides, W, K):
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, method, sides)
+    txt = f"{inst.n} {inst.m} {C}\n" + "\n".join(
+        f"{u} {v} {J} {c}" for u, v, J, c in zip(inst.eu, inst.ev, inst.J, colour))
+    return subprocess.run([checker, str(W), str(K)], input=txt, capture_output=True, text=True,
+                          timeout=120)
+
+
+def fields(out):
+    return dict(kv.split("=") for kv in out.split())
+
+
+@pytest.mark.parametrize("W", [1, 2, 4])
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_maxcut_graph_complete_and_conflict_free(checker, W, K):
+    r = run(checker, ci.random_regular(2000, 3, seed=2), cosm.COLOR_BALANCED, None, W, K)
+    assert r.returncode == 0, r.stdout + r.stderr
+    f = fields(r.stdout)
+    assert f["equal"] == "1" and f["indep"] == "1" and f["rows_ok"] == "1", r.stdout
+    assert f["bad_dummy"] == "0" and f["conflicts"] == "0", r.stdout
+    # an independent set of a random cubic graph covers most edges
+    assert int(f["reg_edges"]) >= 0.8 * 3000, r.stdout
+
+
+@pytest.mark.parametrize("case", [
+    (ci.torus(20), cosm.COLOR_TORUS, [20, 20]),
+    (ci.random_regular(600, 3, seed=8, weights="pm12"), cosm.COLOR_MISRA_GRIES, None),
+    (ci.small_random(40, 60, seed=3), cosm.COLOR_GREEDY, None),
+], ids=lambda c: c[0].name)
+@pytest.mark.parametrize("W", [1, 2, 4])
+def test_other_graphs_complete(checker, case, W):
+    inst, method, sides = case
+    r = run(checker, inst, method, sides, W, 1)
+    if r.returncode == 2:
+        assert "ERANGE" in r.stdout
+        return
+    assert r.returncode == 0, r.stdout + r.stderr
+    f = fields(r.stdout)
+    assert f["equal"] == "1" and f["indep"] == "1" and f["rows_ok"] == "1", r.stdout
+    assert f["bad_dummy"] == "0", r.stdout
+
+
+def test_not_applicable_beyond_eight_classes(checker):
+    inst = ci.small_random(37, 150, seed=5)
+    r = run(checker, inst, cosm.COLOR_GREEDY, None, 2, 1)
+    assert r.returncode == 2 and "ERANGE" in r.stdout
