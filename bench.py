@@ -35,8 +35,8 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-ops per second, non-packed FP32
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the counter
 # reads for a 256 MiB device copy (FETCH_SIZE 131087 KiB -> x2.0; WRITE_SIZE
 # 262144 KiB -> x1.0).  Valid only for the kernel sources they were taken on.
-TRAFFIC = dict(fetch_kib=4191.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
-               sources_sha256="638b17d54047e9538b5b3a15b478bf47c730f66a540fbb820ae5ed0766db8cf2")
+TRAFFIC = dict(fetch_kib=4196.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
+               sources_sha256="19c95a03122c5307f539ce2984fa6c498d1eef5a7317495d4113d4895226af8a")
 TRAFFIC_SOURCES = ("paper_2605_30355_amd/csrc/kernels.hip",
                    "paper_2605_30355_amd/csrc/device_common.hpp")
 
@@ -526,6 +526,8 @@ def main():
         for name, over in (("batched_fp32", {}), ("batched_fp16", {"storage": cosm.STORE_FP16}),
                            ("batched_bf16", {"storage": cosm.STORE_BF16}),
                            ("batched_fix16", {"storage": cosm.STORE_FIX16}),
+                           ("batched_fix32", {"storage": cosm.STORE_FIX32}),
+                           ("batched_fp32_register_layout", {"lds_form": cosm.LDS_FORM_REGISTER}),
                            ("batched_fp32_optimal_readout", {"readout": cosm.READOUT_OPTIMAL}),
                            ("batched_fp32_minimum_colouring", {"colouring": cosm.COLOR_MINIMUM})):
             col2, C2 = colour, C
