@@ -104,16 +104,24 @@ int reg_schedule_for(const cosm_state &s, int32_t W, int32_t K, int32_t nth, Lds
 }
 
 // The register form for a fixed row width: the fewest register rows per
-// thread that give a schedule.
+// thread that hold the whole independent set (with a thread count given,
+// the set may need 2 or 4 rows per thread), else the most that give one.
 int pick_reg_schedule(cosm_state *s, int32_t W, int32_t nth) {
   int rc = COSM_ERANGE;
+  bool any = false;
+  LdsSchedule best;
   for (int32_t K : {1, 2, 4}) {
-    rc = reg_schedule_for(*s, W, K, nth, &s->lds);
-    if (rc == COSM_OK) {
-      clear_error();
-      return COSM_OK;
-    }
+    LdsSchedule L;
+    if (reg_schedule_for(*s, W, K, nth, &L) != COSM_OK) continue;
+    any = true;
+    const bool whole = L.reg_set <= (int64_t)K * L.nth;
+    best = std::move(L);
+    if (whole) break;
   }
+  if (!any) return set_error(COSM_ERANGE, "the register form does not apply to this shape");
+  clear_error();
+  s->lds = std::move(best);
+  rc = COSM_OK;
   return rc;
 }
 

@@ -120,6 +120,7 @@ struct LdsSchedule {
   int32_t reg_k = 0;
   int32_t reg_free = 0;
   std::vector<int32_t> reg_vertex;
+  int64_t reg_set = 0;          // size of the independent set before any cut to K nth
   int64_t reg_edges = 0;        // edges with an endpoint in registers
   int64_t reg_conflicts = 0;    // lane groups whose rows share a bank (extra LDS cycles)
 };

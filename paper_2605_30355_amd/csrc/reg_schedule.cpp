@@ -148,6 +148,7 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
   }
   if (nth % 64 != 0 || nth < 64 || nth > 1024) return set_error(COSM_EINVAL, "bad thread count");
   const int64_t cap = (int64_t)K * nth;
+  const int64_t set_size = (int64_t)cand.size();
   if ((int64_t)cand.size() > cap) {
     // keep the vertices that cover the most edges
     std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
@@ -424,6 +425,7 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
   L.reg_k = K;
   L.reg_free = reg_free;
   L.reg_vertex = pos_vertex;
+  L.reg_set = set_size;
   L.reg_edges = reg_edges;
   L.reg_conflicts = conflicts;
   L.fuse = false;

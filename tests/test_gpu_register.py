@@ -88,6 +88,38 @@ def test_ragged_resumed_pm12():
     both(inst, colour, C, 9, 37, [250, 250], **kw)
 
 
+@pytest.mark.parametrize("threads,rows", [(448, 2), (256, 4)])
+def test_two_and_four_register_rows(threads, rows):
+    """Fewer threads than register vertices: 2 or 4 register rows per thread."""
+    inst = ci.random_regular(2000, 3, seed=2, weights="maxcut1")
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+    for storage in (cosm.STORE_FP32, cosm.STORE_FIX16):
+        kw = dict(storage=storage, sweeps_per_trial=1200, dwt_ratio=1.0, dwt_period=6,
+                  replicas_per_wg=2 if storage == cosm.STORE_FP32 else 4, threads_per_wg=threads)
+        a = both(inst, colour, C, 5, 200, [600, 600], **kw)
+        assert a[4]["register_rows"] == rows and a[4]["threads_per_wg"] == threads
+    oracle_rows(inst, colour, C, cosm.Params(**kw), 5, [0, 199], 1200, a[0])
+
+
+@pytest.mark.parametrize("case", ["torus21", "rr4"])
+def test_five_and_six_classes(case):
+    """More than four classes (the odd torus pattern, a 4-regular graph)."""
+    if case == "torus21":
+        inst = ci.torus(21, seed=2)
+        colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [21, 21])
+        assert C == 6
+    else:
+        inst = ci.random_regular(1000, 4, seed=8, weights="pm1")
+        colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_MISRA_GRIES)
+        assert C == 5
+    kw = dict(sweeps_per_trial=900, dwt_ratio=0.5, dwt_period=3)
+    x = both(inst, colour, C, 3, 96, [900], **kw)[0]
+    oracle_rows(inst, colour, C, cosm.Params(**kw), 3, [0, 95], 900, x)
+    kw.update(threads_per_wg=128 if case == "torus21" else 256, replicas_per_wg=2)
+    a = both(inst, colour, C, 3, 96, [450, 450], **kw)
+    assert a[4]["register_rows"] == 2
+
+
 def test_not_applicable():
     inst = ci.torus(8)
     colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [8, 8])
