@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
 #pragma unroll
     for (int c = 0; c < CM; c++) {
       if (c < CLASSES || (CLASSES == 0 && c < a.C)) {
-        const bool fon = (wave_free >> c) & 1u;  // uniform over the wave
+        const bool fon = __builtin_amdgcn_readfirstlane((wave_free >> c) & 1u) != 0u;
         uint32_t w[K][W], pu[W], pv[W];
 #pragma unroll
         for (int k = 0; k < K; k++) lds_load_at<W>(lds, row[c][k], w[k]);
