@@ -73,3 +73,20 @@ def test_not_applicable_beyond_eight_classes(checker):
     inst = ci.small_random(37, 150, seed=5)
     r = run(checker, inst, cosm.COLOR_GREEDY, None, 2, 1)
     assert r.returncode == 2 and "ERANGE" in r.stdout
+
+
+@pytest.mark.parametrize("txt", [
+    "2 1 1\n0 1 -2 0",                                   # one edge
+    "5 4 4\n0 1 1 0\n0 2 1 1\n0 3 -1 2\n0 4 1 3",        # a star: its centre alone covers it
+    "3 3 3\n0 1 1 0\n1 2 1 1\n0 2 -1 2",                 # a triangle: one edge between LDS rows
+    "6 2 1\n0 1 1 0\n4 5 1 0",                           # isolated vertices
+], ids=["one_edge", "star", "triangle", "isolated"])
+@pytest.mark.parametrize("W", [1, 2, 4])
+@pytest.mark.parametrize("K", [1, 4])
+def test_degenerate_graphs(checker, txt, W, K):
+    r = subprocess.run([checker, str(W), str(K)], input=txt, capture_output=True, text=True,
+                       timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
+    f = fields(r.stdout)
+    assert f["equal"] == "1" and f["indep"] == "1" and f["rows_ok"] == "1", r.stdout
+    assert f["bad_dummy"] == "0" and f["conflicts"] == "0", r.stdout
