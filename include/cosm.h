@@ -93,8 +93,10 @@ enum { COSM_SCHED_GRID = 0, COSM_SCHED_CONTINUOUS = 1 };
  * edges outside the register set (COSM_ERANGE otherwise when requested).
  * REGISTER moves far fewer LDS bytes but needs more vector and scalar
  * instructions per update (the u / v roles of each edge, the dummy lanes of
- * vertices without an edge in a class); on gfx950 the pair layout, limited by
- * both, measured faster in every configuration tried, so AUTO means PAIR. */
+ * vertices without an edge in a class): it wins where LDS traffic dominates
+ * (the large even tori) and loses on the 3-regular benchmark graph.  AUTO:
+ * when the shape is autotuned both layouts are timed and the faster kept;
+ * otherwise PAIR. */
 enum { COSM_LDS_FORM_AUTO = 0, COSM_LDS_FORM_PAIR = 1, COSM_LDS_FORM_REGISTER = 2 };
 /* SCS: Eqs. (12)-(13), classes one after another.  FULL_GRADIENT: Eq. (8), all
  * edges read the same state (the "without SCS" variant of Table VII). */

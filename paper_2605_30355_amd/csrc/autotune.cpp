@@ -2,8 +2,8 @@
 //
 // Candidates: every LDS row width that fits (1, 2 or 4 words per row, i.e. 1-4
 // FP32 or 2-8 16-bit replicas per workgroup) crossed with a few thread counts
-// (pair layout), or with 1, 2 or 4 register rows per thread when the register
-// layout is requested.
+// (pair layout), and with 1, 2 or 4 register rows per thread (register layout,
+// where it applies; only these when it is requested).
 // Each candidate runs a short timed probe on the state's own phases (which are
 // re-drawn afterwards, so the probe leaves no trace in the trajectory), and the
 // fastest shape is kept.  Results are cached per process, keyed by the
@@ -149,7 +149,7 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
   if (s->p.lds_form != COSM_LDS_FORM_REGISTER)
     for (int32_t W : widths)
       for (int32_t req : {0, 512, 768, 1024}) cands.emplace_back(W, req, 0);
-  if (s->p.lds_form == COSM_LDS_FORM_REGISTER && reg_form_supported(*s))
+  if (s->p.lds_form != COSM_LDS_FORM_PAIR && reg_form_supported(*s))
     for (int32_t W : widths)
       for (int32_t K : {1, 2, 4}) cands.emplace_back(W, 0, K);
   std::vector<Shape> tried;

@@ -211,7 +211,10 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
           break;
         }
       }
-      if (chosen < 0) break;  // nothing fits this group any more
+      if (chosen < 0) {  // nothing fits this half any more: on to the next half
+        p = (half + 1) * H - 1;
+        continue;
+      }
       placed[(size_t)chosen] = 1;
       pos_vertex[(size_t)k * nth + tg * G + p] = chosen;
       for (const Adj &a : adj[(size_t)chosen]) {

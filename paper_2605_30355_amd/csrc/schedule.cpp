@@ -100,6 +100,7 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
                        bool dummy_pairs) {
   const int32_t n = s.n, C = s.C, G = W == 1 ? 32 : 64 / W, H = 32 / W;
   const int64_t m = s.m;
+  *out = LdsSchedule();  // nothing of an earlier schedule (e.g. register rows) survives
   LdsSchedule &L = *out;
   L.G = G;
   L.n_rows = n;

@@ -120,6 +120,27 @@ def test_five_and_six_classes(case):
     assert a[4]["register_rows"] == 2
 
 
+@pytest.mark.parametrize("case", ["maxcut", "torus"])
+def test_auto_layout_equals_pair(case):
+    """AUTO times both layouts and keeps the faster; whichever it keeps, the
+    result equals the pair layout's (the probes leave no state behind)."""
+    if case == "maxcut":
+        inst = ci.random_regular(2000, 3, seed=2, weights="maxcut1")
+        colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+        kw, R = dict(sweeps_per_trial=800, dwt_ratio=1.0, dwt_period=6), 1024
+    else:
+        inst = ci.torus(40, seed=6)
+        colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [40, 40])
+        kw, R = dict(sweeps_per_trial=800, dwt_ratio=0.5, dwt_period=3), 512
+    say(f"[gpu] auto vs pair {inst.name}")
+    a = run(inst, colour, C, cosm.Params(lds_form=cosm.LDS_FORM_AUTO, **kw), 13, R, [400, 400])
+    b = run(inst, colour, C, cosm.Params(lds_form=cosm.LDS_FORM_PAIR, **kw), 13, R, [400, 400])
+    say(f"[gpu]   auto kept: {a[4]}")
+    assert a[4]["lds_form"] in (cosm.LDS_FORM_PAIR, cosm.LDS_FORM_REGISTER)
+    for u, v in zip(a[:4], b[:4]):
+        assert np.array_equal(u, v)
+
+
 def test_not_applicable():
     inst = ci.torus(8)
     colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [8, 8])
