@@ -111,11 +111,19 @@ def cpu_baseline(inst, colour, C, seconds_goal=10.0):
     oracle.sweeps(prob, op, 7, 0, x, 0, WORKLOAD["sweeps"], n_threads=threads)
     oracle.readout(prob, op, x)
     dt = time.perf_counter() - t0
+    # and one core: one replica, the whole trial
+    x1 = oracle.init_phases(inst.n, 7, 0, 1)
+    t1 = time.perf_counter()
+    oracle.sweeps(prob, op, 7, 0, x1, 0, WORKLOAD["sweeps"], n_threads=1)
+    oracle.readout(prob, op, x1)
+    dt1 = time.perf_counter() - t1
     return {"value": R * WORKLOAD["sweeps"] * inst.m / dt, "unit": "edge-updates/s",
             "cores": threads, "kind": "oracle",
             "sample": f"{R} replicas x {WORKLOAD['sweeps']} sweeps of {WORKLOAD['name']} "
                       f"(init, sweeps, readout), {dt:.1f} s wall",
-            "seconds": round(dt, 2)}
+            "seconds": round(dt, 2),
+            "one_core": {"value": WORKLOAD["sweeps"] * inst.m / dt1, "unit": "edge-updates/s",
+                         "sample": f"1 replica x {WORKLOAD['sweeps']} sweeps, {dt1:.2f} s wall"}}
 
 
 STREAM = dict(name="mixed-stream-256", requests=256, n_min=400, n_max=20000, seed=5,
