@@ -407,6 +407,68 @@ def stream_bench():
     }
 
 
+LARGE = dict(sweeps=300, reps=2, seed=1)
+
+
+def large_bench():
+    """The large-graph configurations: the 100x100 and 141x141 +-1 tori at 4096
+    replicas (FP32, BF16 and FIX16 storage) and the 5-regular N = 20000 and
+    capped Erdos-Renyi N = 10000 graphs at 2048 replicas (FP32): edge-updates/s
+    of the sweep kernel (HIP events around whole sweep calls after a warm-up),
+    the shape and layout the autotuner kept, and the LDS roofline fraction
+    (16 B, or 8 B for 16-bit storage, per edge update plus the twist's bytes)."""
+    import torch
+
+    import cosm_inputs as ci
+    import paper_2605_30355_amd as cosm
+
+    torch.cuda.set_device(0)
+    cases = [("torus-100x100", ci.torus(100, seed=3), cosm.COLOR_TORUS, [100, 100], 4096,
+              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "bf16", "fix16")),
+             ("torus-141x141", ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141], 4096,
+              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "bf16", "fix16")),
+             ("rr5-n20000", ci.random_regular(20000, 5, seed=1000, weights="pm1"),
+              cosm.COLOR_BALANCED, None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32",)),
+             ("er-n10000", ci.erdos_renyi_capped(10000, 4, 8, seed=3), cosm.COLOR_MISRA_GRIES,
+              None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32",))]
+    storages = {"fp32": cosm.STORE_FP32, "bf16": cosm.STORE_BF16, "fix16": cosm.STORE_FIX16}
+    S, reps = LARGE["sweeps"], LARGE["reps"]
+    stream = torch.cuda.current_stream()
+    out = {"metric": "edge-updates/s of the sweep on the large-graph configurations, 1 MI355X",
+           "sweeps_per_call": S, "calls": reps, "cases": []}
+    for name, inst, meth, sides, R, kw, sts in cases:
+        colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, meth, sides)
+        for st_name in sts:
+            p = cosm.Params(sweeps_per_trial=S * (reps + 1), storage=storages[st_name], **kw)
+            st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=LARGE["seed"],
+                            replicas=R)
+            st.sweep(S)  # warm-up
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                st.sweep(S)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3 / reps
+            info = st.info()
+            st.close()
+            rate = inst.m * S * R / sec
+            b = 8 if st_name in ("bf16", "fix16") else 16
+            twist_b = b / 2 * inst.n * R * (S / kw["dwt_period"]) / sec  # read + write per twist
+            frac = (rate * b + twist_b) / (LDS_PEAK_GBS * 1e9)
+            form = {cosm.RES_LDS: "lds", cosm.RES_HBM: "hbm"}.get(info["residency"], "plain")
+            rec = {"workload": name, "n": inst.n, "m": inst.m, "classes": C, "replicas": R,
+                   "storage": st_name, "edge_updates_per_s": round(rate, 1),
+                   "replica_sweeps_per_s": round(S * R / sec, 1), "form": form,
+                   "layout": {1: "pair", 2: "register"}.get(info["lds_form"], None),
+                   "register_rows": info["register_rows"],
+                   "replicas_per_wg": info["replicas_per_wg"],
+                   "threads_per_wg": info["threads_per_wg"], "lds_roofline_frac": round(frac, 3)}
+            out["cases"].append(rec)
+            log(f"large {rec}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -422,6 +484,8 @@ def main():
                     help="run the Table VII ablation instead (prints its own JSON line)")
     ap.add_argument("--scaling", action="store_true",
                     help="run the TTS scaling study on +-1/+-2 tori instead (own JSON line)")
+    ap.add_argument("--large", action="store_true",
+                    help="measure the large tori and bounded-degree graphs instead (own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's replicas are independent, so several "
@@ -436,6 +500,9 @@ def main():
         return
     if args.scaling:
         print(json.dumps(scaling_bench()), flush=True)
+        return
+    if args.large:
+        print(json.dumps(large_bench()), flush=True)
         return
 
     import numpy as np
