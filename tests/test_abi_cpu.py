@@ -154,3 +154,25 @@ def test_largest_class_last(case):
     relabel = np.arange(C0)
     relabel[[big, C0 - 1]] = [C0 - 1, big]
     assert np.array_equal(c1, relabel[c0])
+
+
+def test_params_validation_on_host():
+    """cosm_workspace_bytes validates the parameters without a device: storage
+    formats (FIX32 needs the grid schedule) and the LDS layout selector."""
+    import ctypes
+    lib = cosm.load_library()
+
+    def status(**kw):
+        p = cosm.Params(**kw)._c()
+        out = ctypes.c_size_t(0)
+        return lib.cosm_workspace_bytes(100, 200, 4, 8, ctypes.byref(p), ctypes.byref(out)), out.value
+
+    assert status()[0] == 0 and status()[1] > 0
+    assert status(storage=cosm.STORE_FIX32)[0] == 0
+    assert status(storage=cosm.STORE_FIX32, schedule=cosm.SCHED_CONTINUOUS)[0] == -1
+    assert status(storage=5)[0] == -1
+    for form in (cosm.LDS_FORM_AUTO, cosm.LDS_FORM_PAIR, cosm.LDS_FORM_REGISTER):
+        assert status(lds_form=form)[0] == 0
+    assert status(lds_form=3)[0] == -1
+    # FIX32 phases take 4 bytes per replica-vertex, FIX16 2
+    assert status(storage=cosm.STORE_FIX32)[1] > status(storage=cosm.STORE_FIX16)[1]
