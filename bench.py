@@ -412,8 +412,8 @@ LARGE = dict(sweeps=300, reps=2, seed=1)
 
 def large_bench():
     """The large-graph configurations: the 100x100 and 141x141 +-1 tori at 4096
-    replicas (FP32, BF16 and FIX16 storage) and the 5-regular N = 20000 and
-    capped Erdos-Renyi N = 10000 graphs at 2048 replicas (FP32): edge-updates/s
+    replicas (FP32, FIX32, BF16 and FIX16 storage) and the 5-regular N = 20000 and
+    capped Erdos-Renyi N = 10000 graphs at 2048 replicas (FP32, FIX32): edge-updates/s
     of the sweep kernel (HIP events around whole sweep calls after a warm-up),
     the shape and layout the autotuner kept, and the LDS roofline fraction
     (16 B, or 8 B for 16-bit storage, per edge update plus the twist's bytes)."""
@@ -424,14 +424,15 @@ def large_bench():
 
     torch.cuda.set_device(0)
     cases = [("torus-100x100", ci.torus(100, seed=3), cosm.COLOR_TORUS, [100, 100], 4096,
-              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "bf16", "fix16")),
+              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "bf16", "fix16")),
              ("torus-141x141", ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141], 4096,
-              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "bf16", "fix16")),
+              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "bf16", "fix16")),
              ("rr5-n20000", ci.random_regular(20000, 5, seed=1000, weights="pm1"),
-              cosm.COLOR_BALANCED, None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32",)),
+              cosm.COLOR_BALANCED, None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32", "fix32")),
              ("er-n10000", ci.erdos_renyi_capped(10000, 4, 8, seed=3), cosm.COLOR_MISRA_GRIES,
-              None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32",))]
-    storages = {"fp32": cosm.STORE_FP32, "bf16": cosm.STORE_BF16, "fix16": cosm.STORE_FIX16}
+              None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32", "fix32"))]
+    storages = {"fp32": cosm.STORE_FP32, "fix32": cosm.STORE_FIX32, "bf16": cosm.STORE_BF16,
+                "fix16": cosm.STORE_FIX16}
     S, reps = LARGE["sweeps"], LARGE["reps"]
     stream = torch.cuda.current_stream()
     out = {"metric": "edge-updates/s of the sweep on the large-graph configurations, 1 MI355X",
