@@ -17,8 +17,11 @@
 // LDS vertex is chosen while the register vertices are packed into groups:
 // a vertex joins a group only if, class by class, its neighbours' residues are
 // still free there (unassigned neighbours take a free residue).  Lanes without
-// an edge get dummy rows n_rows + rho with residues free in their group, so
-// every access is conflict-free and needs no branch.
+// an edge get dummy rows n_rows + rho with residues free in their group, so the
+// register slots' accesses are conflict-free and need no branch.  The pair
+// slot's edges are packed the same way, group by group from lane 0 (a wave
+// without one skips the slot); edges that find no conflict-free lane take any
+// free lane and are counted in reg_conflicts.
 //
 // The class order and the edge set per class are unchanged: only which thread
 // applies an update, and in which register or LDS row the phases sit, differ.
