@@ -409,6 +409,94 @@ def stream_bench():
 
 LARGE = dict(sweeps=300, reps=2, seed=1)
 
+# Time to target over many instances of the 5-regular N = 20000 +-1 family
+# (instance seeds first .. first + count - 1).  Per instance: the target is the
+# best energy of target_batches batches of replicas trials (solver seed 1); the
+# time to target is then measured on ttt_batches fresh batches (solver seed 2),
+# at that energy and 0.5 % above it.
+SEEDS = dict(first=1000, count=100, n=20000, degree=5, replicas=2048, sweeps=10000,
+             target_batches=2, ttt_batches=4, relax=0.005)
+
+
+def seeds_bench(count=None, jsonl=None):
+    """Median and interquartile range of TTT @99% over instance seeds."""
+    import numpy as np
+    import torch
+
+    import cosm_inputs as ci
+    import paper_2605_30355_amd as cosm
+
+    torch.cuda.set_device(0)
+    cfg = dict(SEEDS)
+    if count is not None:
+        cfg["count"] = count
+    R, S = cfg["replicas"], cfg["sweeps"]
+    stream = torch.cuda.current_stream()
+    recs = []
+    for k in range(cfg["count"]):
+        seed = cfg["first"] + k
+        inst = ci.random_regular(cfg["n"], cfg["degree"], seed=seed, weights="pm1")
+        colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+        # the shape the autotuner keeps on this family, fixed so that every
+        # instance runs the same kernel
+        p = cosm.Params(sweeps_per_trial=S, dwt_ratio=1.5, dwt_period=3,
+                        lds_form=cosm.LDS_FORM_PAIR, replicas_per_wg=2, threads_per_wg=1024)
+        st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=1, replicas=R)
+        best = None
+        for b in range(cfg["target_batches"]):
+            st.reset(1, b * R)
+            st.sweep(S)
+            H, _, _ = st.energy(return_spins=False)
+            best = int(H.min()) if best is None else min(best, int(H.min()))
+        Hs, ms = [], 0.0
+        for b in range(cfg["ttt_batches"]):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st.reset(2, b * R)
+            st.sweep(S)
+            H, _, _ = st.energy(return_spins=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            Hs.append(H.copy())
+        st.close()
+        H = np.concatenate(Hs)
+        t_trial = ms * 1e-3 / len(H)
+        relaxed = int(math.floor(best * (1.0 - cfg["relax"])))  # H < 0
+        rec = {"seed": seed, "classes": C, "target_H": best, "relaxed_target_H": relaxed,
+               "t_trial_s": t_trial, "best_H_ttt_run": int(H.min())}
+        for label, thr in (("target", best), ("relaxed", relaxed)):
+            hits = int((H <= thr).sum())
+            ps = hits / len(H)
+            r99 = (1.0 if ps >= 1.0 else math.log(0.01) / math.log(1.0 - ps)) if ps > 0 else None
+            rec[label] = {"hits": hits, "ps": ps, "r99": r99,
+                          "ttt_s": t_trial * r99 if r99 is not None else None}
+        recs.append(rec)
+        log(f"seeds {rec}")
+        if jsonl is not None:
+            with open(jsonl, "a") as f:
+                f.write(json.dumps(rec) + "\n")
+
+    def summary(label):
+        # nearest-rank quartiles over every instance, an instance without a hit
+        # counting as an unbounded TTT (null when a quartile falls on one)
+        v = sorted(r[label]["ttt_s"] if r[label]["ttt_s"] is not None else math.inf
+                   for r in recs)
+
+        def rank(p):
+            x = v[max(0, min(len(v) - 1, math.ceil(p / 100 * len(v)) - 1))]
+            return x if math.isfinite(x) else None
+
+        return {"instances_with_hits": sum(1 for x in v if math.isfinite(x)),
+                "instances": len(recs), "median_ttt_s": rank(50),
+                "iqr_ttt_s": [rank(25), rank(75)]}
+
+    return {"metric": "time to target @99% over instance seeds, 5-regular +-1 graphs, 1 MI355X",
+            "config": {k: v for k, v in cfg.items()}, "solver": "FP32, grid schedule, pair layout "
+            "2 replicas x 1024 threads, alpha0 14, dwt ratio 1.5 period 3, 100 bisectors",
+            "t_trial_s_median": float(np.median([r["t_trial_s"] for r in recs])),
+            "target": summary("target"), "relaxed": summary("relaxed"), "instances": recs}
+
 
 def large_bench():
     """The large-graph configurations: the 100x100 and 141x141 +-1 tori at 4096
@@ -487,6 +575,10 @@ def main():
                     help="run the TTS scaling study on +-1/+-2 tori instead (own JSON line)")
     ap.add_argument("--large", action="store_true",
                     help="measure the large tori and bounded-degree graphs instead (own JSON line)")
+    ap.add_argument("--seeds", type=int, nargs="?", const=SEEDS["count"], default=None,
+                    help="time to target over N instance seeds of the 5-regular family instead")
+    ap.add_argument("--seeds-jsonl", default=None,
+                    help="with --seeds: also append each instance's record to this file")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's replicas are independent, so several "
@@ -504,6 +596,9 @@ def main():
         return
     if args.large:
         print(json.dumps(large_bench()), flush=True)
+        return
+    if args.seeds is not None:
+        print(json.dumps(seeds_bench(args.seeds, args.seeds_jsonl)), flush=True)
         return
 
     import numpy as np
