@@ -414,11 +414,18 @@ LARGE = dict(sweeps=300, reps=2, seed=1)
 # best energy of target_batches batches of replicas trials (solver seed 1); the
 # time to target is then measured on ttt_batches fresh batches (solver seed 2),
 # at that energy and 0.5 % above it.
-SEEDS = dict(first=1000, count=100, n=20000, degree=5, replicas=2048, sweeps=10000,
-             target_batches=2, ttt_batches=4, relax=0.005)
+SEEDS = dict(first=1000, count=100, replicas=2048, sweeps=10000, target_batches=2,
+             ttt_batches=4, relax=0.005)
+SEED_FAMILIES = {
+    # instance generator, colouring, the shape the autotuner keeps on the family
+    "rr5": dict(n=20000, make=lambda ci, s: ci.random_regular(20000, 5, seed=s, weights="pm1"),
+                colouring="balanced", rw=2),
+    "er": dict(n=10000, make=lambda ci, s: ci.erdos_renyi_capped(10000, 4, 8, seed=s),
+               colouring="misra-gries", rw=4),
+}
 
 
-def seeds_bench(count=None, jsonl=None):
+def seeds_bench(count=None, jsonl=None, family="rr5"):
     """Median and interquartile range of TTT @99% over instance seeds."""
     import numpy as np
     import torch
@@ -430,17 +437,22 @@ def seeds_bench(count=None, jsonl=None):
     cfg = dict(SEEDS)
     if count is not None:
         cfg["count"] = count
+    fam = SEED_FAMILIES[family]
+    cfg.update(family=family, n=fam["n"], colouring=fam["colouring"])
     R, S = cfg["replicas"], cfg["sweeps"]
     stream = torch.cuda.current_stream()
     recs = []
     for k in range(cfg["count"]):
         seed = cfg["first"] + k
-        inst = ci.random_regular(cfg["n"], cfg["degree"], seed=seed, weights="pm1")
-        colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+        inst = fam["make"](ci, seed)
+        colour, C = cosm.build_partitions(
+            inst.n, inst.eu, inst.ev,
+            cosm.COLOR_BALANCED if fam["colouring"] == "balanced" else cosm.COLOR_MISRA_GRIES)
         # the shape the autotuner keeps on this family, fixed so that every
         # instance runs the same kernel
         p = cosm.Params(sweeps_per_trial=S, dwt_ratio=1.5, dwt_period=3,
-                        lds_form=cosm.LDS_FORM_PAIR, replicas_per_wg=2, threads_per_wg=1024)
+                        lds_form=cosm.LDS_FORM_PAIR, replicas_per_wg=fam["rw"],
+                        threads_per_wg=1024)
         st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=1, replicas=R)
         best = None
         for b in range(cfg["target_batches"]):
@@ -491,9 +503,9 @@ def seeds_bench(count=None, jsonl=None):
                 "instances": len(recs), "median_ttt_s": rank(50),
                 "iqr_ttt_s": [rank(25), rank(75)]}
 
-    return {"metric": "time to target @99% over instance seeds, 5-regular +-1 graphs, 1 MI355X",
-            "config": {k: v for k, v in cfg.items()}, "solver": "FP32, grid schedule, pair layout "
-            "2 replicas x 1024 threads, alpha0 14, dwt ratio 1.5 period 3, 100 bisectors",
+    return {"metric": f"time to target @99% over instance seeds, {family} +-1 graphs, 1 MI355X",
+            "config": {k: v for k, v in cfg.items()}, "solver": f"FP32, grid schedule, pair layout "
+            f"{fam['rw']} replicas x 1024 threads, alpha0 14, dwt ratio 1.5 period 3, 100 bisectors",
             "t_trial_s_median": float(np.median([r["t_trial_s"] for r in recs])),
             "target": summary("target"), "relaxed": summary("relaxed"), "instances": recs}
 
@@ -579,6 +591,8 @@ def main():
                     help="time to target over N instance seeds of the 5-regular family instead")
     ap.add_argument("--seeds-jsonl", default=None,
                     help="with --seeds: also append each instance's record to this file")
+    ap.add_argument("--family", default="rr5", choices=sorted(SEED_FAMILIES),
+                    help="with --seeds: 5-regular N=20000 (rr5) or capped Erdos-Renyi N=10000 (er)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's replicas are independent, so several "
@@ -598,7 +612,7 @@ def main():
         print(json.dumps(large_bench()), flush=True)
         return
     if args.seeds is not None:
-        print(json.dumps(seeds_bench(args.seeds, args.seeds_jsonl)), flush=True)
+        print(json.dumps(seeds_bench(args.seeds, args.seeds_jsonl, args.family)), flush=True)
         return
 
     import numpy as np
