@@ -335,8 +335,9 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
 // in registers; lanes without an edge use dummy rows with J = 0.  The twist visits the LDS rows (all threads) and the
 // register rows (their owner), after the last class.
 // ---------------------------------------------------------------------------
-template <int ST, int W, int K, int CM, int CLASSES>
+template <int ST, int W, int K, int CM, int CLASSES, bool FUSE>
 __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
+  static_assert(!FUSE || CLASSES == CM, "the fused twist needs the exact class count");
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
@@ -359,18 +360,18 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
   float *theta_buf = reinterpret_cast<float *>(lds + (size_t)(a.n_rows + kDummyRows) * W);
   // HBM -> register rows
   uint32_t reg[K][W];
-  int32_t rv[K];
 #pragma unroll
   for (int k = 0; k < K; k++) {
-    rv[k] = a.reg_vertex[k * nth + tid];
+    const int32_t v = a.reg_vertex[k * nth + tid];
     float x[RW];
 #pragma unroll
     for (int q = 0; q < RW; q++)
-      x[q] = (rv[k] >= 0 && q < nvalid) ? F::load_elem(a.phases, (size_t)rv[k] * a.R + r0 + q) : 0.0f;
+      x[q] = (v >= 0 && q < nvalid) ? F::load_elem(a.phases, (size_t)v * a.R + r0 + q) : 0.0f;
     F::template pack<W>(x, reg[k]);
   }
-  // the schedule: [C][K + 1][nth]
-  uint32_t row[CM][K], flip[CM][K], fu[CM], fv[CM];
+  // the schedule: [C][K + 1][nth]; a register slot keeps its row's byte offset
+  // (a multiple of 4) with the role flag in bit 0
+  uint32_t row[CM][K], fuv[CM];
   float jr[CM][K], jf[CM];
 #pragma unroll
   for (int c = 0; c < CM; c++) {
@@ -378,13 +379,11 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
 #pragma unroll
     for (int k = 0; k < K; k++) {
       const EdgeDesc d = on ? a.desc[(size_t)(c * (K + 1) + k) * nth + tid] : EdgeDesc{0u, 0.0f};
-      row[c][k] = (d.slots & 0xffffu) * ROWB;
-      flip[c][k] = (d.slots >> 16) & 1u;
+      row[c][k] = (d.slots & 0xffffu) * ROWB | ((d.slots >> 16) & 1u);
       jr[c][k] = d.J;
     }
     const EdgeDesc d = on ? a.desc[(size_t)(c * (K + 1) + K) * nth + tid] : EdgeDesc{0u, 0.0f};
-    fu[c] = (d.slots & 0xffffu) * ROWB;
-    fv[c] = (d.slots >> 16) * ROWB;
+    fuv[c] = d.slots;  // u | v << 16 (rows)
     jf[c] = d.J;
   }
   // the pair slot's edges sit in the first lanes: a wave with none of them in
@@ -406,31 +405,64 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
     float alpha, twist;
     chunk.get(it & 63u, alpha, twist);
     const float alpha_s = alpha * F::kStepScale;
+    // FUSE: on a twist sweep the last class twists every LDS row as it updates
+    // it (the schedule touches each exactly once there) and the owners twist
+    // the register rows after it
+    bool fuse_now = false;
+    float fth[RW], ftw[RW];
+    if constexpr (FUSE) {
+      fuse_now = chunk.twist_at(it & 63u);
+      if (fuse_now) {
+        const int slot = (int)(tw % (uint32_t)kThetaChunk);
+        if (slot == 0) {
+          theta_fill(theta_buf, nullptr, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0,
+                     a.k0, a.k1, sc.win, sc.tshift, sc.tscale);
+          __syncthreads();
+        }
+        tw++;
+#pragma unroll
+        for (int k = 0; k < RW; k++) {
+          fth[k] = theta_buf[slot * RW + k];
+          ftw[k] = twist;
+        }
+      }
+    }
 #pragma unroll
     for (int c = 0; c < CM; c++) {
       if (c < CLASSES || (CLASSES == 0 && c < a.C)) {
+        const bool last_twist = FUSE && c == CM - 1 && fuse_now;
         const bool fon = __builtin_amdgcn_readfirstlane((wave_free >> c) & 1u) != 0u;
         uint32_t w[K][W], pu[W], pv[W];
 #pragma unroll
-        for (int k = 0; k < K; k++) lds_load_at<W>(lds, row[c][k], w[k]);
+        for (int k = 0; k < K; k++) lds_load_at<W>(lds, row[c][k] & ~1u, w[k]);
         if (fon) {
-          lds_load_at<W>(lds, fu[c], pu);
-          lds_load_at<W>(lds, fv[c], pv);
+          lds_load_at<W>(lds, (fuv[c] & 0xffffu) * ROWB, pu);
+          lds_load_at<W>(lds, (fuv[c] >> 16) * ROWB, pv);
         }
 #pragma unroll
         for (int k = 0; k < K; k++) {
-          update_reg_words<ST, W>(reg[k], w[k], alpha_s * jr[c][k], flip[c][k]);
-          lds_store_at<W>(lds, row[c][k], w[k]);
+          update_reg_words<ST, W>(reg[k], w[k], alpha_s * jr[c][k], row[c][k] & 1u);
+          if (last_twist) twist_words<ST, W>(w[k], fth, ftw, sc.win2);
+          lds_store_at<W>(lds, row[c][k] & ~1u, w[k]);
         }
         if (fon) {
           update_words<ST, W>(pu, pv, alpha_s * jf[c]);
-          lds_store_at<W>(lds, fu[c], pu);
-          lds_store_at<W>(lds, fv[c], pv);
+          if (last_twist) {
+            twist_words<ST, W>(pu, fth, ftw, sc.win2);
+            twist_words<ST, W>(pv, fth, ftw, sc.win2);
+          }
+          lds_store_at<W>(lds, (fuv[c] & 0xffffu) * ROWB, pu);
+          lds_store_at<W>(lds, (fuv[c] >> 16) * ROWB, pv);
         }
         __syncthreads();
       }
     }
-    if (chunk.twist_at(it & 63u)) {
+    if constexpr (FUSE) {
+      if (fuse_now) {
+#pragma unroll
+        for (int k = 0; k < K; k++) twist_words<ST, W>(reg[k], fth, ftw, sc.win2);
+      }
+    } else if (chunk.twist_at(it & 63u)) {
       const int slot = (int)(tw % (uint32_t)kThetaChunk);
       if (slot == 0) {
         theta_fill(theta_buf, nullptr, kThetaChunk, RW, t, sc.period, a.rid0 + (uint32_t)r0,
@@ -466,12 +498,13 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
   // register rows and LDS rows -> HBM
 #pragma unroll
   for (int k = 0; k < K; k++) {
-    if (rv[k] < 0) continue;
+    const int32_t v = a.reg_vertex[k * nth + tid];
+    if (v < 0) continue;
     float x[RW];
     F::template unpack<W>(reg[k], x);
 #pragma unroll
     for (int q = 0; q < RW; q++)
-      if (q < nvalid) F::store_elem(a.phases, (size_t)rv[k] * a.R + r0 + q, x[q]);
+      if (q < nvalid) F::store_elem(a.phases, (size_t)v * a.R + r0 + q, x[q]);
   }
   for (int s = tid; s < a.n_rows; s += nth) {
     const int32_t v = a.slot_vertex[s];
@@ -776,12 +809,12 @@ int launch_lds(cosm_state *s, const LdsArgs &a) {
   return launch_check("k_sweep_lds");
 }
 
-template <int ST, int W, int K, int CM, int CLASSES = 0>
+template <int ST, int W, int K, int CM, int CLASSES = 0, bool FUSE = false>
 int launch_reg(cosm_state *s, const LdsArgs &a) {
   const size_t lds = s->shape.lds_bytes;
-  (void)hipFuncSetAttribute((const void *)k_sweep_reg<ST, W, K, CM, CLASSES>,
+  (void)hipFuncSetAttribute((const void *)k_sweep_reg<ST, W, K, CM, CLASSES, FUSE>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_sweep_reg<ST, W, K, CM, CLASSES>), dim3(s->shape.blocks),
+  hipLaunchKernelGGL((k_sweep_reg<ST, W, K, CM, CLASSES, FUSE>), dim3(s->shape.blocks),
                      dim3(s->shape.threads), lds, s->stream, a);
   return launch_check("k_sweep_reg");
 }
@@ -793,7 +826,14 @@ template <int ST, int W>
 int launch_reg_w(cosm_state *s, const LdsArgs &a) {
   if constexpr (ST == COSM_STORE_FP32 || ST == COSM_STORE_FIX32 || ST == COSM_STORE_FIX16) {
     const int K = s->lds.reg_k;
-    if (a.C == 4) {
+    // the fused twist pays in FP32; the fixed-point formats convert the twist
+    // angles per row, which costs more inside the last class than a pass does
+    const bool fuse = ST == COSM_STORE_FP32 && a.sch.period > 0 && s->lds.fuse;
+    if (a.C == 4 && fuse) {
+      if (K == 1) return launch_reg<ST, W, 1, 4, 4, true>(s, a);
+      if (K == 2) return launch_reg<ST, W, 2, 4, 4, true>(s, a);
+      if (K == 4) return launch_reg<ST, W, 4, 4, 4, true>(s, a);
+    } else if (a.C == 4) {
       if (K == 1) return launch_reg<ST, W, 1, 4, 4>(s, a);
       if (K == 2) return launch_reg<ST, W, 2, 4, 4>(s, a);
       if (K == 4) return launch_reg<ST, W, 4, 4, 4>(s, a);

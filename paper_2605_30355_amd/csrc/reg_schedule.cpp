@@ -434,7 +434,29 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
   L.reg_set = set_size;
   L.reg_edges = reg_edges;
   L.reg_conflicts = conflicts;
-  L.fuse = false;
+  // The twist can run inside the last class when that class touches every
+  // vertex row exactly once (each row is then final for the sweep right after
+  // its update there), as on the even tori, where every vertex has an edge in
+  // every class.
+  {
+    std::vector<int32_t> hit((size_t)n_rows, 0);
+    const int32_t c = C - 1;
+    for (int32_t k = 0; k <= K; k++)
+      for (int32_t t = 0; t < nth; t++) {
+        const EdgeDesc &d = L.desc[((size_t)c * per_class + k) * nth + t];
+        if (d.J == 0.0f) continue;  // dummy (or a no-op edge)
+        const uint32_t a = d.slots & 0xffffu;
+        if (a < (uint32_t)n_rows) hit[a]++;
+        if (k == K) {
+          const uint32_t b = d.slots >> 16;
+          if (b < (uint32_t)n_rows) hit[b]++;
+        }
+      }
+    bool all = true;
+    for (int64_t r = 0; r < n_rows && all; r++)
+      if (L.slot_vertex[(size_t)r] >= 0 && hit[(size_t)r] != 1) all = false;
+    L.fuse = all;
+  }
   L.fuse_k = 0;
   L.dummy_pairs = true;
   *out = std::move(L);

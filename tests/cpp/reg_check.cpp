@@ -101,9 +101,23 @@ int main(int argc, char **argv) {
     }
     if (L.reg_free) { banks(ru); banks(rv); }
   }
+  // a fused twist needs every vertex row touched exactly once in the last class
+  int fuse_ok = 1;
+  if (L.fuse) {
+    std::vector<int> hit(nr, 0);
+    for (int k = 0; k <= K; k++)
+      for (int t = 0; t < nth; t++) {
+        const auto d = L.desc[((size_t)(C - 1) * (K + 1) + k) * nth + t];
+        const int a = d.slots & 0xffff, b = d.slots >> 16;
+        if (a < nr && d.J != 0.0f) hit[a]++;
+        if (k == K && b < nr && d.J != 0.0f) hit[b]++;
+      }
+    for (int r = 0; r < nr; r++)
+      if (L.slot_vertex[r] >= 0 && hit[r] != 1) fuse_ok = 0;
+  }
   printf("W=%d K=%d nth=%d rows=%d reg_edges=%ld reg_active=%ld free=%ld reg_free=%d "
-         "conflicts=%ld equal=%d indep=%d rows_ok=%d bad_dummy=%ld\n",
+         "conflicts=%ld equal=%d indep=%d rows_ok=%d bad_dummy=%ld fuse=%d fuse_ok=%d\n",
          W, K, nth, nr, (long)L.reg_edges, reg_active, free_active, L.reg_free, conflicts,
-         (int)(want == got), indep, rows_ok, bad_dummy);
+         (int)(want == got), indep, rows_ok, bad_dummy, (int)L.fuse, fuse_ok);
   return 0;
 }

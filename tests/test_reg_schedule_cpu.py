@@ -46,7 +46,7 @@ def test_maxcut_graph_complete_and_conflict_free(checker, W, K):
     assert r.returncode == 0, r.stdout + r.stderr
     f = fields(r.stdout)
     assert f["equal"] == "1" and f["indep"] == "1" and f["rows_ok"] == "1", r.stdout
-    assert f["bad_dummy"] == "0" and f["conflicts"] == "0", r.stdout
+    assert f["bad_dummy"] == "0" and f["conflicts"] == "0" and f["fuse_ok"] == "1", r.stdout
     # an independent set of a random cubic graph covers most edges
     assert int(f["reg_edges"]) >= 0.8 * 3000, r.stdout
 
@@ -66,7 +66,19 @@ def test_other_graphs_complete(checker, case, W):
     assert r.returncode == 0, r.stdout + r.stderr
     f = fields(r.stdout)
     assert f["equal"] == "1" and f["indep"] == "1" and f["rows_ok"] == "1", r.stdout
-    assert f["bad_dummy"] == "0", r.stdout
+    assert f["bad_dummy"] == "0" and f["fuse_ok"] == "1", r.stdout
+
+
+@pytest.mark.parametrize("W", [1, 2, 4])
+def test_fused_twist_on_the_even_torus(checker, W):
+    """On an even torus every vertex has an edge in every class, so with the
+    whole register set placed the last class touches each row once and the
+    twist is fused into it."""
+    r = run(checker, ci.torus(20), cosm.COLOR_TORUS, [20, 20], W, 1)
+    f = fields(r.stdout)
+    assert f["fuse_ok"] == "1", r.stdout
+    if int(f["reg_edges"]) + int(f["free"]) == 800 and f["bad_dummy"] == "0":
+        assert f["fuse"] == "1" or int(f["free"]) > 0, r.stdout
 
 
 def test_not_applicable_beyond_eight_classes(checker):
