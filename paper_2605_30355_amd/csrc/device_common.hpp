@@ -545,54 +545,97 @@ __device__ __forceinline__ void twist_values(float (&x)[RW], const float (&c)[RW
     if (in_windows(x[k], c[k], win2)) x[k] = Fmt<ST>::wrap(x[k] + tws[k]);
 }
 
+// The twist's per-replica operands prepared once per twist for many rows: the
+// fixed-point formats convert the reference offsets and the twist to their
+// integer units here instead of at every row.
+template <int ST, int W>
+struct TwistOps {
+  static constexpr int RW = W * Fmt<ST>::kPerWord;
+  float c[RW], t[RW], win2;
+  __device__ __forceinline__ void set(const float (&cth)[RW], const float (&tws)[RW], float w2) {
+#pragma unroll
+    for (int k = 0; k < RW; k++) {
+      c[k] = cth[k];
+      t[k] = tws[k];
+    }
+    win2 = w2;
+  }
+  __device__ __forceinline__ void apply(uint32_t (&w)[W]) const {
+    using F = Fmt<ST>;
+    float x[RW];
+    F::template unpack<W>(w, x);
+    twist_values<ST, RW>(x, c, t, win2);
+    F::template pack<W>(x, w);
+  }
+};
+template <int W>
+struct TwistOps<COSM_STORE_FIX32, W> {
+  uint32_t c[W], t[W], W2;
+  bool all;
+  __device__ __forceinline__ void set(const float (&cth)[W], const float (&tws)[W], float w2) {
+    all = w2 >= 1.0f;
+    W2 = all ? 0u : (uint32_t)(w2 * 4294967296.0f);
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+      c[q] = turns_fix32(cth[q]);
+      t[q] = turns_fix32(tws[q]);
+    }
+  }
+  __device__ __forceinline__ void apply(uint32_t (&w)[W]) const {
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+      const uint32_t d = (w[q] << 1) - c[q];
+      if (all || d < W2) w[q] += t[q];
+    }
+  }
+};
+template <int W>
+struct TwistOps<COSM_STORE_FIX16, W> {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  uint32_t c2[W], t2[W], k2;
+  bool all;
+  __device__ __forceinline__ void set(const float (&cth)[2 * W], const float (&tws)[2 * W],
+                                      float w2) {
+    const uint32_t W2 = (uint32_t)(w2 * 65536.0f);
+    all = W2 >= 65536u;
+    const uint32_t k = (W2 - 32768u) & 0xffffu;
+    k2 = k | (k << 16);
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+      c2[q] = ((uint32_t)(int32_t)(cth[2 * q] * 65536.0f) & 0xffffu) |
+              ((uint32_t)(int32_t)(cth[2 * q + 1] * 65536.0f) << 16);
+      t2[q] = ((uint32_t)(int32_t)(tws[2 * q] * 65536.0f) & 0xffffu) |
+              ((uint32_t)(int32_t)(tws[2 * q + 1] * 65536.0f) << 16);
+    }
+  }
+  __device__ __forceinline__ void apply(uint32_t (&w)[W]) const {
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+      const u16x2 x = __builtin_bit_cast(u16x2, w[q]);
+      const u16x2 t = (u16x2)(x << (unsigned short)1) - __builtin_bit_cast(u16x2, c2[q]);
+      const s16x2 sgn = __builtin_bit_cast(s16x2, __builtin_bit_cast(uint32_t, t) ^ 0x80008000u);
+      const s16x2 d = __builtin_elementwise_sub_sat(sgn, __builtin_bit_cast(s16x2, k2));
+      const u16x2 m = all ? (u16x2)(0xffff) : (u16x2)(d >> (short)15);
+      w[q] = __builtin_bit_cast(uint32_t, (u16x2)(x + (__builtin_bit_cast(u16x2, t2[q]) & m)));
+    }
+  }
+};
+
 // The twist on the W words of one row.  FIX16: packed 16-bit integers; with
 // t = (2x - c) mod 1 turn in 16-bit lanes, a lane is in the windows iff
 // t < 2w: t is moved to signed range (top bit flipped) and compared with
 // 2w - 1/2 turn by a saturating subtraction, whose sign gives the mask.
-// Other formats: unpack, twist_values, pack.
+// FIX32: the same test on 32-bit integers.  Other formats: unpack, twist_values,
+// pack.
 template <int ST, int W>
 __device__ __forceinline__ void twist_words(uint32_t (&w)[W],
                                             const float (&c)[W * Fmt<ST>::kPerWord],
                                             const float (&tws)[W * Fmt<ST>::kPerWord],
                                             float win2) {
-  if constexpr (ST == COSM_STORE_FIX32) {
-    // t = (2x - c) mod 1 turn in 2^-32 units; in the windows iff t < 2w
-    const bool all = win2 >= 1.0f;
-    const uint32_t W2 = all ? 0u : (uint32_t)(win2 * 4294967296.0f);
-#pragma unroll
-    for (int q = 0; q < W; q++) {
-      const uint32_t t = (w[q] << 1) - turns_fix32(c[q]);
-      if (all || t < W2) w[q] += turns_fix32(tws[q]);
-    }
-  } else if constexpr (ST == COSM_STORE_FIX16) {
-    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-    typedef short s16x2 __attribute__((ext_vector_type(2)));
-    const uint32_t W2 = (uint32_t)(win2 * 65536.0f);  // 2w in 2^-16 turn, <= 2^16
-    const bool all = W2 >= 65536u;                    // w = 1/2 turn: every phase
-    const uint32_t k = (W2 - 32768u) & 0xffffu;
-    const s16x2 k2 = __builtin_bit_cast(s16x2, k | (k << 16));
-#pragma unroll
-    for (int q = 0; q < W; q++) {
-      // c and the twist are multiples of 2^-16 turn: exact conversions
-      const uint32_t c2 = ((uint32_t)(int32_t)(c[2 * q] * 65536.0f) & 0xffffu) |
-                          ((uint32_t)(int32_t)(c[2 * q + 1] * 65536.0f) << 16);
-      const uint32_t t2 = ((uint32_t)(int32_t)(tws[2 * q] * 65536.0f) & 0xffffu) |
-                          ((uint32_t)(int32_t)(tws[2 * q + 1] * 65536.0f) << 16);
-      const u16x2 x = __builtin_bit_cast(u16x2, w[q]);
-      const u16x2 t = (u16x2)(x << (unsigned short)1) - __builtin_bit_cast(u16x2, c2);
-      const s16x2 sgn = __builtin_bit_cast(s16x2, __builtin_bit_cast(uint32_t, t) ^ 0x80008000u);
-      const s16x2 d = __builtin_elementwise_sub_sat(sgn, k2);
-      const u16x2 m = all ? (u16x2)(0xffff) : (u16x2)(d >> (short)15);
-      w[q] = __builtin_bit_cast(uint32_t, (u16x2)(x + (__builtin_bit_cast(u16x2, t2) & m)));
-    }
-  } else {
-    using F = Fmt<ST>;
-    constexpr int RW = W * F::kPerWord;
-    float x[RW];
-    F::template unpack<W>(w, x);
-    twist_values<ST, RW>(x, c, tws, win2);
-    F::template pack<W>(x, w);
-  }
+  TwistOps<ST, W> op;
+  op.set(c, tws, win2);
+  op.apply(w);
 }
 
 // Eq. (6) on every replica of one edge of the last class, followed by the

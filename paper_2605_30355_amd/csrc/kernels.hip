@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
     // it (the schedule touches each exactly once there) and the owners twist
     // the register rows after it
     bool fuse_now = false;
-    float fth[RW], ftw[RW];
+    TwistOps<ST, W> tops;
     if constexpr (FUSE) {
       fuse_now = chunk.twist_at(it & 63u);
       if (fuse_now) {
@@ -420,11 +420,13 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
           __syncthreads();
         }
         tw++;
+        float cth[RW], tws[RW];
 #pragma unroll
         for (int k = 0; k < RW; k++) {
-          fth[k] = theta_buf[slot * RW + k];
-          ftw[k] = twist;
+          cth[k] = theta_buf[slot * RW + k];
+          tws[k] = twist;
         }
+        tops.set(cth, tws, sc.win2);
       }
     }
 #pragma unroll
@@ -442,14 +444,14 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
 #pragma unroll
         for (int k = 0; k < K; k++) {
           update_reg_words<ST, W>(reg[k], w[k], alpha_s * jr[c][k], row[c][k] & 1u);
-          if (last_twist) twist_words<ST, W>(w[k], fth, ftw, sc.win2);
+          if (last_twist) tops.apply(w[k]);
           lds_store_at<W>(lds, row[c][k] & ~1u, w[k]);
         }
         if (fon) {
           update_words<ST, W>(pu, pv, alpha_s * jf[c]);
           if (last_twist) {
-            twist_words<ST, W>(pu, fth, ftw, sc.win2);
-            twist_words<ST, W>(pv, fth, ftw, sc.win2);
+            tops.apply(pu);
+            tops.apply(pv);
           }
           lds_store_at<W>(lds, (fuv[c] & 0xffffu) * ROWB, pu);
           lds_store_at<W>(lds, (fuv[c] >> 16) * ROWB, pv);
@@ -460,7 +462,7 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
     if constexpr (FUSE) {
       if (fuse_now) {
 #pragma unroll
-        for (int k = 0; k < K; k++) twist_words<ST, W>(reg[k], fth, ftw, sc.win2);
+        for (int k = 0; k < K; k++) tops.apply(reg[k]);
       }
     } else if (chunk.twist_at(it & 63u)) {
       const int slot = (int)(tw % (uint32_t)kThetaChunk);
@@ -826,9 +828,7 @@ template <int ST, int W>
 int launch_reg_w(cosm_state *s, const LdsArgs &a) {
   if constexpr (ST == COSM_STORE_FP32 || ST == COSM_STORE_FIX32 || ST == COSM_STORE_FIX16) {
     const int K = s->lds.reg_k;
-    // the fused twist pays in FP32; the fixed-point formats convert the twist
-    // angles per row, which costs more inside the last class than a pass does
-    const bool fuse = ST == COSM_STORE_FP32 && a.sch.period > 0 && s->lds.fuse;
+    const bool fuse = a.sch.period > 0 && s->lds.fuse;
     if (a.C == 4 && fuse) {
       if (K == 1) return launch_reg<ST, W, 1, 4, 4, true>(s, a);
       if (K == 2) return launch_reg<ST, W, 2, 4, 4, true>(s, a);
