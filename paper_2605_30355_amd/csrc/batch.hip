@@ -159,6 +159,8 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
           ck[r] = cth[r];
           tws[r] = twist;
         }
+        TwistOps<ST, W> op;
+        op.set(ck, tws, sc.win2);
         uint32_t *set = lds + (size_t)k * g.n * W;
         for (int s0 = tid; s0 < g.n; s0 += 2 * nth) {
           uint32_t w[2][W];
@@ -168,7 +170,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
 #pragma unroll
           for (int q = 0; q < 2; q++) {
             if (s0 + q * nth < g.n) {
-              twist_words<ST, W>(w[q], ck, tws, sc.win2);
+              op.apply(w[q]);
               lds_store<W>(set, s0 + q * nth, w[q]);
             }
           }

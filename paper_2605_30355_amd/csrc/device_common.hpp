@@ -644,27 +644,23 @@ __device__ __forceinline__ void twist_words(uint32_t (&w)[W],
 // sees the stored (rounded) phases, as a pass of its own would.
 template <int ST, int W>
 __device__ __forceinline__ void edge_rows_twist(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ,
-                                                const float (&c)[W * Fmt<ST>::kPerWord],
-                                                const float (&tws)[W * Fmt<ST>::kPerWord],
-                                                float win2) {
+                                                const TwistOps<ST, W> &op) {
   uint32_t wu[W], wv[W];
   lds_load_at<W>(lds, bu, wu);
   lds_load_at<W>(lds, bv, wv);
   update_words<ST, W>(wu, wv, aJ);
-  twist_words<ST, W>(wu, c, tws, win2);
-  twist_words<ST, W>(wv, c, tws, win2);
+  op.apply(wu);
+  op.apply(wv);
   lds_store_at<W>(lds, bu, wu);
   lds_store_at<W>(lds, bv, wv);
 }
 
 // The twist of one row that no edge of the last class touches.
 template <int ST, int W>
-__device__ __forceinline__ void row_twist(uint32_t *lds, uint32_t b,
-                                          const float (&c)[W * Fmt<ST>::kPerWord],
-                                          const float (&tws)[W * Fmt<ST>::kPerWord], float win2) {
+__device__ __forceinline__ void row_twist(uint32_t *lds, uint32_t b, const TwistOps<ST, W> &op) {
   uint32_t w[W];
   lds_load_at<W>(lds, b, w);
-  twist_words<ST, W>(w, c, tws, win2);
+  op.apply(w);
   lds_store_at<W>(lds, b, w);
 }
 

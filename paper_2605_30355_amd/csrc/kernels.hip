@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       // EMAX slots, one class each.  On a twist sweep the last class twists
       // the rows it updates and, concurrently, the rows it leaves out.
       const bool fuse_now = chunk.twist_at(it & 63u);
-      float cth[RW], tws[RW];
+      TwistOps<ST, W> op;
       if (fuse_now) {
         const int slot = (int)(tw % (uint32_t)kThetaChunk);
         tw++;
@@ -170,11 +170,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
                      a.k0, a.k1, sc.win, sc.tshift, sc.tscale);
           __syncthreads();
         }
+        float cth[RW], tws[RW];
 #pragma unroll
         for (int k = 0; k < RW; k++) {
           cth[k] = theta_buf[slot * RW + k];
           tws[k] = twist;
         }
+        op.set(cth, tws, sc.win2);
       }
 #pragma unroll
       for (int j = 0; j < EMAX - 1; j++) {
@@ -182,11 +184,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         __syncthreads();
       }
       if (fuse_now) {
-        edge_rows_twist<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1], cth, tws,
-                               sc.win2);
+        edge_rows_twist<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1], op);
 #pragma unroll
         for (int q = 0; q < kFuseRowsMax; q++)
-          if (q < a.fuse_k && fr[q] != kEmptySlot) row_twist<ST, W>(lds, fr[q], cth, tws, sc.win2);
+          if (q < a.fuse_k && fr[q] != kEmptySlot) row_twist<ST, W>(lds, fr[q], op);
       } else {
         edge_rows<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1]);
       }
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         // streamed form: on a twist sweep the last class twists the rows it
         // updates, then each thread twists its fuse_k rows outside that class
         const bool fuse_now = chunk.twist_at(it & 63u);
-        float cth[RW], tws[RW];
+        TwistOps<ST, W> op;
         if (fuse_now) {
           const int slot = (int)(tw % (uint32_t)kThetaChunk);
           tw++;
@@ -223,11 +224,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
                        a.k0, a.k1, sc.win, sc.tshift, sc.tscale);
             __syncthreads();
           }
+          float cth[RW], tws[RW];
 #pragma unroll
           for (int k = 0; k < RW; k++) {
             cth[k] = theta_buf[slot * RW + k];
             tws[k] = twist;
           }
+          op.set(cth, tws, sc.win2);
         }
         const gptr<EdgeDesc> rest =
             as_global(a.desc) + (size_t)(a.total_slots + kStreamRepeat) * nth + tid;
@@ -235,12 +238,12 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
             a.desc, Ks, a.C, a.total_slots, dA, dB, jslot, edge,
             [&](const EdgeDesc &d) {
               edge_rows_twist<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
-                                     alpha_s * d.J, cth, tws, sc.win2);
+                                     alpha_s * d.J, op);
             },
             [&] {
               for (int q = 0; q < a.fuse_k; q++) {
                 const uint32_t row = rest[(size_t)q * nth].slots;
-                if (row != kEmptySlot) row_twist<ST, W>(lds, row * ROWB, cth, tws, sc.win2);
+                if (row != kEmptySlot) row_twist<ST, W>(lds, row * ROWB, op);
               }
             },
             fuse_now);
@@ -294,6 +297,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         cth[k] = theta_buf[slot * RW + k];
         tws[k] = a.h_slot != nullptr ? dir_buf[slot * RW + k] * twist : twist;
       }
+      TwistOps<ST, W> op;
+      op.set(cth, tws, sc.win2);
       // four rows per thread in flight: all loads, then the updates and stores
       for (int s0 = tid; s0 < a.n_rows; s0 += 4 * nth) {
         uint32_t w[4][W];
@@ -303,7 +308,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           if (s0 + q * nth < a.n_rows) {
-            twist_words<ST, W>(w[q], cth, tws, sc.win2);
+            op.apply(w[q]);
             lds_store<W>(lds, s0 + q * nth, w[q]);
           }
         }
@@ -478,8 +483,10 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
         cth[k] = theta_buf[slot * RW + k];
         tws[k] = twist;
       }
+      TwistOps<ST, W> op;
+      op.set(cth, tws, sc.win2);
 #pragma unroll
-      for (int k = 0; k < K; k++) twist_words<ST, W>(reg[k], cth, tws, sc.win2);
+      for (int k = 0; k < K; k++) op.apply(reg[k]);
       for (int s0 = tid; s0 < a.n_rows; s0 += 4 * nth) {
         uint32_t w[4][W];
 #pragma unroll
@@ -488,7 +495,7 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           if (s0 + q * nth < a.n_rows) {
-            twist_words<ST, W>(w[q], cth, tws, sc.win2);
+            op.apply(w[q]);
             lds_store<W>(lds, s0 + q * nth, w[q]);
           }
         }
