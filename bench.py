@@ -36,7 +36,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-ops per second, non-packed FP32
 # reads for a 256 MiB device copy (FETCH_SIZE 131087 KiB -> x2.0; WRITE_SIZE
 # 262144 KiB -> x1.0).  Valid only for the kernel sources they were taken on.
 TRAFFIC = dict(fetch_kib=4193.0, write_kib=8000.0, fetch_factor=2.0, write_factor=1.0,
-               sources_sha256="5a756f80dadb8678a2d7b5f72dbd3c098a6ec9e3776fcb1b7f7bd671df4a0d03")
+               sources_sha256="fa5a7fee85f7346897f4820200ea0c0982bd7d69ef7ddd01d8f8ab30d877320e")
 TRAFFIC_SOURCES = ("paper_2605_30355_amd/csrc/kernels.hip",
                    "paper_2605_30355_amd/csrc/device_common.hpp")
 
