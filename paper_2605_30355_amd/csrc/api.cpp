@@ -148,6 +148,11 @@ int make_schedule(const cosm_params &p, int32_t max_abs_J, Schedule *sc) {
   sc->iscale = sc->grid ? (float)std::ldexp(1.0, -bits) : (float)std::ldexp(1.0, -24);
   sc->S = p.sweeps_per_trial;
   sc->a0_units = (int64_t)std::floor(p.alpha0_deg / 360.0 * step_per_turn + 0.5);
+  // FIX32: the largest step, alpha0 rounded to the step grid times |J|, in
+  // units of 2^-32 turn (2^10 per step unit) must stay a positive int32, so
+  // the bound is checked after the rounding
+  if (p.storage == COSM_STORE_FIX32 && sc->a0_units * (int64_t)max_abs_J >= ((int64_t)1 << 21))
+    return set_error(COSM_ERANGE, "FIX32 needs alpha0 * |J| (on the step grid) below half a turn");
   const double r2 = 2.0 * p.dwt_ratio;
   sc->twist_num2 = (int32_t)std::llround(r2);
   // the window on the step grid keeps the twist's membership test exact

@@ -7,7 +7,8 @@
 // Each candidate runs a short timed probe on the state's own phases (which are
 // re-drawn afterwards, so the probe leaves no trace in the trajectory), and the
 // fastest shape is kept.  Results are cached per process, keyed by the
-// instance's size signature.  None of the candidates changes the dynamics: they
+// instance's signature (sizes, storage, layout request, bias fields and a hash
+// of the edge list and colouring).  None of the candidates changes the dynamics: they
 // differ only in how the same class-by-class updates are laid out on the GPU.
 #include <algorithm>
 #include <cstdlib>
@@ -21,24 +22,25 @@ namespace cosm {
 
 namespace {
 
-using Key = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t, int32_t, int64_t, int32_t>;
+// Instance signature: sizes, storage, layout request, bias fields, and an
+// FNV-1a hash of the edge list and its colouring (the schedules are built from
+// exactly these, so two instances with the same key accept the same shapes).
+using Key = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t, uint64_t>;
 using Shape = std::tuple<int32_t, int32_t, int32_t>;  // (W, threads, register rows or 0)
 std::mutex g_cache_mu;
 std::map<Key, Shape> g_cache;
 
 Key make_key(const cosm_state &s) {
-  int64_t h = 1469598103934665603LL;  // FNV-1a over the class sizes
-  for (int32_t c : s.class_sizes) h = (h ^ c) * 1099511628211LL;
-  int32_t delta = 0;
-  {
-    std::vector<int32_t> deg((size_t)s.n, 0);
-    for (int64_t k = 0; k < s.m; k++) {
-      deg[(size_t)s.h_eu[(size_t)k]]++;
-      deg[(size_t)s.h_ev[(size_t)k]]++;
-    }
-    for (int32_t d : deg) delta = std::max(delta, d);
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](uint32_t v) {
+    for (int b = 0; b < 4; b++) h = (h ^ ((v >> (8 * b)) & 0xffu)) * 1099511628211ull;
+  };
+  for (int64_t k = 0; k < s.m; k++) {
+    mix((uint32_t)s.h_eu[(size_t)k]);
+    mix((uint32_t)s.h_ev[(size_t)k]);
+    mix((uint32_t)s.h_colour[(size_t)k]);
   }
-  return Key{s.n, s.m, s.C, delta, s.R, s.p.storage, h, s.p.lds_form};
+  return Key{s.n, s.m, s.C, s.R, s.p.storage, s.p.lds_form, s.has_h ? 1 : 0, h};
 }
 
 int upload_schedule(cosm_state *s) {
@@ -131,9 +133,14 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find(key);
-    if (it != g_cache.end())
-      return apply_shape(s, std::get<0>(it->second), std::get<1>(it->second), pw,
-                         std::get<2>(it->second));
+    if (it != g_cache.end()) {
+      if (apply_shape(s, std::get<0>(it->second), std::get<1>(it->second), pw,
+                      std::get<2>(it->second)) == COSM_OK)
+        return COSM_OK;
+      // the cached shape does not apply to this instance: measure afresh
+      clear_error();
+      g_cache.erase(it);
+    }
   }
   const int64_t probe = std::min<int64_t>(256, s->p.sweeps_per_trial);
   hipEvent_t e0, e1;

@@ -176,3 +176,32 @@ def test_params_validation_on_host():
     assert status(lds_form=3)[0] == -1
     # FIX32 phases take 4 bytes per replica-vertex, FIX16 2
     assert status(storage=cosm.STORE_FIX32)[1] > status(storage=cosm.STORE_FIX16)[1]
+
+
+def test_fix32_step_bound_checked_after_rounding():
+    """FIX32 takes alpha0 * |J| in 2^-32 turn units as a signed 32-bit step:
+    alpha0 just below 180 degrees rounds to half a turn on the 2^-22 turn step
+    grid and is rejected (ERANGE) before any device work; slightly smaller
+    values pass the check (they fail later only for want of a device)."""
+    import ctypes
+    lib = cosm.load_library()
+    inst = ci.torus(4, seed=1)
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [4, 4])
+
+    from paper_2605_30355_amd.cosm import _ptr
+    eu, ev, J, col = (np.ascontiguousarray(a, dtype=np.int32)
+                      for a in (inst.eu, inst.ev, inst.J, colour))
+
+    def init_status(alpha0, storage):
+        p = cosm.Params(alpha0_deg=alpha0, storage=storage)._c()
+        st = ctypes.c_void_p(None)
+        rc = lib.cosm_init(ctypes.byref(st), inst.n, inst.m, _ptr(eu), _ptr(ev), _ptr(J), None,
+                           _ptr(col), C, ctypes.byref(p), 1, 4, None, None, 0)
+        if rc == 0:
+            lib.cosm_destroy(st)
+        return rc
+
+    assert init_status(180.0 - 2e-5, cosm.STORE_FIX32) == -4
+    assert init_status(179.9, cosm.STORE_FIX32) != -4
+    # FP32 storage has no such bound below a full turn
+    assert init_status(180.0 - 2e-5, cosm.STORE_FP32) != -4
