@@ -1,15 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the Cosm sweep on one MI355X.
 
-A step is one whole trial batch of the hot path on the Max-Cut workload (random
-3-regular graph, N = 2000, 3000 edges, +1 weights, Misra-Gries colouring in 4
-classes of equal size, 1024 replicas, 10^4 sweeps): phase init, 10^4 sweeps (SCS sub-sweeps,
-twist, schedule) and the bisector readout with int64 energies.
+A step is one whole trial batch of the hot path on the largest single-GPU
+workload: the 141 x 141 +-1 toroidal spin glass (N = 19881, 39762 edges, the
+torus colouring's 6 classes, 4096 replicas, FP32 phases, grid schedule, 10^4
+sweeps): phase init, the sweeps (SCS sub-sweeps, twist, schedule) and the
+bisector readout with int64 energies.
 
 Prints one JSON line: edge-updates/s of the batched LDS-resident form (value),
-the plain one-replica-per-launch form, replica-sweeps/s, time-to-target at 99%
-for the batched, plain and 16-bit-storage forms, the roofline of the sweep
-kernel, and the CPU oracle timed on the host as a baseline.
+replica-sweeps/s, the roofline of the sweep kernel, and the CPU oracle timed on
+the host on a bounded sample of the same workload.  Extra keys: the Max-Cut
+workload (random 3-regular, N = 2000, 1024 replicas, 10^4 sweeps) with the
+plain one-replica-per-launch form and time-to-target at 99% for the batched,
+plain and reduced-precision forms; the other large graphs' sweep rates.
 """
 from __future__ import annotations
 
@@ -59,9 +62,35 @@ def traffic_bytes():
                          + TRAFFIC["write_kib"] * TRAFFIC["write_factor"]))
 
 
+# The timed workload: the 141 x 141 +-1 torus (the size of the paper's largest
+# toroidal instance, with an odd side, so the torus colouring has 6 classes),
+# 4096 replicas, FP32 phases, in the kernel shape given here (2 replicas and
+# 1024 threads per workgroup: one workgroup fills a CU's LDS).
+HEADLINE = dict(name="torus141-pm1", L=141, seed=4, weights="pm1", replicas=4096, sweeps=10000,
+                alpha0_deg=14.0, dwt_ratio=0.5, dwt_period=3, window_deg=90.0, bisectors=100,
+                colouring=2, sides=[141, 141], replicas_per_wg=2, threads_per_wg=1024)
+
+# The Max-Cut workload of the time-to-target legs.
 WORKLOAD = dict(name="maxcut-3reg-n2000", n=2000, degree=3, seed=2, weights="maxcut1",
                 replicas=1024, sweeps=10000, alpha0_deg=14.0, dwt_ratio=1.0, dwt_period=6,
                 window_deg=90.0, bisectors=100)
+
+
+def headline_instance():
+    import cosm_inputs as ci
+    return ci.torus(HEADLINE["L"], seed=HEADLINE["seed"], weights=HEADLINE["weights"])
+
+
+def headline_params(cosm, **over):
+    h = HEADLINE
+    p = cosm.Params(alpha0_deg=h["alpha0_deg"], dwt_ratio=h["dwt_ratio"],
+                    dwt_period=h["dwt_period"], dwt_window_deg=h["window_deg"],
+                    n_bisectors=h["bisectors"], sweeps_per_trial=h["sweeps"],
+                    replicas_per_wg=h["replicas_per_wg"], threads_per_wg=h["threads_per_wg"],
+                    residency=cosm.RES_LDS)
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
 
 
 def log(*a):
@@ -92,38 +121,55 @@ def load_target():
         return None
 
 
-def cpu_baseline(inst, colour, C, seconds_goal=10.0):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+def cpu_model():
+    """The host CPU's model name (as lscpu prints it), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(inst, colour, C, work, seconds_goal=12.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload
+    `work`: whole trials (init, all sweeps, readout) of as many replicas as fit
+    in about seconds_goal, one replica per thread at a time; then one replica
+    on one core."""
     import oracle
     threads = len(os.sched_getaffinity(0))
-    op = oracle.Params(alpha0_deg=WORKLOAD["alpha0_deg"], dwt_ratio=WORKLOAD["dwt_ratio"],
-                       dwt_period=WORKLOAD["dwt_period"], dwt_window_deg=WORKLOAD["window_deg"],
-                       n_bisectors=WORKLOAD["bisectors"], sweeps=WORKLOAD["sweeps"])
+    S = work["sweeps"]
+    op = oracle.Params(alpha0_deg=work["alpha0_deg"], dwt_ratio=work["dwt_ratio"],
+                       dwt_period=work["dwt_period"], dwt_window_deg=work["window_deg"],
+                       n_bisectors=work["bisectors"], sweeps=S)
     prob = oracle.Problem(inst.n, inst.eu, inst.ev, inst.J, colour=colour, C=C)
-    # calibrate on one replica per thread for 200 sweeps, then size the sample
+    # calibrate on one replica per thread for 100 sweeps, then size the sample
     x = oracle.init_phases(inst.n, 7, 0, threads)
     t0 = time.perf_counter()
-    oracle.sweeps(prob, op, 7, 0, x, 0, 200, n_threads=threads)
-    rate = threads * 200 * inst.m / (time.perf_counter() - t0)
-    R = max(threads, int(seconds_goal * rate / (inst.m * WORKLOAD["sweeps"])) // threads * threads)
-    x = oracle.init_phases(inst.n, 7, 0, R)
+    oracle.sweeps(prob, op, 7, 0, x, 0, 100, n_threads=threads)
+    rate = threads * 100 * inst.m / (time.perf_counter() - t0)
+    R = max(threads, int(seconds_goal * rate / (inst.m * S)) // threads * threads)
     t0 = time.perf_counter()
-    oracle.sweeps(prob, op, 7, 0, x, 0, WORKLOAD["sweeps"], n_threads=threads)
+    x = oracle.init_phases(inst.n, 7, 0, R)
+    oracle.sweeps(prob, op, 7, 0, x, 0, S, n_threads=threads)
     oracle.readout(prob, op, x)
     dt = time.perf_counter() - t0
     # and one core: one replica, the whole trial
-    x1 = oracle.init_phases(inst.n, 7, 0, 1)
     t1 = time.perf_counter()
-    oracle.sweeps(prob, op, 7, 0, x1, 0, WORKLOAD["sweeps"], n_threads=1)
+    x1 = oracle.init_phases(inst.n, 7, 0, 1)
+    oracle.sweeps(prob, op, 7, 0, x1, 0, S, n_threads=1)
     oracle.readout(prob, op, x1)
     dt1 = time.perf_counter() - t1
-    return {"value": R * WORKLOAD["sweeps"] * inst.m / dt, "unit": "edge-updates/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{R} replicas x {WORKLOAD['sweeps']} sweeps of {WORKLOAD['name']} "
+    return {"value": R * S * inst.m / dt, "unit": "edge-updates/s",
+            "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{R} replicas x {S} sweeps of {work['name']} "
                       f"(init, sweeps, readout), {dt:.1f} s wall",
             "seconds": round(dt, 2),
-            "one_core": {"value": WORKLOAD["sweeps"] * inst.m / dt1, "unit": "edge-updates/s",
-                         "sample": f"1 replica x {WORKLOAD['sweeps']} sweeps, {dt1:.2f} s wall"}}
+            "replica_sweeps_per_s": R * S / dt,
+            "one_core": {"value": S * inst.m / dt1, "unit": "edge-updates/s",
+                         "sample": f"1 replica x {S} sweeps, {dt1:.2f} s wall"}}
 
 
 STREAM = dict(name="mixed-stream-256", requests=256, n_min=400, n_max=20000, seed=5,
@@ -510,36 +556,62 @@ def seeds_bench(count=None, jsonl=None, family="rr5"):
             "target": summary("target"), "relaxed": summary("relaxed"), "instances": recs}
 
 
-def large_bench():
+def lds_bytes(info, inst, R, S, period, storage_bytes):
+    """LDS bytes of S sweeps of R replicas: the algorithmic count (2 reads and
+    2 writes of a phase per edge update, a read and a write of every phase per
+    twist) and the bytes the kernel's layout moves (the register layout reads
+    and writes one LDS row for an edge with an endpoint in registers, and the
+    twist touches only the LDS rows)."""
+    b = storage_bytes
+    twists = S // period if period > 0 else 0
+    algo = R * (S * 4 * b * inst.m + twists * 2 * b * inst.n)
+    if info.get("lds_form") == 2:
+        er, nr = info["register_edges"], info["register_vertices"]
+        moved = R * (S * b * (2 * er + 4 * (inst.m - er)) + twists * 2 * b * (inst.n - nr))
+    else:
+        moved = algo
+    return algo, moved
+
+
+def large_bench(cases_wanted=None, S=None, reps=None):
     """The large-graph configurations: the 100x100 and 141x141 +-1 tori at 4096
     replicas (FP32, FIX32, BF16 and FIX16 storage) and the 5-regular N = 20000 and
     capped Erdos-Renyi N = 10000 graphs at 2048 replicas (FP32, FIX32): edge-updates/s
     of the sweep kernel (HIP events around whole sweep calls after a warm-up),
-    the shape and layout the autotuner kept, and the LDS roofline fraction
-    (16 B, or 8 B for 16-bit storage, per edge update plus the twist's bytes)."""
+    the shape and layout the autotuner kept, and the LDS roofline fraction of the
+    algorithmic bytes (16 B, or 8 B for 16-bit storage, per edge update plus a
+    read and a write of every phase per twist) and of the bytes the layout moves."""
     import torch
 
     import cosm_inputs as ci
     import paper_2605_30355_amd as cosm
 
     torch.cuda.set_device(0)
-    cases = [("torus-100x100", ci.torus(100, seed=3), cosm.COLOR_TORUS, [100, 100], 4096,
+    cases = [("torus-100x100", lambda: ci.torus(100, seed=3), cosm.COLOR_TORUS, [100, 100], 4096,
               dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "bf16", "fix16")),
-             ("torus-141x141", ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141], 4096,
+             ("torus-141x141", lambda: ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141], 4096,
               dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "bf16", "fix16")),
-             ("rr5-n20000", ci.random_regular(20000, 5, seed=1000, weights="pm1"),
+             ("rr5-n20000", lambda: ci.random_regular(20000, 5, seed=1000, weights="pm1"),
               cosm.COLOR_BALANCED, None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32", "fix32")),
-             ("er-n10000", ci.erdos_renyi_capped(10000, 4, 8, seed=3), cosm.COLOR_MISRA_GRIES,
-              None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32", "fix32"))]
+             ("er-n10000", lambda: ci.erdos_renyi_capped(10000, 4, 8, seed=3),
+              cosm.COLOR_MISRA_GRIES, None, 2048, dict(dwt_ratio=1.5, dwt_period=3),
+              ("fp32", "fix32"))]
     storages = {"fp32": cosm.STORE_FP32, "fix32": cosm.STORE_FIX32, "bf16": cosm.STORE_BF16,
                 "fix16": cosm.STORE_FIX16}
-    S, reps = LARGE["sweeps"], LARGE["reps"]
+    S = S or LARGE["sweeps"]
+    reps = reps or LARGE["reps"]
     stream = torch.cuda.current_stream()
     out = {"metric": "edge-updates/s of the sweep on the large-graph configurations, 1 MI355X",
            "sweeps_per_call": S, "calls": reps, "cases": []}
-    for name, inst, meth, sides, R, kw, sts in cases:
+    for name, make_inst, meth, sides, R, kw, sts in cases:
+        want = None if cases_wanted is None else cases_wanted.get(name)
+        if cases_wanted is not None and want is None:
+            continue
+        inst = make_inst()
         colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, meth, sides)
         for st_name in sts:
+            if want is not None and st_name not in want:
+                continue
             p = cosm.Params(sweeps_per_trial=S * (reps + 1), storage=storages[st_name], **kw)
             st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=LARGE["seed"],
                             replicas=R)
@@ -554,19 +626,113 @@ def large_bench():
             info = st.info()
             st.close()
             rate = inst.m * S * R / sec
-            b = 8 if st_name in ("bf16", "fix16") else 16
-            twist_b = b / 2 * inst.n * R * (S / kw["dwt_period"]) / sec  # read + write per twist
-            frac = (rate * b + twist_b) / (LDS_PEAK_GBS * 1e9)
+            b = 2 if st_name in ("bf16", "fix16") else 4
+            algo, moved = lds_bytes(info, inst, R, S, kw["dwt_period"], b)
             form = {cosm.RES_LDS: "lds", cosm.RES_HBM: "hbm"}.get(info["residency"], "plain")
             rec = {"workload": name, "n": inst.n, "m": inst.m, "classes": C, "replicas": R,
                    "storage": st_name, "edge_updates_per_s": round(rate, 1),
                    "replica_sweeps_per_s": round(S * R / sec, 1), "form": form,
                    "layout": {1: "pair", 2: "register"}.get(info["lds_form"], None),
-                   "register_rows": info["register_rows"],
+                   "register_rows": info["register_rows"], "twist_fused": info["twist_fused"],
                    "replicas_per_wg": info["replicas_per_wg"],
-                   "threads_per_wg": info["threads_per_wg"], "lds_roofline_frac": round(frac, 3)}
+                   "threads_per_wg": info["threads_per_wg"],
+                   "lds_roofline_frac": round(algo / sec / (LDS_PEAK_GBS * 1e9), 3),
+                   "lds_moved_frac": round(moved / sec / (LDS_PEAK_GBS * 1e9), 3)}
             out["cases"].append(rec)
             log(f"large {rec}")
+    return out
+
+
+def maxcut_legs(args):
+    """The Max-Cut workload: the batched sweep kernel's rate, the plain
+    one-replica-per-launch form, and time to target at 99 % for the batched
+    FP32, reduced-precision and other forms (cosm_solve_to_target)."""
+    import torch
+
+    import paper_2605_30355_amd as cosm
+
+    inst = make_instance()
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+    R, S, m = WORKLOAD["replicas"], WORKLOAD["sweeps"], inst.m
+    stream = torch.cuda.current_stream()
+    st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, params(cosm), seed=1,
+                    replicas=R)
+    info = st.info()
+    st.sweep(S)  # warm-up
+    st.reset(1, R)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    st.sweep(S)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kernel_s = e0.elapsed_time(e1) * 1e-3
+    batched_rate = m * S * R / kernel_s
+    algo, _ = lds_bytes(info, inst, R, S, WORKLOAD["dwt_period"], 4)
+    out = {"workload": WORKLOAD["name"], "n": inst.n, "edges": m, "classes": C, "replicas": R,
+           "sweeps": S, "colouring": "misra-gries, class sizes equalised",
+           "replicas_per_wg": info["replicas_per_wg"], "threads_per_wg": info["threads_per_wg"],
+           "layout": {1: "pair", 2: "register"}.get(info["lds_form"], None),
+           "sweep_kernel_edge_updates_per_s": round(batched_rate, 1),
+           "sweep_kernel_lds_roofline_frac": round(algo / kernel_s / (LDS_PEAK_GBS * 1e9), 4)}
+    log(f"maxcut batched: {batched_rate:.3e} edge-updates/s, shape {info}")
+
+    # plain form: one replica per launch, one launch per colour class
+    plain_sweeps = 500
+    sp = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C,
+                    params(cosm, residency=cosm.RES_PLAIN), seed=1, replicas=1)
+    sp.sweep(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sp.sweep(plain_sweeps)
+    torch.cuda.synchronize()
+    plain_dt = time.perf_counter() - t0
+    plain_rate = m * plain_sweeps / plain_dt
+    plain_t_trial = plain_dt / plain_sweeps * S
+    sp.close()
+    out["plain_edge_updates_per_s"] = round(plain_rate, 1)
+    out["batched_over_plain"] = round(batched_rate / plain_rate, 1)
+    log(f"plain: {plain_rate:.3e} edge-updates/s, t_trial {plain_t_trial:.3f} s")
+
+    target = load_target()
+    if args.no_ttt or target is None:
+        st.close()
+        return out
+    ttt = {"target_H": target, "target_cut": (int(-inst.J.sum()) - target) // 2}
+    for name, over in (("batched_fp32", {}), ("batched_fp16", {"storage": cosm.STORE_FP16}),
+                       ("batched_bf16", {"storage": cosm.STORE_BF16}),
+                       ("batched_fix16", {"storage": cosm.STORE_FIX16}),
+                       ("batched_fix32", {"storage": cosm.STORE_FIX32}),
+                       ("batched_fp32_register_layout", {"lds_form": cosm.LDS_FORM_REGISTER}),
+                       ("batched_fp32_optimal_readout", {"readout": cosm.READOUT_OPTIMAL}),
+                       ("batched_fp32_minimum_colouring", {"colouring": cosm.COLOR_MINIMUM})):
+        col2, C2 = colour, C
+        if "colouring" in over:  # 3 classes of 1000 instead of 4 of 750
+            col2, C2 = cosm.build_partitions(inst.n, inst.eu, inst.ev, over.pop("colouring"))
+        s2 = st if not over and col2 is colour else cosm.State(
+            inst.n, inst.eu, inst.ev, inst.J, col2, C2, params(cosm, **over), seed=1,
+            replicas=R)
+        res, _ = s2.solve_to_target(target, 8 * R)
+        ttt[name] = {"ps": res.ps, "ps_ci95": [res.ps_lo, res.ps_hi], "trials": res.trials,
+                     "r99": res.r99, "t_trial_s": res.t_trial_s, "ttt_s": res.ttt_s,
+                     "best_H": res.best_H,
+                     # whole trials (init, sweeps, readout) per second, as edge updates
+                     "edge_updates_per_s": round(m * S / res.t_trial_s, 1)}
+        if col2 is not colour:
+            ttt[name]["classes"] = C2
+        if s2 is not st:
+            s2.close()
+        log(f"{name}: {ttt[name]}")
+    ps = ttt["batched_fp32"]["ps"]
+    r99 = ttt["batched_fp32"]["r99"]
+    # the plain form runs the same trajectories (bit-exact), so it shares P_s
+    ttt["plain_fp32"] = {"ps": ps, "r99": r99, "t_trial_s": plain_t_trial,
+                         "ttt_s": plain_t_trial * r99 if math.isfinite(r99) else None}
+    for k, v in ttt.items():
+        if isinstance(v, dict) and v.get("ttt_s") is not None and not math.isfinite(v["ttt_s"]):
+            v["ttt_s"] = None
+            v["r99"] = None
+    st.close()
+    out["ttt"] = ttt
     return out
 
 
@@ -577,6 +743,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="time the headline workload only (no Max-Cut legs or other graphs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--stream", action="store_true",
@@ -615,16 +783,16 @@ def main():
         print(json.dumps(seeds_bench(args.seeds, args.seeds_jsonl, args.family)), flush=True)
         return
 
-    import numpy as np
     import torch
 
     import paper_2605_30355_amd as cosm
 
     torch.cuda.set_device(0)
-    inst = make_instance()
-    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
-    R, S, m = WORKLOAD["replicas"], WORKLOAD["sweeps"], inst.m
-    log(f"workload {WORKLOAD['name']}: n={inst.n} m={m} C={C} R={R} S={S}")
+    h = HEADLINE
+    inst = headline_instance()
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, h["colouring"], h["sides"])
+    R, S, m = h["replicas"], h["sweeps"], inst.m
+    log(f"workload {h['name']}: n={inst.n} m={m} C={C} R={R} S={S}")
 
     if args.copy_probe:
         # 256 MiB source, then 1 GiB of other writes so that the copy reads HBM
@@ -638,8 +806,8 @@ def main():
         torch.cuda.synchronize()
         del a, b, evict
 
-    # ---- batched LDS-resident form: the timed steps --------------------------------
-    st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, params(cosm), seed=1,
+    # ---- the timed steps: whole trials of the batched LDS-resident form --------------
+    st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, headline_params(cosm), seed=1,
                     replicas=R)
     info = st.info()
     log(f"shape: {info}")
@@ -668,15 +836,15 @@ def main():
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     updates = m * S * R * args.steps
     value = updates / elapsed
+    st.close()
     log(f"batched: {elapsed * 1e3 / args.steps:.2f} ms/step, sweep kernel {avg_kernel_s * 1e3:.2f} ms, "
         f"{value:.3e} edge-updates/s")
 
-    b = 4  # FP32 phase bytes
-    n_dwt = S // WORKLOAD["dwt_period"]
-    lds_bytes_per_launch = R * (S * 4 * b * m + n_dwt * 2 * b * inst.n)
-    achieved = lds_bytes_per_launch / avg_kernel_s / 1e9
+    algo, moved = lds_bytes(info, inst, R, S, h["dwt_period"], 4)
+    achieved = algo / avg_kernel_s / 1e9
     row_words = info["replicas_per_wg"]  # FP32: one word per replica
     measured = max(cosm.lds_probe(row_words, bpc) for bpc in (1, 2))
+    layout = {1: "pair", 2: "register"}.get(info["lds_form"], None)
     roofline = {"bound": "lds", "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
                 "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
                 "traffic": traffic_bytes(), "traffic_unit": "HBM bytes per launch",
@@ -684,64 +852,13 @@ def main():
                 "measured_peak_note": "cosm_lds_probe: 2 reads + 2 writes per lane of "
                                       f"{4 * row_words}-byte rows, no arithmetic or barriers",
                 "frac_of_measured": round(achieved / measured, 4),
-                "kernel": f"k_sweep_lds<fp32, {row_words} words/row>",
-                "bytes_per_edge_update": 4 * b,
-                "edge_updates_per_s_kernel": round(m * S * R / avg_kernel_s, 1)}
-
-    # ---- plain form: one replica per launch, one launch per colour class ------------
-    plain_sweeps = 500
-    sp = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C,
-                    params(cosm, residency=cosm.RES_PLAIN), seed=1, replicas=1)
-    sp.sweep(20)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sp.sweep(plain_sweeps)
-    torch.cuda.synchronize()
-    plain_dt = time.perf_counter() - t0
-    plain_rate = m * plain_sweeps / plain_dt
-    plain_t_trial = plain_dt / plain_sweeps * S
-    sp.close()
-    log(f"plain: {plain_rate:.3e} edge-updates/s, t_trial {plain_t_trial:.3f} s")
-
-    # ---- time to target at 99% -------------------------------------------------------
-    ttt = None
-    target = load_target()
-    if not args.no_ttt and target is not None:
-        ttt = {"target_H": target, "target_cut": (int(-inst.J.sum()) - target) // 2}
-        for name, over in (("batched_fp32", {}), ("batched_fp16", {"storage": cosm.STORE_FP16}),
-                           ("batched_bf16", {"storage": cosm.STORE_BF16}),
-                           ("batched_fix16", {"storage": cosm.STORE_FIX16}),
-                           ("batched_fix32", {"storage": cosm.STORE_FIX32}),
-                           ("batched_fp32_register_layout", {"lds_form": cosm.LDS_FORM_REGISTER}),
-                           ("batched_fp32_optimal_readout", {"readout": cosm.READOUT_OPTIMAL}),
-                           ("batched_fp32_minimum_colouring", {"colouring": cosm.COLOR_MINIMUM})):
-            col2, C2 = colour, C
-            if "colouring" in over:  # 3 classes of 1000 instead of 4 of 750
-                col2, C2 = cosm.build_partitions(inst.n, inst.eu, inst.ev, over.pop("colouring"))
-            s2 = st if not over and col2 is colour else cosm.State(
-                inst.n, inst.eu, inst.ev, inst.J, col2, C2, params(cosm, **over), seed=1,
-                replicas=R)
-            res, _ = s2.solve_to_target(target, 8 * R)
-            ttt[name] = {"ps": res.ps, "ps_ci95": [res.ps_lo, res.ps_hi], "trials": res.trials,
-                         "r99": res.r99, "t_trial_s": res.t_trial_s, "ttt_s": res.ttt_s,
-                         "best_H": res.best_H,
-                         # whole trials (init, sweeps, readout) per second, as edge updates
-                         "edge_updates_per_s": round(m * S / res.t_trial_s, 1)}
-            if col2 is not colour:
-                ttt[name]["classes"] = C2
-            if s2 is not st:
-                s2.close()
-            log(f"{name}: {ttt[name]}")
-        ps = ttt["batched_fp32"]["ps"]
-        r99 = ttt["batched_fp32"]["r99"]
-        # the plain form runs the same trajectories (bit-exact), so it shares P_s
-        ttt["plain_fp32"] = {"ps": ps, "r99": r99, "t_trial_s": plain_t_trial,
-                             "ttt_s": plain_t_trial * r99 if math.isfinite(r99) else None}
-        for k, v in ttt.items():
-            if isinstance(v, dict) and v.get("ttt_s") is not None and not math.isfinite(v["ttt_s"]):
-                v["ttt_s"] = None
-                v["r99"] = None
-    st.close()
+                "moved_frac": round(moved / avg_kernel_s / 1e9 / LDS_PEAK_GBS, 4),
+                "kernel": f"sweep kernel, fp32, {row_words} words/row, {layout} layout",
+                "bytes_per_edge_update": 16,
+                "bytes_per_launch": algo,
+                "kernel_ms": round(avg_kernel_s * 1e3, 4),
+                "edge_updates_per_s_kernel": round(m * S * R / avg_kernel_s, 1),
+                "valu_peak_lane_ops_per_s": VALU_PEAK_OPS}
 
     out = {
         "metric": "edge-updates/s (batched vs plain) + time-to-target @99% success, 1 MI355X",
@@ -756,21 +873,29 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD["name"], "n": inst.n, "edges": m, "classes": C,
-                   "colouring": "misra-gries, class sizes equalised", "replicas": R, "sweeps": S,
-                   "alpha0_deg": WORKLOAD["alpha0_deg"], "dwt_ratio": WORKLOAD["dwt_ratio"],
-                   "dwt_period": WORKLOAD["dwt_period"], "bisectors": WORKLOAD["bisectors"],
-                   "schedule": "grid", "storage": "fp32", "residency": "lds",
+        "config": {"workload": h["name"], "n": inst.n, "edges": m, "classes": C,
+                   "colouring": "torus pattern", "replicas": R, "sweeps": S,
+                   "alpha0_deg": h["alpha0_deg"], "dwt_ratio": h["dwt_ratio"],
+                   "dwt_period": h["dwt_period"], "bisectors": h["bisectors"],
+                   "schedule": "grid", "storage": "fp32", "residency": "lds", "layout": layout,
                    "replicas_per_wg": info["replicas_per_wg"],
-                   "threads_per_wg": info["threads_per_wg"], "workgroups": info["workgroups"]},
+                   "threads_per_wg": info["threads_per_wg"], "workgroups": info["workgroups"],
+                   "step": "init + sweeps + 100-bisector readout of all replicas"},
         "replica_sweeps_per_s": round(S * R * args.steps / elapsed, 1),
-        "plain_edge_updates_per_s": round(plain_rate, 1),
-        "batched_over_plain": round(value / plain_rate, 1),
         "roofline": roofline,
-        "ttt": ttt,
     }
+    if not args.no_extra:
+        out["maxcut"] = maxcut_legs(args)
+        out["large"] = large_bench({"torus-100x100": ("fp32", "bf16", "fix16"),
+                                    "torus-141x141": ("bf16", "fix16"),
+                                    "rr5-n20000": ("fp32",), "er-n10000": ("fp32",)})["cases"]
+        if "maxcut" in out:
+            mc = out["maxcut"]
+            out["plain_edge_updates_per_s"] = mc["plain_edge_updates_per_s"]
+            out["batched_over_plain"] = mc["batched_over_plain"]
+            out["ttt"] = mc.get("ttt")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, colour, C)
+        out["cpu_baseline"] = cpu_baseline(inst, colour, C, h)
         log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 

@@ -318,6 +318,11 @@ typedef struct {
   double sweep_kernel_ms;  /* their summed duration (HIP events), when timing is on */
   int32_t lds_form;        /* resolved COSM_LDS_FORM_* (0 outside the LDS form) */
   int32_t register_rows;   /* REGISTER: register vertices per thread */
+  int32_t twist_fused;     /* 1: the LDS sweep applies the twist inside the last class's
+                              sub-sweep (same result as a pass after the classes) */
+  int32_t register_vertices; /* REGISTER: vertices whose phases stay in registers */
+  int64_t register_edges;  /* REGISTER: edges with an endpoint in registers (one LDS row
+                              read and written per update instead of two) */
 } cosm_info;
 int cosm_get_info(const cosm_state *s, cosm_info *out);
 

@@ -66,7 +66,9 @@ class _CInfo(ctypes.Structure):
                 ("threads_per_wg", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("max_class_edges", ctypes.c_int32),
                 ("sweep_launches", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double),
-                ("lds_form", ctypes.c_int32), ("register_rows", ctypes.c_int32)]
+                ("lds_form", ctypes.c_int32), ("register_rows", ctypes.c_int32),
+                ("twist_fused", ctypes.c_int32), ("register_vertices", ctypes.c_int32),
+                ("register_edges", ctypes.c_int64)]
 
 
 _lib = None

@@ -755,6 +755,13 @@ int cosm_get_info(const cosm_state *s, cosm_info *out) {
                   : s->lds.reg_k > 0                 ? COSM_LDS_FORM_REGISTER
                                                      : COSM_LDS_FORM_PAIR;
   out->register_rows = s->shape.residency == COSM_RES_LDS ? s->lds.reg_k : 0;
+  out->twist_fused = lds_twist_fused(*s) ? 1 : 0;
+  out->register_vertices = 0;
+  out->register_edges = 0;
+  if (s->shape.residency == COSM_RES_LDS && s->lds.reg_k > 0) {
+    for (int32_t v : s->lds.reg_vertex) out->register_vertices += v >= 0 ? 1 : 0;
+    out->register_edges = s->lds.reg_edges;
+  }
   return COSM_OK;
 }
 

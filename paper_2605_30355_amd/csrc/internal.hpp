@@ -209,6 +209,9 @@ namespace cosm {
 // ---- kernel launchers (kernels.hip) -------------------------------------------------
 int launch_init(cosm_state *s);
 int launch_sweeps(cosm_state *s, int64_t n_sweeps);
+// Whether the LDS sweep of s runs the twist inside the last class's sub-sweep
+// (the launchers pick the fused kernel forms by this test).
+bool lds_twist_fused(const cosm_state &s);
 int launch_readout(cosm_state *s);
 // Optimal-bisector readout (readout_opt.hip); h must be absent.
 int launch_readout_optimal(cosm_state *s);

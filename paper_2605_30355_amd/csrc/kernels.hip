@@ -835,8 +835,7 @@ template <int ST, int W>
 int launch_reg_w(cosm_state *s, const LdsArgs &a) {
   if constexpr (ST == COSM_STORE_FP32 || ST == COSM_STORE_FIX32 || ST == COSM_STORE_FIX16) {
     const int K = s->lds.reg_k;
-    const bool fuse = a.sch.period > 0 && s->lds.fuse;
-    if (a.C == 4 && fuse) {
+    if (lds_twist_fused(*s)) {
       if (K == 1) return launch_reg<ST, W, 1, 4, 4, true>(s, a);
       if (K == 2) return launch_reg<ST, W, 2, 4, 4, true>(s, a);
       if (K == 4) return launch_reg<ST, W, 4, 4, 4, true>(s, a);
@@ -866,9 +865,7 @@ int launch_lds_w(cosm_state *s, const LdsArgs &a) {
   const int slots = a.total_slots;
   // one slot per class and exactly 4 / 8 slots: the unconditional form
   const bool one_each = slots == a.C && slots <= 32 && a.bar_mask == (uint32_t)((1ull << slots) - 1);
-  // the twist inside the last class: a twist period, no field pass after the
-  // classes, and the rows outside the last class few enough for registers
-  const bool fuse = a.sch.period > 0 && a.h_slot == nullptr && s->lds.fuse;
+  const bool fuse = lds_twist_fused(*s);
   if (fuse && one_each && slots == 4) return launch_lds<ST, W, 4, true, true>(s, a);
   if (fuse && one_each && slots == 8) return launch_lds<ST, W, 8, true, true>(s, a);
   if (one_each && slots == 4) return launch_lds<ST, W, 4, true>(s, a);
@@ -1098,6 +1095,21 @@ template <int ST> struct SweepFn {
 };
 
 }  // namespace
+
+// The fused twist exists in the register form with exactly 4 classes and in
+// the pair form's one-slot-per-class (4 or 8 classes) and streamed schedules;
+// it needs a twist period, no bias-field pass after the classes, and a
+// schedule that lists the rows outside the last class (lds.fuse).
+bool lds_twist_fused(const cosm_state &s) {
+  if (s.shape.residency != COSM_RES_LDS || s.sched.dwt_period <= 0 || !s.lds.fuse) return false;
+  if (s.lds.reg_k > 0) return s.C == 4;
+  if (s.has_h) return false;
+  const int slots = s.lds.total_slots;
+  bool one_each = slots == s.C;
+  for (int32_t k : s.lds.K) one_each = one_each && k == 1;
+  if (one_each && (slots == 4 || slots == 8)) return true;
+  return slots > kRegisterSlotsMax;
+}
 
 size_t readout_lds_bytes(int32_t n, int32_t B) {
   return 16 * 8 + (size_t)(B + 1) * 8 + (size_t)B * 4 + (size_t)n * 2 + 16;

@@ -117,3 +117,57 @@ def test_sixteen_bit_phase_error_first_sweeps(store):
             say(f"store={store} sweep {k}: max {err.max():.3e} rad, median {np.median(err):.3e} rad")
     # beyond the storage rounding the error grows only through flipped sign decisions
     assert np.median(err) < 2 * np.pi * quantum * 16
+
+
+# ---------------------------------------------------------------------------
+# The large torus (the 100 x 100 +-1 torus, the shape of the G72-like
+# configuration), 1024 replicas a side, 1000 sweeps: FP16 and BF16 storage
+# (FP32 arithmetic, the streamed LDS form at 4 or 8 replicas per workgroup)
+# against the oracle's grid schedule, and FP32 with the continuous schedule
+# against the oracle's continuous schedule.
+# ---------------------------------------------------------------------------
+LARGE_S, LARGE_R, LARGE_SEED = 1000, 1024, 29
+_large_oracle = {}
+
+
+def _torus100():
+    inst = ci.torus(100, seed=3)
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [100, 100])
+    return inst, colour, C
+
+
+def _large_oracle_energies(sched):
+    if sched not in _large_oracle:
+        inst, colour, C = _torus100()
+        op = oracle.Params(sweeps=LARGE_S, dwt_ratio=0.5, dwt_period=3, schedule=sched)
+        say(f"[oracle] torus100 {LARGE_R} replicas x {LARGE_S} sweeps, schedule {sched}")
+        _large_oracle[sched] = oracle_energies(inst, colour, C, op, LARGE_SEED, 0, LARGE_R)
+    return _large_oracle[sched]
+
+
+@pytest.mark.parametrize("case", [(cosm.SCHED_GRID, cosm.STORE_FP16, 4),
+                                  (cosm.SCHED_GRID, cosm.STORE_FP16, 8),
+                                  (cosm.SCHED_GRID, cosm.STORE_BF16, 4),
+                                  (cosm.SCHED_GRID, cosm.STORE_BF16, 8),
+                                  (cosm.SCHED_CONTINUOUS, cosm.STORE_FP32, 2)],
+                         ids=["fp16-rw4", "fp16-rw8", "bf16-rw4", "bf16-rw8", "fp32-continuous"])
+def test_large_torus_energy_distribution(case):
+    """Each case runs the streamed pair form (20 slots per thread at 1024
+    threads) at the given replicas per workgroup."""
+    sched, store, rw = case
+    inst, colour, C = _torus100()
+    p = cosm.Params(sweeps_per_trial=LARGE_S, dwt_ratio=0.5, dwt_period=3, schedule=sched,
+                    storage=store, lds_form=cosm.LDS_FORM_PAIR, replicas_per_wg=rw,
+                    threads_per_wg=1024, residency=cosm.RES_LDS)
+    Ho = _large_oracle_energies(sched)                                      # replicas 0 .. R-1
+    Hg = gpu_energies(inst, colour, C, p, LARGE_SEED, LARGE_R, LARGE_R)     # replicas R .. 2R-1
+    # the success threshold: the oracle sample's lower decile
+    tgt = int(np.quantile(Ho, 0.1))
+    kg, ko = int((Hg <= tgt).sum()), int((Ho <= tgt).sum())
+    lo, hi = newcombe_diff(kg, LARGE_R, ko, LARGE_R)
+    ks = stats.ks_2samp(Hg, Ho)
+    say(f"torus100 sched={sched} store={store}: P_s(H <= {tgt}) gpu {kg}/{LARGE_R} oracle "
+        f"{ko}/{LARGE_R} (95% CI of the difference [{lo:.4f}, {hi:.4f}]); mean H gpu "
+        f"{Hg.mean():.2f} oracle {Ho.mean():.2f}; KS p = {ks.pvalue:.3g}")
+    assert lo <= 0.0 <= hi
+    assert ks.pvalue > 0.01

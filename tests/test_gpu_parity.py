@@ -161,16 +161,67 @@ def test_ragged_replicas_and_resume():
     check_trial(inst, colour, C, prob, p, seed=9, R=37, sweeps=500, chunks=7)
 
 
-def test_c2_full_size_sampled():
+def check_all(inst, colour, C, prob, params, seed, R, sweeps, phase_rows):
+    """Every replica's energy, cut and spins, and the phases of phase_rows,
+    against the oracle run on all host cores."""
+    x, H, cut, spins, info = run_gpu(inst, colour, C, params, seed, R, sweeps)
+    op = oparams(params)
+    say(f"[oracle] all {R} replicas x {sweeps} sweeps")
+    xr, sr, Hr, cr = oracle.solve(prob, op, seed, 0, R, n_threads=16)
+    bad = np.nonzero((H != Hr) | (cut != cr))[0]
+    assert len(bad) == 0, f"energies differ at replicas {bad[:10].tolist()}"
+    assert np.array_equal(spins, sr), "spins differ"
+    for r in phase_rows:
+        assert np.array_equal(x[r] * 360.0, xr[r]), f"replica {r}: phases differ"
+    return info
+
+
+def xcd_sample(R, rw, per_block=3):
+    """Replicas spread over the 8 XCD ranges of the sweep's workgroup map: the
+    kernel gives XCD x the replica blocks [x q, (x + 1) q), q = blocks / 8."""
+    blocks = (R + rw - 1) // rw
+    q = blocks // 8
+    rows = set()
+    for x in range(8):
+        lo, hi = x * q * rw, (x + 1) * q * rw - 1
+        rows.update(np.linspace(lo, hi, per_block).round().astype(int).tolist())
+    rows.add(R - 1)
+    return sorted(r for r in rows if r < R)
+
+
+def test_c2_full_size_bench_shape():
     """3-regular N=2000 Max-Cut (+1 weights), equalised Misra-Gries colouring,
-    1024 replicas, 1e4 sweeps, in the launch shape the benchmark uses; 6
-    replicas checked."""
+    1024 replicas, 1e4 sweeps, in the shape the benchmark times (2 replicas
+    and 768 threads per workgroup, one slot per class, the twist fused into the
+    last class): energies, cuts and spins of all 1024 replicas, phases of
+    replicas spread over the XCD blocks."""
     inst = ci.random_regular(2000, 3, seed=2, weights="maxcut1")
     colour, C, prob = make(inst, cosm.COLOR_BALANCED)
-    p = cosm.Params(sweeps_per_trial=10000, dwt_ratio=1.0, dwt_period=6)
-    info = check_trial(inst, colour, C, prob, p, seed=42, R=1024, sweeps=10000,
-                       sample=[0, 1, 511, 512, 1022, 1023])
+    p = cosm.Params(sweeps_per_trial=10000, dwt_ratio=1.0, dwt_period=6, replicas_per_wg=2,
+                    threads_per_wg=768, lds_form=cosm.LDS_FORM_PAIR)
+    info = check_all(inst, colour, C, prob, p, seed=42, R=1024, sweeps=10000,
+                     phase_rows=xcd_sample(1024, 2))
     assert info["residency"] == cosm.RES_LDS
+    assert info["replicas_per_wg"] == 2 and info["threads_per_wg"] == 768
+    assert info["lds_form"] == cosm.LDS_FORM_PAIR and info["twist_fused"] == 1
+
+
+def test_torus141_full_width():
+    """The 141 x 141 +-1 torus (N = 19881, 6 classes) at 4096 replicas in the
+    benchmark's shape: energies, cuts and spins of replicas sampled from every
+    XCD block of the workgroup map, and their phases, against the oracle."""
+    import bench
+    cfg = bench.HEADLINE
+    inst = bench.headline_instance()
+    colour, C, prob = make(inst, cfg["colouring"], cfg["sides"])
+    S = 600
+    p = bench.headline_params(cosm, sweeps_per_trial=S)
+    R = cfg["replicas"]
+    rows = xcd_sample(R, p.replicas_per_wg or 2)
+    info = check_trial(inst, colour, C, prob, p, seed=3, R=R, sweeps=S, sample=rows)
+    assert info["residency"] == cosm.RES_LDS and info["replicas"] == R
+    assert info["replicas_per_wg"] == p.replicas_per_wg
+    assert info["threads_per_wg"] == p.threads_per_wg
 
 
 @pytest.mark.parametrize("order", [0, cosm.ORDER_LARGEST_LAST])

@@ -153,3 +153,20 @@ def test_not_applicable():
     with pytest.raises(CosmError) as e:
         cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, replicas=4, h=h)
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("storage", [cosm.STORE_FP32, cosm.STORE_FIX32, cosm.STORE_FIX16])
+def test_fused_twist_four_register_rows(storage):
+    """The register kernel with 4 register rows per thread and the twist fused
+    into the last class (the form the large even tori run): 64 threads hold
+    the 200 register vertices of the 20 x 20 torus, four each; twist every 3
+    sweeps; equal to the pair layout and to the oracle."""
+    inst = ci.torus(20, seed=1)
+    colour, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [20, 20])
+    kw = dict(storage=storage, sweeps_per_trial=1500, dwt_ratio=0.5, dwt_period=3,
+              residency=cosm.RES_LDS, replicas_per_wg=2 if storage != cosm.STORE_FIX16 else 4,
+              threads_per_wg=64)
+    a = both(inst, colour, C, 17, 40, [700, 800], **kw)
+    assert a[4]["register_rows"] == 4 and a[4]["threads_per_wg"] == 64
+    assert a[4]["twist_fused"] == 1
+    oracle_rows(inst, colour, C, cosm.Params(**kw), 17, [0, 19, 39], 1500, a[0])
