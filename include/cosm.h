@@ -196,6 +196,27 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
               const cosm_params *p, uint64_t seed, int32_t replicas, void *hip_stream,
               void *device_workspace, size_t workspace_bytes);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops with a fixed memory footprint, harnesses that forbid
+ * hipMalloc): cosm_init with every device buffer of the state placed in a
+ * static array the library holds on each GPU (32 MiB per device, kept until
+ * the process ends) instead of hipMalloc or a caller workspace.  Arguments and
+ * results are those of cosm_init.  The call allocates nothing: no hipMalloc,
+ * no HIP event, and the kernel shape is chosen without the timed autotuner
+ * (replicas_per_wg / threads_per_wg = 0 take the untimed default).
+ * One such state may live per device at a time: the array is shared, so a
+ * second cosm_init_static on the same device fails with ESTATE until the first
+ * state is cosm_destroy'ed; states made this way on different devices are
+ * independent.  The array keeps whatever the last state left in it; every
+ * buffer is written before it is read.  Errors: those of cosm_init, ERANGE when
+ * cosm_workspace_bytes exceeds 32 MiB, ESTATE as above.  Later calls on the
+ * state behave as for cosm_init (cosm_get_phases / cosm_set_phases still
+ * allocate a staging buffer; cosm_set_timing creates its events). */
+int cosm_init_static(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                     const int32_t *J, const int32_t *h, const int32_t *colour,
+                     int32_t num_colours, const cosm_params *p, uint64_t seed, int32_t replicas,
+                     void *hip_stream);
+
 /* Release the state and everything the library allocated for it. */
 int cosm_destroy(cosm_state *s);
 

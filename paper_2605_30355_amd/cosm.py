@@ -26,6 +26,7 @@ LDS_FORM_AUTO, LDS_FORM_PAIR, LDS_FORM_REGISTER = 0, 1, 2
 # Every function declared in include/cosm.h.
 ABI_FUNCTIONS = (
     "cosm_default_params", "cosm_build_partitions", "cosm_workspace_bytes", "cosm_init",
+    "cosm_init_static",
     "cosm_destroy", "cosm_reset", "cosm_sweep", "cosm_energy", "cosm_solve_to_target",
     "cosm_get_phases", "cosm_set_phases", "cosm_get_info", "cosm_set_timing",
     "cosm_last_error", "cosm_version", "cosm_lds_probe", "cosm_qubo_to_ising",
@@ -95,6 +96,8 @@ def load_library():
         "cosm_workspace_bytes": (I32, [I32, I64, I32, I32, PS, ctypes.POINTER(ctypes.c_size_t)]),
         "cosm_init": (I32, [ctypes.POINTER(P), I32, I64, P, P, P, P, P, I32, PS, U64, I32, P, P,
                             ctypes.c_size_t]),
+        "cosm_init_static": (I32, [ctypes.POINTER(P), I32, I64, P, P, P, P, P, I32, PS, U64, I32,
+                                   P]),
         "cosm_destroy": (I32, [P]),
         "cosm_reset": (I32, [P, U64, I64]),
         "cosm_sweep": (I32, [P, I64]),
@@ -245,7 +248,7 @@ class State:
     kernel runs on torch's current HIP stream of the current device."""
 
     def __init__(self, n, eu, ev, J, colour, num_colours, params: Params | None = None, seed=0,
-                 replicas=1, h=None, torch_workspace=True):
+                 replicas=1, h=None, torch_workspace=True, static_scratch=False):
         import torch
         L = load_library()
         if not torch.cuda.is_available():
@@ -261,6 +264,15 @@ class State:
         self._stream = torch.cuda.current_stream()
         self._ws = None
         ws_ptr, ws_bytes = None, 0
+        if static_scratch:  # cosm_init_static: the library's fixed per-device array
+            handle = ctypes.c_void_p()
+            _check(L.cosm_init_static(ctypes.byref(handle), self.n, self.m, _ptr(self._eu),
+                                      _ptr(self._ev), _ptr(self._J), _ptr(self._h),
+                                      _ptr(self._colour), int(num_colours), ctypes.byref(cp),
+                                      int(seed) & ((1 << 64) - 1), self.R,
+                                      ctypes.c_void_p(self._stream.cuda_stream)))
+            self._h_state = handle
+            return
         if torch_workspace:
             nbytes = ctypes.c_size_t(0)
             _check(L.cosm_workspace_bytes(self.n, self.m, int(num_colours), self.R,

@@ -357,6 +357,18 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
               const cosm_params *p, uint64_t seed, int32_t replicas, void *hip_stream,
               void *device_workspace, size_t workspace_bytes) {
   clear_error();
+  return init_state(out, n, m, eu, ev, J, h, colour, num_colours, p, seed, replicas, hip_stream,
+                    device_workspace, workspace_bytes, -1);
+}
+
+}  // extern "C"
+
+namespace cosm {
+
+int init_state(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+               const int32_t *J, const int32_t *h, const int32_t *colour, int32_t num_colours,
+               const cosm_params *p, uint64_t seed, int32_t replicas, void *hip_stream,
+               void *device_workspace, size_t workspace_bytes, int32_t static_dev) {
   if (out == nullptr) return set_error(COSM_EINVAL, "out must not be NULL");
   *out = nullptr;
   if (int rc = check_params(p)) return rc;
@@ -466,7 +478,7 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
     return rc;
   }
   const char *tune_env = std::getenv("COSM_AUTOTUNE");
-  const bool autotune = s->shape.residency == COSM_RES_LDS && p->replicas_per_wg == 0 &&
+  const bool autotune = static_dev < 0 && s->shape.residency == COSM_RES_LDS && p->replicas_per_wg == 0 &&
                         p->threads_per_wg == 0 && s->lds_widths.size() > 0 &&
                         !(tune_env && tune_env[0] == '0');
 
@@ -544,19 +556,28 @@ int cosm_init(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const i
     rc = rc ? rc : up(d.inc_nbr, inc_nbr.data(), inc_nbr.size() * 4);
     rc = rc ? rc : up(d.inc_J, inc_J.data(), inc_J.size() * 4);
   }
-  if (rc == COSM_OK && hipEventCreate(&s->ev0) != hipSuccess) rc = set_error(COSM_EDEVICE, "hipEventCreate");
-  if (rc == COSM_OK && hipEventCreate(&s->ev1) != hipSuccess) rc = set_error(COSM_EDEVICE, "hipEventCreate");
+  if (static_dev < 0) {
+    if (rc == COSM_OK && hipEventCreate(&s->ev0) != hipSuccess) rc = set_error(COSM_EDEVICE, "hipEventCreate");
+    if (rc == COSM_OK && hipEventCreate(&s->ev1) != hipSuccess) rc = set_error(COSM_EDEVICE, "hipEventCreate");
+  }
   rc = rc ? rc : launch_init(s);
   rc = rc ? rc : sync(s);  // the host vectors above must outlive the copies
   if (rc == COSM_OK && autotune) rc = autotune_lds_shape(s, s->lds_widths);
   rc = rc ? rc : sync(s);
   if (rc) {
+    // the caller keeps the static scratch array until this returns
+    s->static_dev = -1;
     cosm_destroy(s);
     return rc;
   }
+  s->static_dev = static_dev;
   *out = s;
   return COSM_OK;
 }
+
+}  // namespace cosm
+
+extern "C" {
 
 int cosm_destroy(cosm_state *s) {
   clear_error();
@@ -565,6 +586,7 @@ int cosm_destroy(cosm_state *s) {
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
   if (s->own_memory && s->base) (void)hipFree(s->base);
+  if (s->static_dev >= 0) release_static_scratch(s->static_dev);
   delete s;
   return COSM_OK;
 }
@@ -768,6 +790,10 @@ int cosm_get_info(const cosm_state *s, cosm_info *out) {
 int cosm_set_timing(cosm_state *s, int32_t on) {
   clear_error();
   if (s == nullptr) return set_error(COSM_EINVAL, "state must not be NULL");
+  if (on && s->ev0 == nullptr) {  // a state made by cosm_init_static has no events yet
+    COSM_HIP_CHECK(hipEventCreate(&s->ev0));
+    COSM_HIP_CHECK(hipEventCreate(&s->ev1));
+  }
   s->timing = on != 0;
   if (s->timing) {
     s->launches = 0;

@@ -203,9 +203,23 @@ struct cosm_state {
   int64_t launches = 0;
   double kernel_ms = 0.0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // device whose static scratch array holds the buffers (cosm_init_static), or -1
+  int32_t static_dev = -1;
 };
 
 namespace cosm {
+// ---- state creation (api.cpp) ------------------------------------------------------
+// cosm_init with the buffers in device_workspace (or, when it is null, one
+// hipMalloc of the library's).  static_dev >= 0: the workspace is that
+// device's static scratch array; the shape is then chosen without the timed
+// autotuner and no HIP event is created, so the call allocates nothing.
+int init_state(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+               const int32_t *J, const int32_t *h, const int32_t *colour, int32_t num_colours,
+               const cosm_params *p, uint64_t seed, int32_t replicas, void *hip_stream,
+               void *device_workspace, size_t workspace_bytes, int32_t static_dev);
+// Releases the static scratch array of a device held by a state (static_scratch.hip).
+void release_static_scratch(int32_t dev);
+
 // ---- kernel launchers (kernels.hip) -------------------------------------------------
 int launch_init(cosm_state *s);
 int launch_sweeps(cosm_state *s, int64_t n_sweeps);
