@@ -344,6 +344,8 @@ typedef struct {
   int32_t register_vertices; /* REGISTER: vertices whose phases stay in registers */
   int64_t register_edges;  /* REGISTER: edges with an endpoint in registers (one LDS row
                               read and written per update instead of two) */
+  int32_t streamed;        /* 1: the LDS sweep streams its lane schedule from memory, two
+                              slots in flight per wave (long schedules: the large graphs) */
 } cosm_info;
 int cosm_get_info(const cosm_state *s, cosm_info *out);
 

@@ -32,7 +32,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every device buffer inside one allocation.
 struct MemPlan {
-  size_t phases, desc, class_off, slot_vertex, reg_vertex, h_slot, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
+  size_t phases, desc, jmag, class_off, slot_vertex, reg_vertex, h_slot, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
       inc_off, inc_nbr, inc_J, phases_alt, opt_keys, opt_keys2, opt_vals, opt_vals2, opt_off,
       opt_temp, opt_temp_bytes, codes, total;
 };
@@ -50,11 +50,13 @@ MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_param
   // lane schedule: at most 32 lanes per edge group plus one partial pass per
   // class, the repeated slots, then the rows outside the last class
   // (or the register-owner form's [C][K + 1][nth])
-  const size_t pair_desc = (size_t)32 * m + (size_t)1024 * C + 1024 +
-                           (size_t)(kStreamRepeat + kFuseRowsMax) * 1024;
+  // (the streamed word form pads each class to a multiple of kWordGroup slots)
+  const size_t pair_desc = (size_t)32 * m + (size_t)kWordGroup * 1024 * C + 1024 +
+                           (size_t)(kWordRepeat + kFuseRowsMax) * 1024;
   const size_t reg_desc = (size_t)std::min(C, kRegClassesMax) * (kRegKMax + 1) * 1024;
   mp.desc = take(std::max(pair_desc, reg_desc) * sizeof(EdgeDesc));
-  mp.class_off = take(((size_t)C + 1) * 4);
+  mp.jmag = take(pair_desc * 4);
+  mp.class_off = take(((size_t)2 * C + 1) * 4);
   mp.slot_vertex = take(((size_t)n + kRegRowsSlack) * 4);
   mp.reg_vertex = take((size_t)kRegKMax * 1024 * 4);
   mp.h_slot = take(((size_t)n + 1) * 4);
@@ -503,6 +505,7 @@ int init_state(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const 
   d.phases = at<void>(s->base, mp.phases);
   d.desc = at<EdgeDesc>(s->base, mp.desc);
   d.class_off = at<int32_t>(s->base, mp.class_off);
+  d.jmag = at<float>(s->base, mp.jmag);
   d.slot_vertex = at<int32_t>(s->base, mp.slot_vertex);
   d.reg_vertex = at<int32_t>(s->base, mp.reg_vertex);
   d.h_slot = at<int32_t>(s->base, mp.h_slot);
@@ -537,13 +540,7 @@ int init_state(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const 
     return COSM_OK;
   };
   int rc = COSM_OK;
-  if (s->shape.residency == COSM_RES_LDS) {
-    rc = rc ? rc : up(d.desc, s->lds.desc.data(), s->lds.desc.size() * sizeof(EdgeDesc));
-    rc = rc ? rc : up(d.class_off, s->lds.K.data(), s->lds.K.size() * 4);
-    rc = rc ? rc : up(d.slot_vertex, s->lds.slot_vertex.data(), s->lds.slot_vertex.size() * 4);
-    rc = rc ? rc : up(d.reg_vertex, s->lds.reg_vertex.data(), s->lds.reg_vertex.size() * 4);
-    rc = rc ? rc : upload_h_slot(s);
-  }
+  if (s->shape.residency == COSM_RES_LDS) rc = upload_lds_schedule(s);
   rc = rc ? rc : up(d.eu, eu, (size_t)m * 4);
   rc = rc ? rc : up(d.ev, ev, (size_t)m * 4);
   rc = rc ? rc : up(d.J, J, (size_t)m * 4);
@@ -784,6 +781,7 @@ int cosm_get_info(const cosm_state *s, cosm_info *out) {
     for (int32_t v : s->lds.reg_vertex) out->register_vertices += v >= 0 ? 1 : 0;
     out->register_edges = s->lds.reg_edges;
   }
+  out->streamed = s->shape.residency == COSM_RES_LDS && s->lds.stream ? 1 : 0;
   return COSM_OK;
 }
 

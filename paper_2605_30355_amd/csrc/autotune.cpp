@@ -2,8 +2,10 @@
 //
 // Candidates: every LDS row width that fits (1, 2 or 4 words per row, i.e. 1-4
 // FP32 or 2-8 16-bit replicas per workgroup) crossed with a few thread counts
-// (pair layout), and with 1, 2 or 4 register rows per thread (register layout,
-// where it applies; only these when it is requested).
+// (pair layout; a long schedule in both streamed forms: the word form with two
+// slots in flight per wave, and the classic one), and with 1, 2 or 4 register
+// rows per thread (register layout, where it applies; only these when it is
+// requested).
 // Each candidate runs a short timed probe on the state's own phases (which are
 // re-drawn afterwards, so the probe leaves no trace in the trajectory), and the
 // fastest shape is kept.  Results are cached per process, keyed by the
@@ -26,7 +28,9 @@ namespace {
 // FNV-1a hash of the edge list and its colouring (the schedules are built from
 // exactly these, so two instances with the same key accept the same shapes).
 using Key = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t, uint64_t>;
-using Shape = std::tuple<int32_t, int32_t, int32_t>;  // (W, threads, register rows or 0)
+// (W, threads, register rows or 0, 1 = the classic streamed schedule instead of
+// the streamed word form)
+using Shape = std::tuple<int32_t, int32_t, int32_t, int32_t>;
 std::mutex g_cache_mu;
 std::map<Key, Shape> g_cache;
 
@@ -43,12 +47,41 @@ Key make_key(const cosm_state &s) {
   return Key{s.n, s.m, s.C, s.R, s.p.storage, s.p.lds_form, s.has_h ? 1 : 0, h};
 }
 
-int upload_schedule(cosm_state *s) {
+
+int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw, int32_t K,
+                int32_t classic = 0) {
+  if (K > 0) {
+    if (int rc = reg_schedule_for(*s, W, K, nth, &s->lds)) return rc;
+  } else {
+    if (int rc = build_lds_schedule(*s, W, nth, &s->lds, true, classic == 0)) return rc;
+  }
+  s->shape.residency = COSM_RES_LDS;
+  s->shape.rw = W * pw;
+  s->shape.blocks = (s->R + s->shape.rw - 1) / s->shape.rw;
+  s->shape.lds_bytes = (int32_t)lds_sweep_bytes(K > 0 ? s->lds.n_rows : s->n_slots, W, s->C);
+  s->shape.threads = s->lds.nth;
+  return upload_lds_schedule(s);
+}
+
+}  // namespace
+
+int upload_lds_schedule(cosm_state *s) {
   const LdsSchedule &L = s->lds;
-  COSM_HIP_CHECK(hipMemcpyAsync(s->d.desc, L.desc.data(), L.desc.size() * sizeof(EdgeDesc),
-                                hipMemcpyHostToDevice, s->stream));
-  if (!L.K.empty())
-    COSM_HIP_CHECK(hipMemcpyAsync(s->d.class_off, L.K.data(), L.K.size() * 4,
+  if (L.stream) {
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.desc, L.sdesc.data(), L.sdesc.size() * 4,
+                                  hipMemcpyHostToDevice, s->stream));
+    if (!L.sjmag.empty())
+      COSM_HIP_CHECK(hipMemcpyAsync(s->d.jmag, L.sjmag.data(), L.sjmag.size() * 4,
+                                    hipMemcpyHostToDevice, s->stream));
+  } else {
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.desc, L.desc.data(), L.desc.size() * sizeof(EdgeDesc),
+                                  hipMemcpyHostToDevice, s->stream));
+  }
+  // slots per class, then (streamed word form) the lanes of each class's last slot
+  std::vector<int32_t> cls(L.K);
+  if (L.stream) cls.insert(cls.end(), L.last_lanes.begin(), L.last_lanes.end());
+  if (!cls.empty())
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.class_off, cls.data(), cls.size() * 4,
                                   hipMemcpyHostToDevice, s->stream));
   COSM_HIP_CHECK(hipMemcpyAsync(s->d.slot_vertex, L.slot_vertex.data(),
                                 L.slot_vertex.size() * 4, hipMemcpyHostToDevice, s->stream));
@@ -59,22 +92,6 @@ int upload_schedule(cosm_state *s) {
   COSM_HIP_CHECK(hipStreamSynchronize(s->stream));  // host vectors may change next
   return COSM_OK;
 }
-
-int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw, int32_t K) {
-  if (K > 0) {
-    if (int rc = reg_schedule_for(*s, W, K, nth, &s->lds)) return rc;
-  } else {
-    if (int rc = build_lds_schedule(*s, W, nth, &s->lds, true)) return rc;
-  }
-  s->shape.residency = COSM_RES_LDS;
-  s->shape.rw = W * pw;
-  s->shape.blocks = (s->R + s->shape.rw - 1) / s->shape.rw;
-  s->shape.lds_bytes = (int32_t)lds_sweep_bytes(K > 0 ? s->lds.n_rows : s->n_slots, W, s->C);
-  s->shape.threads = s->lds.nth;
-  return upload_schedule(s);
-}
-
-}  // namespace
 
 int upload_h_slot(cosm_state *s) {
   if (!s->has_h) return COSM_OK;
@@ -135,7 +152,7 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
       if (apply_shape(s, std::get<0>(it->second), std::get<1>(it->second), pw,
-                      std::get<2>(it->second)) == COSM_OK)
+                      std::get<2>(it->second), std::get<3>(it->second)) == COSM_OK)
         return COSM_OK;
       // the cached shape does not apply to this instance: measure afresh
       clear_error();
@@ -147,24 +164,27 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
   COSM_HIP_CHECK(hipEventCreate(&e0));
   COSM_HIP_CHECK(hipEventCreate(&e1));
   float best_ms = 0.0f;
-  int32_t best_W = 0, best_nth = 0, best_K = 0;
+  int32_t best_W = 0, best_nth = 0, best_K = 0, best_classic = 0;
   int rc = COSM_OK;
   const bool timing = s->timing;
   s->timing = false;
   // candidates: (W, requested threads, register rows); pair form first
   std::vector<Shape> cands;
+  // (the pair form with a long schedule is timed in both streamed forms)
   if (s->p.lds_form != COSM_LDS_FORM_REGISTER)
     for (int32_t W : widths)
-      for (int32_t req : {0, 512, 768, 1024}) cands.emplace_back(W, req, 0);
+      for (int32_t req : {0, 512, 768, 1024})
+        for (int32_t classic : {0, 1}) cands.emplace_back(W, req, 0, classic);
   if (s->p.lds_form != COSM_LDS_FORM_PAIR && reg_form_supported(*s))
     for (int32_t W : widths)
-      for (int32_t K : {1, 2, 4}) cands.emplace_back(W, 0, K);
+      for (int32_t K : {1, 2, 4}) cands.emplace_back(W, 0, K, 0);
   std::vector<Shape> tried;
   int32_t auto_nth = 0;
   for (const Shape &cand : cands) {
     const int32_t W = std::get<0>(cand), req = std::get<1>(cand), K = std::get<2>(cand);
+    const int32_t classic = std::get<3>(cand);
     if (K == 0 && req > 0 && req < auto_nth / 2) continue;  // far too few threads for one pass
-    rc = apply_shape(s, W, req, pw, K);
+    rc = apply_shape(s, W, req, pw, K, classic);
     if (rc && K > 0) {  // the register form does not apply to this shape
       rc = COSM_OK;
       clear_error();
@@ -172,7 +192,10 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
     }
     if (rc) break;
     if (K == 0 && req == 0) auto_nth = s->lds.nth;
-    const Shape got{W, s->lds.nth, K};
+    // a short schedule (or one with a field pass) has no word form: the two
+    // candidates are one
+    const bool long_sched = K == 0 && s->lds.total_slots > kRegisterSlotsMax && !s->has_h;
+    const Shape got{W, s->lds.nth, K, classic != 0 && long_sched ? 1 : 0};
     if (std::find(tried.begin(), tried.end(), got) != tried.end()) continue;
     tried.push_back(got);
     const int64_t t_saved = s->t;
@@ -201,6 +224,7 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
       best_W = W;
       best_nth = s->lds.nth;
       best_K = K;
+      best_classic = std::get<3>(got);
     }
   }
   if (rc == COSM_OK && best_W == 0)
@@ -213,9 +237,9 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
   s->kernel_ms = 0.0;
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    g_cache[key] = Shape{best_W, best_nth, best_K};
+    g_cache[key] = Shape{best_W, best_nth, best_K, best_classic};
   }
-  rc = apply_shape(s, best_W, best_nth, pw, best_K);
+  rc = apply_shape(s, best_W, best_nth, pw, best_K, best_classic);
   if (rc) return rc;
   return launch_init(s);  // the probes moved the phases: draw them again
 }

@@ -117,6 +117,25 @@ struct LdsSchedule {
   // two LDS rows (the pair form's encoding), used when reg_free is 1.  Lanes
   // without an edge carry a dummy row with J = 0.  Rows: slot_vertex, -1 for
   // padding; n_rows is a multiple of 64 and the dummy rows follow it.
+  // Streamed word form (stream = true; schedules longer than the register-
+  // resident ones, no bias fields): the schedule again as two 32-bit words per
+  // lane and slot in sdesc, (u_off | Jneg << 31, v_off), where u_off / v_off
+  // are the LDS byte offsets of the rows (row * 4 W) and Jneg the sign bit of
+  // J; masked lanes hold dummy-row pairs (J = 0).  Class c keeps its K[c]
+  // slots, padded to an even number (an added slot holds dummy pairs and is
+  // never run), stotal slots in all, then kWordRepeat repeated slots, then the
+  // rows outside the last class as (row_off, 0).  For odd K[c] the last slot
+  // holds entries in its first last_lanes[c] lanes only (later waves skip it;
+  // for even K[c] last_lanes[c] = nth: the final pair runs on every wave).
+  // With junit every |J| equals jscale; otherwise sjmag holds |J| per entry of
+  // the slots and the repeated slots.
+  bool stream = false;
+  bool junit = true;
+  float jscale = 1.0f;
+  int32_t stotal = 0;
+  std::vector<uint32_t> sdesc;
+  std::vector<float> sjmag;
+  std::vector<int32_t> last_lanes;
   int32_t reg_k = 0;
   int32_t reg_free = 0;
   std::vector<int32_t> reg_vertex;
@@ -130,11 +149,17 @@ constexpr int32_t kRegRowsSlack = 4096;  // slot_vertex capacity beyond n
 constexpr int32_t kRegisterSlotsMax = 16;  // schedules this short stay in registers
 constexpr int32_t kFuseRowsMax = 4;
 constexpr int32_t kStreamRepeat = 3;
+// Streamed word form: every class is padded to a multiple of kWordGroup
+// slots (the sweep kernel runs them in pairs); kWordRepeat slots repeat after
+// the last, for the words fetched two slots ahead.
+constexpr int32_t kWordGroup = 2;
+constexpr int32_t kWordRepeat = 2;
 
 struct DeviceBuffers {
   void *phases = nullptr;       // [n][R] float or 16-bit, replica-major
   EdgeDesc *desc = nullptr;     // LDS-form descriptors, grouped by class
-  int32_t *class_off = nullptr; // [C+1] offsets into desc
+  int32_t *class_off = nullptr; // [2C + 1]: slots per class, then (streamed form) last_lanes
+  float *jmag = nullptr;        // streamed word form: |J| per schedule entry (non-uniform |J|)
   int32_t *slot_vertex = nullptr; // [n_slots] vertex held by each LDS slot
   int32_t *reg_vertex = nullptr;  // [kRegKMax * 1024] register-owner form
   int32_t *h_slot = nullptr;    // [n_slots] bias field of the vertex in each slot (with h)
@@ -239,8 +264,13 @@ int lds_capacity_bytes();
 // dummy_pairs: masked lanes of a register-resident schedule get conflict-free
 // no-op edges between dummy rows (only for the single-instance sweep kernel,
 // whose LDS holds the dummy rows).
+// allow_stream: long schedules without bias fields take the streamed word
+// form (needs dummy_pairs); false keeps the classic streamed schedule.
 int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out,
-                       bool dummy_pairs = false);
+                       bool dummy_pairs = false, bool allow_stream = true);
+// The streamed word form's sweep (sweep_stream.hip), for states whose schedule
+// has it (lds.stream).
+int launch_sweeps_stream(cosm_state *s, int64_t n_sweeps);
 // Register-owner schedule (see LdsSchedule) for rows of W words, K register
 // vertices per thread and nth_request threads (0: as many as the register
 // vertices need).  COSM_ERANGE when the form does not apply (more than
@@ -258,6 +288,9 @@ int pick_reg_schedule(cosm_state *s, int32_t W, int32_t nth);
 int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths);
 // Uploads the bias field in LDS-slot order (no-op without bias fields).
 int upload_h_slot(cosm_state *s);
+// Uploads s->lds (the schedule in the kernel's encoding, the slots per class,
+// the slot map, the register rows and the slot-ordered fields); synchronises.
+int upload_lds_schedule(cosm_state *s);
 // Reference angles of the dual window twist are drawn kThetaChunk twists at a
 // time into an LDS table of kThetaChunk x (at most 8) floats, followed by a
 // table of the same size for the twist directions (bias fields).
@@ -270,7 +303,7 @@ constexpr int kDummyRows = 64;
 // LDS bytes of the sweep kernel: the vertex and dummy rows, the table of
 // reference angles and the slot count of each of the C classes.
 inline size_t lds_sweep_bytes(int32_t n_rows, int W, int32_t C) {
-  return (size_t)(n_rows + kDummyRows) * W * 4 + (size_t)2 * kThetaFloats * 4 + (size_t)C * 4;
+  return (size_t)(n_rows + kDummyRows) * W * 4 + (size_t)2 * kThetaFloats * 4 + (size_t)C * 8;
 }
 
 size_t readout_lds_bytes(int32_t n, int32_t B);

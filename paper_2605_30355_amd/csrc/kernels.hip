@@ -1086,7 +1086,9 @@ template <int ST> struct ReadoutFn { static int run(cosm_state *s) { return read
 template <int ST> struct SweepFn {
   static int run(cosm_state *s, int64_t n) {
     switch (s->shape.residency) {
-      case COSM_RES_LDS: return sweeps_lds_st<ST>(s, n);
+      case COSM_RES_LDS:
+        if (s->lds.stream) return launch_sweeps_stream(s, n);
+        return sweeps_lds_st<ST>(s, n);
       case COSM_RES_HBM: return sweeps_hbm_st<ST>(s, n);
       case COSM_RES_PLAIN: return sweeps_plain_st<ST>(s, n);
     }

@@ -25,6 +25,7 @@
 // None of this changes the dynamics: each class is still applied in full, in
 // the class order given by the caller.
 #include <algorithm>
+#include <cmath>
 #include <numeric>
 #include <random>
 
@@ -97,7 +98,7 @@ int32_t bipartite_edge_colouring(int32_t G, const std::vector<int32_t> &left,
 }  // namespace
 
 int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsSchedule *out,
-                       bool dummy_pairs) {
+                       bool dummy_pairs, bool allow_stream) {
   const int32_t n = s.n, C = s.C, G = W == 1 ? 32 : 64 / W, H = 32 / W;
   const int64_t m = s.m;
   *out = LdsSchedule();  // nothing of an earlier schedule (e.g. register rows) survives
@@ -292,7 +293,12 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
   // between two dummy rows (after the n vertex rows) whose residues no other
   // lane of its group uses, so that it costs no bank conflict.  u-dummies are
   // dummy rows [0, 32), v-dummies [32, 64).
-  L.dummy_pairs = dummy_pairs && L.total_slots <= kRegisterSlotsMax && n + kDummyRows <= 65536;
+  // The streamed word form replaces the streamed schedule when the sweep has
+  // no field pass (it needs the dummy pairs too).
+  L.stream = dummy_pairs && allow_stream && L.total_slots > kRegisterSlotsMax && !s.has_h &&
+             n + kDummyRows <= 65536;
+  L.dummy_pairs = dummy_pairs && (L.total_slots <= kRegisterSlotsMax || L.stream) &&
+                  n + kDummyRows <= 65536;
   if (L.dummy_pairs) {
     std::vector<char> used_u((size_t)G), used_v((size_t)G);
     for (int32_t jj = 0; jj < L.total_slots; jj++)
@@ -373,6 +379,75 @@ int build_lds_schedule(const cosm_state &s, int32_t W, int32_t nth_request, LdsS
         L.desc[base + q] = EdgeDesc{(uint32_t)bucket[g][next[g]++], 0.0f};
       }
     }
+  }
+  // 6. the streamed word form: byte offsets, the sign of J, |J| when it
+  // varies; every class padded to an even number of slots (an added slot holds
+  // dummy pairs and is never run), so that a class always starts on an even
+  // slot.
+  if (L.stream) {
+    const uint32_t rowb = (uint32_t)(4 * W);
+    float mag = -1.0f;
+    L.junit = true;
+    for (int64_t k = 0; k < m; k++) {
+      const float a = std::fabs((float)s.h_J[(size_t)k]);
+      if (mag < 0.0f) mag = a;
+      if (a != mag || a == 0.0f) L.junit = false;
+    }
+    L.jscale = L.junit && mag > 0.0f ? mag : 1.0f;
+    auto word = [&](const EdgeDesc &d, uint32_t *w, float *jm) {
+      const uint32_t su = d.slots & 0xffffu, sv = d.slots >> 16;
+      w[0] = su * rowb | (std::signbit(d.J) ? 0x80000000u : 0u);
+      w[1] = sv * rowb;
+      *jm = std::fabs(d.J);
+    };
+    // an added slot: lane t pairs the dummy rows of residue t mod G (distinct
+    // in every lane group, so conflict-free), J = 0
+    const int32_t q0 = n % L.G;
+    L.last_lanes.assign((size_t)C, 0);
+    std::vector<uint32_t> words;
+    std::vector<float> mags;
+    int32_t j0 = 0;
+    for (int32_t c = 0; c < C; c++) {
+      const int32_t K = L.K[(size_t)c];
+      const int32_t Kp = (K + kWordGroup - 1) / kWordGroup * kWordGroup;
+      // lanes holding entries in the last slot; with an even slot count every
+      // wave runs the final pair, so all of them count
+      const int32_t last = K > 0 ? std::min(nth, L.padded[(size_t)c] - (K - 1) * nth) : 0;
+      L.last_lanes[(size_t)c] = K % 2 == 0 ? nth : last;
+      for (int32_t k = 0; k < Kp; k++)
+        for (int32_t t = 0; t < nth; t++) {
+          uint32_t w[2];
+          float jm;
+          if (k < K) {
+            word(L.desc[(size_t)(j0 + k) * nth + t], w, &jm);
+          } else {
+            const uint32_t r = (uint32_t)((t % L.G - q0 + L.G) % L.G);
+            word(EdgeDesc{((uint32_t)n + r) | (((uint32_t)n + 32u + r) << 16), 0.0f}, w, &jm);
+          }
+          words.push_back(w[0]);
+          words.push_back(w[1]);
+          mags.push_back(jm);
+        }
+      j0 += K;
+    }
+    L.stotal = (int32_t)(mags.size() / (size_t)nth);
+    // the first slots again after the last, then the rows outside the last class
+    for (int32_t q = 0; q < kWordRepeat; q++)
+      for (int32_t t = 0; t < nth; t++) {
+        const size_t e = (size_t)(q % std::max(1, L.stotal)) * nth + t;
+        words.push_back(words[2 * e]);
+        words.push_back(words[2 * e + 1]);
+        mags.push_back(mags[e]);
+      }
+    const size_t rows_at = (size_t)(L.total_slots + kStreamRepeat) * nth;
+    for (size_t e = rows_at; e < L.desc.size(); e++) {
+      const EdgeDesc &d = L.desc[e];
+      words.push_back(d.slots == kEmptySlot ? kEmptySlot : d.slots * rowb);
+      words.push_back(0u);
+    }
+    L.sdesc = std::move(words);
+    if (L.junit) L.sjmag.clear();
+    else L.sjmag = std::move(mags);
   }
   return COSM_OK;
 }

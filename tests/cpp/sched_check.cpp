@@ -106,6 +106,76 @@ int main(int argc, char** argv) {
   } else if (L.desc.size() != rep) {
     fuse_ok = 0;
   }
-  printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d fuse=%d fuse_k=%d fuse_ok=%d fuse_conflicts=%ld dummies=%ld bad_dummy=%ld\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got), (int)L.fuse, L.fuse_k, fuse_ok, fuse_conflicts, dummies, bad_dummy);
+  // The streamed word form: decode (u_off | Jneg << 31, v_off) back to rows;
+  // every class holds an even number of slots whose real entries are exactly
+  // the class's edges (sign and magnitude of J), dummy entries pair dummy rows
+  // only, lanes past last_lanes in a class's last slot and every lane of a
+  // padding slot hold dummies only, the
+  // first slots repeat after the last, the rows outside the last class follow
+  // as byte offsets, and no group of the LDS model touches a bank twice.
+  int stream_ok = 1;
+  long stream_conflicts = 0;
+  if (L.stream) {
+    const uint32_t rowb = 4u * W;
+    std::multiset<std::tuple<int,int,int,float>> sgot;
+    const size_t nth = (size_t)L.nth;
+    auto dec = [&](size_t e, int &ru, int &rv, float &J) {
+      const uint32_t x = L.sdesc[2 * e], y = L.sdesc[2 * e + 1];
+      if ((x & 0x7fffffffu) % rowb || y % rowb) stream_ok = 0;
+      ru = (int)((x & 0x7fffffffu) / rowb);
+      rv = (int)(y / rowb);
+      const float mag = L.junit ? L.jscale : L.sjmag[e];
+      J = (x >> 31) ? -mag : mag;
+    };
+    int jj = 0;
+    for (int c = 0; c < C && stream_ok; c++) {
+      const int K = L.K[c], Kp = (K + cosm::kWordGroup - 1) / cosm::kWordGroup * cosm::kWordGroup;
+      if (K % 2 == 0 && L.last_lanes[c] != L.nth) stream_ok = 0;
+      for (int k = 0; k < Kp; k++, jj++) {
+        for (size_t t = 0; t < nth; t++) {
+          int ru, rv; float J;
+          dec((size_t)jj * nth + t, ru, rv, J);
+          const bool dummy = ru >= n || rv >= n;
+          if (dummy) {
+            if (!(ru >= n && rv >= n && ru < n + cosm::kDummyRows && rv < n + cosm::kDummyRows &&
+                  ru != rv)) stream_ok = 0;
+            if (!L.junit && J != 0.0f) stream_ok = 0;
+          } else {
+            // padding slots and lanes past last_lanes in the last slot are not run
+            if (k >= K || (k == K - 1 && (int)t >= L.last_lanes[c])) stream_ok = 0;
+            sgot.insert({c, ru, rv, J});
+          }
+        }
+        for (int lanes : {rlanes, wlanes})
+          for (size_t g0 = 0; g0 < nth; g0 += lanes) {
+            int bu[64] = {0}, bv[64] = {0};
+            for (size_t t = g0; t < g0 + lanes && t < nth; t++) {
+              int ru, rv; float J;
+              dec((size_t)jj * nth + t, ru, rv, J);
+              for (int w = 0; w < W; w++) { bu[(ru * W + w) % 64]++; bv[(rv * W + w) % 64]++; }
+            }
+            for (int b = 0; b < 64; b++)
+              stream_conflicts += (bu[b] > 1 ? bu[b] - 1 : 0) + (bv[b] > 1 ? bv[b] - 1 : 0);
+          }
+      }
+    }
+    if (jj != L.stotal) stream_ok = 0;
+    if (sgot != got) stream_ok = 0;
+    const size_t rep = (size_t)(L.stotal + cosm::kWordRepeat) * nth;
+    if (L.sdesc.size() != 2 * (rep + (L.fuse ? (size_t)L.fuse_k * nth : 0))) stream_ok = 0;
+    if (!L.junit && L.sjmag.size() != rep) stream_ok = 0;
+    for (int q = 0; q < cosm::kWordRepeat && stream_ok; q++)
+      for (size_t t = 0; t < nth; t++) {
+        const size_t a = (size_t)(L.stotal + q) * nth + t, b = (size_t)(q % L.stotal) * nth + t;
+        if (L.sdesc[2 * a] != L.sdesc[2 * b] || L.sdesc[2 * a + 1] != L.sdesc[2 * b + 1]) stream_ok = 0;
+      }
+    if (L.fuse)
+      for (size_t e = 0; e < (size_t)L.fuse_k * nth; e++) {
+        const cosm::EdgeDesc d = L.desc[(size_t)(L.total_slots + cosm::kStreamRepeat) * nth + e];
+        const uint32_t want_w = d.slots == cosm::kEmptySlot ? cosm::kEmptySlot : d.slots * rowb;
+        if (L.sdesc[2 * (rep + e)] != want_w) stream_ok = 0;
+      }
+  }
+  printf("W=%d G=%d nth=%d slots=%d rows=%d active=%ld pad=%ld (%.1f%%) conflicts=%ld equal=%d fuse=%d fuse_k=%d fuse_ok=%d fuse_conflicts=%ld dummies=%ld bad_dummy=%ld stream=%d stream_ok=%d stream_conflicts=%ld junit=%d\n", W, L.G, L.nth, L.total_slots, L.n_rows, active, L.pad_entries, 100.0*L.pad_entries/m, conflicts, (int)(want==got), (int)L.fuse, L.fuse_k, fuse_ok, fuse_conflicts, dummies, bad_dummy, (int)L.stream, stream_ok, stream_conflicts, (int)L.junit);
   return 0;
 }

@@ -33,7 +33,8 @@ CASES = [(ci.random_regular(2000, 3, seed=2), cosm.COLOR_BALANCED, None),
          (ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141]),
          (ci.random_regular(20000, 5, seed=1000, weights="pm1"), cosm.COLOR_GREEDY, None),
          (ci.erdos_renyi_capped(10000, 4, 8, seed=3), cosm.COLOR_MISRA_GRIES, None),
-         (ci.small_random(37, 150, seed=5), cosm.COLOR_GREEDY, None)]
+         (ci.small_random(37, 150, seed=5), cosm.COLOR_GREEDY, None),
+         (ci.torus(101, seed=6, weights="pm12"), cosm.COLOR_TORUS, [101, 101])]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: c[0].name)
@@ -47,3 +48,5 @@ def test_schedule_conflict_free_and_complete(checker, case, W):
     assert r.returncode == 0, r.stdout + r.stderr
     assert "conflicts=0" in r.stdout and "equal=1" in r.stdout and "fuse_ok=1" in r.stdout \
         and "bad_dummy=0" in r.stdout, r.stdout
+    # the streamed word form (long schedules): same edges, dummies, no conflicts
+    assert "stream_ok=1" in r.stdout and "stream_conflicts=0" in r.stdout, r.stdout
