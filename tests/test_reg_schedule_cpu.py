@@ -13,18 +13,19 @@ import cosm_inputs as ci
 import paper_2605_30355_amd as cosm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-BIN = os.path.join(ROOT, "tests", "cpp", "reg_check")
 
 
 @pytest.fixture(scope="module")
-def checker():
+def checker(tmp_path_factory):
+    # built per test process (parallel workers must not share the binary)
+    out = str(tmp_path_factory.mktemp("bin") / "reg_check")
     src = os.path.join(ROOT, "tests", "cpp", "reg_check.cpp")
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
                            "-I", os.path.join(ROOT, "paper_2605_30355_amd", "csrc"),
                            "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", src,
                            os.path.join(ROOT, "paper_2605_30355_amd", "csrc", "reg_schedule.cpp"),
-                           "-o", BIN])
-    return BIN
+                           "-o", out])
+    return out
 
 
 def run(checker, inst, method, sides, W, K):
