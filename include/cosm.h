@@ -346,6 +346,9 @@ typedef struct {
                               read and written per update instead of two) */
   int32_t streamed;        /* 1: the LDS sweep streams its lane schedule from memory, two
                               slots in flight per wave (long schedules: the large graphs) */
+  int32_t lazy_wrap;       /* 1: the streamed FP32 sweep wraps phases to [0, 1) turn only at
+                              the twists (grid schedule; the result is the same bit for
+                              bit, since no phase can drift by 1/2 turn between twists) */
 } cosm_info;
 int cosm_get_info(const cosm_state *s, cosm_info *out);
 

@@ -69,7 +69,8 @@ class _CInfo(ctypes.Structure):
                 ("sweep_launches", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double),
                 ("lds_form", ctypes.c_int32), ("register_rows", ctypes.c_int32),
                 ("twist_fused", ctypes.c_int32), ("register_vertices", ctypes.c_int32),
-                ("register_edges", ctypes.c_int64), ("streamed", ctypes.c_int32)]
+                ("register_edges", ctypes.c_int64), ("streamed", ctypes.c_int32),
+                ("lazy_wrap", ctypes.c_int32)]
 
 
 _lib = None

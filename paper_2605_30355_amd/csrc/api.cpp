@@ -428,6 +428,16 @@ int init_state(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const 
   s->h_J.assign(J, J + m);
   s->sumJ = 0;
   for (int64_t k = 0; k < m; k++) s->sumJ += J[k];
+  {
+    std::vector<int64_t> wdeg((size_t)n, 0);
+    for (int64_t k = 0; k < m; k++) {
+      const int64_t a = J[k] < 0 ? -(int64_t)J[k] : (int64_t)J[k];
+      wdeg[(size_t)eu[k]] += a;
+      wdeg[(size_t)ev[k]] += a;
+    }
+    s->wdeg_max = 0;
+    for (int64_t w : wdeg) s->wdeg_max = std::max(s->wdeg_max, w);
+  }
   if (h) s->h_h.assign(h, h + n);
   s->h_colour.assign(colour, colour + m);
 
@@ -782,6 +792,7 @@ int cosm_get_info(const cosm_state *s, cosm_info *out) {
     out->register_edges = s->lds.reg_edges;
   }
   out->streamed = s->shape.residency == COSM_RES_LDS && s->lds.stream ? 1 : 0;
+  out->lazy_wrap = lds_lazy_wrap(*s) ? 1 : 0;
   return COSM_OK;
 }
 

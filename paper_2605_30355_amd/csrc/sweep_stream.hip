@@ -80,6 +80,37 @@ __device__ __forceinline__ void row_store(uint32_t addr, const uint32_t (&w)[W])
   }
 }
 
+// Eq. (6) on an edge's two rows of FP32 phases, without the wrap to [0, 1)
+// turn (the lazy form).  On the grid schedule every phase is a multiple of
+// 2^-23 turn and every step a multiple of 2^-22; while all phases stay inside
+// (-1/2, 3/2) turn, each phase, each step result and each difference x_u - x_v
+// (|.| < 2) is exact in FP32, so fract(x_u - x_v) and every later phase mod 1
+// equal those of the wrapped form bit for bit.  The host enables this form
+// only when the phases provably stay there: between two twists (which wrap
+// every row first) a phase moves by at most period * alpha_max * (largest sum
+// of |J| at one vertex) < 1/2 turn.
+template <int W>
+__device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
+#pragma unroll
+  for (int k = 0; k < W; k++) {
+    const float xu = __uint_as_float(wu[k]), xv = __uint_as_float(wv[k]);
+    const float dl = (fract1(xu - xv) < 0.5f) ? aJ : -aJ;
+    wu[k] = __float_as_uint(xu - dl);
+    wv[k] = __float_as_uint(xv + dl);
+  }
+}
+
+// The twist on one row; the lazy form wraps the row first, so the window test
+// and the twisted value are those of the wrapped form.
+template <int ST, int W, bool LAZY>
+__device__ __forceinline__ void twist_row(const TwistOps<ST, W> &op, uint32_t (&w)[W]) {
+  if constexpr (LAZY) {
+#pragma unroll
+    for (int k = 0; k < W; k++) w[k] = __float_as_uint(fract1(__uint_as_float(w[k])));
+  }
+  op.apply(w);
+}
+
 // One slot in flight: its rows, their addresses and the step alpha_t J.
 template <int W>
 struct Slot {
@@ -88,8 +119,9 @@ struct Slot {
   float aJ;
 };
 
-template <int ST, int W, bool JU, bool FUSE>
+template <int ST, int W, bool JU, bool FUSE, bool LAZY>
 __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
+  static_assert(!LAZY || ST == COSM_STORE_FP32, "the lazy wrap is an FP32 form");
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
@@ -200,10 +232,14 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
     // Eq. (6) on the slot in set p and store; twr: the fused twist
     auto finish = [&](int p, auto twr) {
       Slot<W> &x = sl[p];
-      update_words<ST, W>(x.u, x.v, x.aJ);
+      if constexpr (LAZY) {
+        update_words_lazy<W>(x.u, x.v, x.aJ);
+      } else {
+        update_words<ST, W>(x.u, x.v, x.aJ);
+      }
       if constexpr (decltype(twr)::value) {
-        op.apply(x.u);
-        op.apply(x.v);
+        twist_row<ST, W, LAZY>(op, x.u);
+        twist_row<ST, W, LAZY>(op, x.v);
       }
       row_store<W>(x.au, x.u);
       row_store<W>(x.av, x.v);
@@ -265,7 +301,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
           if (off != kEmptySlot) {
             uint32_t w[W];
             row_load<W>(off, w);
-            op.apply(w);
+            twist_row<ST, W, LAZY>(op, w);
             row_store<W>(off, w);
           }
         }
@@ -286,7 +322,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           if (s0 + q * nth < a.n_rows) {
-            op.apply(w[q]);
+            twist_row<ST, W, LAZY>(op, w[q]);
             lds_store<W>(lds, s0 + q * nth, w[q]);
           }
         }
@@ -304,16 +340,16 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
     F::template unpack<W>(w, v);
 #pragma unroll
     for (int k = 0; k < RW; k++)
-      if (k < nvalid) F::store_elem(a.phases, base + k, v[k]);
+      if (k < nvalid) F::store_elem(a.phases, base + k, LAZY ? fract1(v[k]) : v[k]);
   }
 }
 
-template <int ST, int W, bool JU, bool FUSE>
+template <int ST, int W, bool JU, bool FUSE, bool LAZY>
 int launch_stream_k(cosm_state *s, const StreamArgs &a) {
   const size_t lds = s->shape.lds_bytes;
-  (void)hipFuncSetAttribute((const void *)k_sweep_stream<ST, W, JU, FUSE>,
+  (void)hipFuncSetAttribute((const void *)k_sweep_stream<ST, W, JU, FUSE, LAZY>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_sweep_stream<ST, W, JU, FUSE>), dim3(s->shape.blocks),
+  hipLaunchKernelGGL((k_sweep_stream<ST, W, JU, FUSE, LAZY>), dim3(s->shape.blocks),
                      dim3(s->shape.threads), lds, s->stream, a);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess)
@@ -321,14 +357,22 @@ int launch_stream_k(cosm_state *s, const StreamArgs &a) {
   return COSM_OK;
 }
 
-template <int ST, int W>
-int launch_stream_w(cosm_state *s, const StreamArgs &a) {
+template <int ST, int W, bool LAZY>
+int launch_stream_l(cosm_state *s, const StreamArgs &a) {
   const bool fuse = lds_twist_fused(*s);
   const bool ju = s->lds.junit;
-  if (ju && fuse) return launch_stream_k<ST, W, true, true>(s, a);
-  if (ju) return launch_stream_k<ST, W, true, false>(s, a);
-  if (fuse) return launch_stream_k<ST, W, false, true>(s, a);
-  return launch_stream_k<ST, W, false, false>(s, a);
+  if (ju && fuse) return launch_stream_k<ST, W, true, true, LAZY>(s, a);
+  if (ju) return launch_stream_k<ST, W, true, false, LAZY>(s, a);
+  if (fuse) return launch_stream_k<ST, W, false, true, LAZY>(s, a);
+  return launch_stream_k<ST, W, false, false, LAZY>(s, a);
+}
+
+template <int ST, int W>
+int launch_stream_w(cosm_state *s, const StreamArgs &a) {
+  if constexpr (ST == COSM_STORE_FP32) {
+    if (lds_lazy_wrap(*s)) return launch_stream_l<ST, W, true>(s, a);
+  }
+  return launch_stream_l<ST, W, false>(s, a);
 }
 
 template <int ST>
@@ -362,6 +406,16 @@ int launch_stream_st(cosm_state *s, int64_t n_sweeps) {
 }
 
 }  // namespace
+
+bool lds_lazy_wrap(const cosm_state &s) {
+  if (s.shape.residency != COSM_RES_LDS || !s.lds.stream || s.p.storage != COSM_STORE_FP32 ||
+      !s.sched.grid || s.sched.dwt_period <= 0)
+    return false;
+  // the largest step in turns, then the largest drift of one phase between
+  // two twists (exact products of small integers and a power of two)
+  const double alpha_max = (double)s.sched.a0_units * (double)s.sched.aunit;
+  return (double)s.sched.dwt_period * alpha_max * (double)s.wdeg_max < 0.5;
+}
 
 int launch_sweeps_stream(cosm_state *s, int64_t n_sweeps) {
   switch (s->p.storage) {

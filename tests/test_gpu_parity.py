@@ -222,6 +222,7 @@ def test_torus141_full_width():
     assert info["residency"] == cosm.RES_LDS and info["replicas"] == R
     assert info["replicas_per_wg"] == p.replicas_per_wg
     assert info["threads_per_wg"] == p.threads_per_wg
+    assert info["streamed"] == 1 and info["lazy_wrap"] == 1
 
 
 @pytest.mark.parametrize("order", [0, cosm.ORDER_LARGEST_LAST])

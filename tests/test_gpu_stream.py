@@ -3,7 +3,8 @@ against the oracle's grid schedules on sampled replicas: uniform and varying
 |J| (a second stream of magnitudes), classes with an odd number of slots (a
 padding slot of dummy pairs) and final pairs that only the first waves run,
 the twist fused into the last class, one, two and four FP32 replicas per
-workgroup, and the fixed-point and 16-bit storage formats."""
+workgroup, the fixed-point and 16-bit storage formats, and FP32 phases wrapped
+only at the twists (at the edge of the drift bound that keeps them exact)."""
 import numpy as np
 import pytest
 
@@ -92,3 +93,23 @@ def test_row_widths(rw):
     info = check_trial(inst, colour, C, prob, p, seed=9, R=37, sweeps=200, chunks=3,
                        sample=[0, 18, 36])
     assert info["streamed"] == 1 and info["replicas_per_wg"] == rw
+
+
+@pytest.mark.parametrize("case", [(14.9, 3, 1, 0), (14.9, 3, 1, cosm.ORDER_LARGEST_LAST),
+                                  (14.0, 4, 0, 0)],
+                         ids=["lazy-drift-0.497", "lazy-fused-twist", "eager-drift-0.622"])
+def test_lazy_wrap_bound(case):
+    """FP32 phases wrapped to [0, 1) turn only at the twists stay exact while no
+    phase can drift by 1/2 turn between two twists (period x alpha0 x 4 on a
+    +-1 torus).  alpha0 = 14.9 deg with a twist every 3 sweeps sits just inside
+    the bound (0.497 turn), also with the twist inside the last class; every 4
+    sweeps at 14 deg lies outside it (0.622) and keeps the wrap at every update.
+    All bit-exact against the oracle."""
+    a0, T, lazy, order = case
+    inst = ci.torus(101, seed=9)
+    colour, C, prob = make(inst, cosm.COLOR_TORUS | order, [101, 101])
+    p = cosm.Params(alpha0_deg=a0, sweeps_per_trial=300, dwt_ratio=0.5, dwt_period=T,
+                    replicas_per_wg=2, threads_per_wg=1024, residency=cosm.RES_LDS)
+    info = run_case(inst, colour, C, prob, p, 11, 64, 300, [0, 31, 63])
+    assert info["lazy_wrap"] == lazy
+    assert info["twist_fused"] == (1 if order else 0)
