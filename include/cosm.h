@@ -97,7 +97,13 @@ enum { COSM_SCHED_GRID = 0, COSM_SCHED_CONTINUOUS = 1 };
  * (the large even tori) and loses on the 3-regular benchmark graph.  AUTO:
  * when the shape is autotuned both layouts are timed and the faster kept;
  * otherwise PAIR. */
-enum { COSM_LDS_FORM_AUTO = 0, COSM_LDS_FORM_PAIR = 1, COSM_LDS_FORM_REGISTER = 2 };
+enum {
+  COSM_LDS_FORM_AUTO = 0,
+  COSM_LDS_FORM_PAIR = 1,
+  COSM_LDS_FORM_REGISTER = 2,
+  COSM_LDS_FORM_REGISTER_STREAM = 3 /* register owners with a streamed schedule: FP32, no bias
+                                       fields, up to 32 classes (the large graphs) */
+};
 /* SCS: Eqs. (12)-(13), classes one after another.  FULL_GRADIENT: Eq. (8), all
  * edges read the same state (the "without SCS" variant of Table VII). */
 enum { COSM_UPDATE_SCS = 0, COSM_UPDATE_FULL_GRADIENT = 1 };
@@ -348,7 +354,8 @@ typedef struct {
                               slots in flight per wave (long schedules: the large graphs) */
   int32_t lazy_wrap;       /* 1: the streamed FP32 sweep wraps phases to [0, 1) turn only at
                               the twists (grid schedule; the result is the same bit for
-                              bit, since no phase can drift by 1/2 turn between twists) */
+                              bit, since no phase can drift by 1/2 turn between twists:
+                              twist + period x alpha0 x largest sum of |J| < 1/2 turn) */
 } cosm_info;
 int cosm_get_info(const cosm_state *s, cosm_info *out);
 

@@ -8,7 +8,7 @@ and the HIP stream.  Importing the package does not touch the GPU; creating a
 """
 from .cosm import (  # noqa: F401
     COLOR_BALANCED, COLOR_GREEDY, COLOR_MINIMUM, COLOR_MISRA_GRIES, COLOR_TORUS,
-    LDS_FORM_AUTO, LDS_FORM_PAIR, LDS_FORM_REGISTER,
+    LDS_FORM_AUTO, LDS_FORM_PAIR, LDS_FORM_REGISTER, LDS_FORM_REGISTER_STREAM,
     ORDER_LARGEST_LAST,
     RES_AUTO, RES_HBM, RES_LDS, RES_PLAIN,
     READOUT_BISECTORS, READOUT_OPTIMAL,

@@ -21,7 +21,7 @@ SCHED_GRID, SCHED_CONTINUOUS = 0, 1
 UPDATE_SCS, UPDATE_FULL_GRADIENT = 0, 1
 READOUT_BISECTORS, READOUT_OPTIMAL = 0, 1
 UNIT_TURNS, UNIT_DEGREES, UNIT_RADIANS = 0, 1, 2
-LDS_FORM_AUTO, LDS_FORM_PAIR, LDS_FORM_REGISTER = 0, 1, 2
+LDS_FORM_AUTO, LDS_FORM_PAIR, LDS_FORM_REGISTER, LDS_FORM_REGISTER_STREAM = 0, 1, 2, 3
 
 # Every function declared in include/cosm.h.
 ABI_FUNCTIONS = (

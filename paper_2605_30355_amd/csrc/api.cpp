@@ -32,7 +32,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every device buffer inside one allocation.
 struct MemPlan {
-  size_t phases, desc, jmag, class_off, slot_vertex, reg_vertex, h_slot, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
+  size_t phases, desc, jmag, class_off, slot_vertex, reg_vertex, rs_words, rs_pwords, rs_act, h_slot, eu, ev, J, h, peu, pev, pJ, spins, H, cut, best_p,
       inc_off, inc_nbr, inc_J, phases_alt, opt_keys, opt_keys2, opt_vals, opt_vals2, opt_off,
       opt_temp, opt_temp_bytes, codes, total;
 };
@@ -58,7 +58,11 @@ MemPlan plan_memory(int32_t n, int64_t m, int32_t C, int32_t R, const cosm_param
   mp.jmag = take(pair_desc * 4);
   mp.class_off = take(((size_t)2 * C + 1) * 4);
   mp.slot_vertex = take(((size_t)n + kRegRowsSlack) * 4);
-  mp.reg_vertex = take((size_t)kRegKMax * 1024 * 4);
+  mp.reg_vertex = take((size_t)kRStreamKMax * 1024 * 4);
+  const size_t rs_classes = (size_t)std::min(C, kRStreamClassesMax);
+  mp.rs_words = take(rs_classes * kRStreamKMax * 1024 * 8);
+  mp.rs_pwords = take(rs_classes * kRStreamPairs * 1024 * 8);
+  mp.rs_act = take(rs_classes * 16 * 4);
   mp.h_slot = take(((size_t)n + 1) * 4);
   mp.eu = take((size_t)m * 4);
   mp.ev = take((size_t)m * 4);
@@ -116,7 +120,7 @@ int check_params(const cosm_params *p) {
     return bad("FIX32 storage needs the GRID schedule");
   if (p->residency < COSM_RES_AUTO || p->residency > COSM_RES_PLAIN) return bad("bad residency");
   if (p->update != COSM_UPDATE_SCS && p->update != COSM_UPDATE_FULL_GRADIENT) return bad("bad update");
-  if (p->lds_form < COSM_LDS_FORM_AUTO || p->lds_form > COSM_LDS_FORM_REGISTER)
+  if (p->lds_form < COSM_LDS_FORM_AUTO || p->lds_form > COSM_LDS_FORM_REGISTER_STREAM)
     return bad("bad lds_form");
   if (p->readout != COSM_READOUT_BISECTORS && p->readout != COSM_READOUT_OPTIMAL)
     return bad("bad readout");
@@ -244,6 +248,10 @@ int choose_shape(cosm_state *s) {
         if (int rc = pick_reg_schedule(s, chosen, p.threads_per_wg)) return rc;
         sh.threads = s->lds.nth;
         sh.lds_bytes = (int32_t)lds_sweep_bytes(s->lds.n_rows, chosen, s->C);
+      } else if (p.lds_form == COSM_LDS_FORM_REGISTER_STREAM) {
+        if (int rc = rstream_schedule_for(*s, chosen, p.threads_per_wg, &s->lds)) return rc;
+        sh.threads = s->lds.nth;
+        sh.lds_bytes = (int32_t)rstream_lds_bytes(s->lds, chosen, s->C);
       }
     }
   }
@@ -518,6 +526,9 @@ int init_state(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const 
   d.jmag = at<float>(s->base, mp.jmag);
   d.slot_vertex = at<int32_t>(s->base, mp.slot_vertex);
   d.reg_vertex = at<int32_t>(s->base, mp.reg_vertex);
+  d.rs_words = at<uint32_t>(s->base, mp.rs_words);
+  d.rs_pwords = at<uint32_t>(s->base, mp.rs_pwords);
+  d.rs_act = at<uint32_t>(s->base, mp.rs_act);
   d.h_slot = at<int32_t>(s->base, mp.h_slot);
   d.eu = at<int32_t>(s->base, mp.eu);
   d.ev = at<int32_t>(s->base, mp.ev);
@@ -781,6 +792,7 @@ int cosm_get_info(const cosm_state *s, cosm_info *out) {
   out->sweep_launches = s->launches;
   out->sweep_kernel_ms = s->kernel_ms;
   out->lds_form = s->shape.residency != COSM_RES_LDS ? 0
+                  : s->lds.rstream                   ? COSM_LDS_FORM_REGISTER_STREAM
                   : s->lds.reg_k > 0                 ? COSM_LDS_FORM_REGISTER
                                                      : COSM_LDS_FORM_PAIR;
   out->register_rows = s->shape.residency == COSM_RES_LDS ? s->lds.reg_k : 0;
@@ -791,7 +803,7 @@ int cosm_get_info(const cosm_state *s, cosm_info *out) {
     for (int32_t v : s->lds.reg_vertex) out->register_vertices += v >= 0 ? 1 : 0;
     out->register_edges = s->lds.reg_edges;
   }
-  out->streamed = s->shape.residency == COSM_RES_LDS && s->lds.stream ? 1 : 0;
+  out->streamed = s->shape.residency == COSM_RES_LDS && (s->lds.stream || s->lds.rstream) ? 1 : 0;
   out->lazy_wrap = lds_lazy_wrap(*s) ? 1 : 0;
   return COSM_OK;
 }

@@ -3,9 +3,10 @@
 // Candidates: every LDS row width that fits (1, 2 or 4 words per row, i.e. 1-4
 // FP32 or 2-8 16-bit replicas per workgroup) crossed with a few thread counts
 // (pair layout; a long schedule in both streamed forms: the word form with two
-// slots in flight per wave, and the classic one), and with 1, 2 or 4 register
-// rows per thread (register layout, where it applies; only these when it is
-// requested).
+// slots in flight per wave, and the classic one), with 1, 2 or 4 register
+// rows per thread (register layout, where it applies), and the streamed
+// register-owner form (FP32; 512 to 1024 threads); a requested layout
+// restricts the candidates to its own.
 // Each candidate runs a short timed probe on the state's own phases (which are
 // re-drawn afterwards, so the probe leaves no trace in the trajectory), and the
 // fastest shape is kept.  Results are cached per process, keyed by the
@@ -28,8 +29,9 @@ namespace {
 // FNV-1a hash of the edge list and its colouring (the schedules are built from
 // exactly these, so two instances with the same key accept the same shapes).
 using Key = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t, uint64_t>;
-// (W, threads, register rows or 0, 1 = the classic streamed schedule instead of
-// the streamed word form)
+// (W, threads, register rows (kShapeRStream: the streamed register-owner form,
+// 0: the pair form), 1 = the classic streamed schedule instead of the streamed
+// word form)
 using Shape = std::tuple<int32_t, int32_t, int32_t, int32_t>;
 std::mutex g_cache_mu;
 std::map<Key, Shape> g_cache;
@@ -48,17 +50,24 @@ Key make_key(const cosm_state &s) {
 }
 
 
+// K > 0: the register form with K rows; K = kShapeRStream: the streamed
+// register-owner form; 0: the pair form.
+constexpr int32_t kShapeRStream = -1;
+
 int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw, int32_t K,
                 int32_t classic = 0) {
   if (K > 0) {
     if (int rc = reg_schedule_for(*s, W, K, nth, &s->lds)) return rc;
+  } else if (K == kShapeRStream) {
+    if (int rc = rstream_schedule_for(*s, W, nth, &s->lds)) return rc;
   } else {
     if (int rc = build_lds_schedule(*s, W, nth, &s->lds, true, classic == 0)) return rc;
   }
   s->shape.residency = COSM_RES_LDS;
   s->shape.rw = W * pw;
   s->shape.blocks = (s->R + s->shape.rw - 1) / s->shape.rw;
-  s->shape.lds_bytes = (int32_t)lds_sweep_bytes(K > 0 ? s->lds.n_rows : s->n_slots, W, s->C);
+  s->shape.lds_bytes = (int32_t)(K == kShapeRStream ? rstream_lds_bytes(s->lds, W, s->C)
+                                 : lds_sweep_bytes(K > 0 ? s->lds.n_rows : s->n_slots, W, s->C));
   s->shape.threads = s->lds.nth;
   return upload_lds_schedule(s);
 }
@@ -67,6 +76,20 @@ int apply_shape(cosm_state *s, int32_t W, int32_t nth, int32_t pw, int32_t K,
 
 int upload_lds_schedule(cosm_state *s) {
   const LdsSchedule &L = s->lds;
+  if (L.rstream) {
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.rs_words, L.rs_words.data(), L.rs_words.size() * 4,
+                                  hipMemcpyHostToDevice, s->stream));
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.rs_pwords, L.rs_pwords.data(), L.rs_pwords.size() * 4,
+                                  hipMemcpyHostToDevice, s->stream));
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.rs_act, L.rs_act.data(), L.rs_act.size() * 4,
+                                  hipMemcpyHostToDevice, s->stream));
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.slot_vertex, L.slot_vertex.data(),
+                                  L.slot_vertex.size() * 4, hipMemcpyHostToDevice, s->stream));
+    COSM_HIP_CHECK(hipMemcpyAsync(s->d.reg_vertex, L.reg_vertex.data(), L.reg_vertex.size() * 4,
+                                  hipMemcpyHostToDevice, s->stream));
+    COSM_HIP_CHECK(hipStreamSynchronize(s->stream));  // host vectors may change next
+    return COSM_OK;
+  }
   if (L.stream) {
     COSM_HIP_CHECK(hipMemcpyAsync(s->d.desc, L.sdesc.data(), L.sdesc.size() * 4,
                                   hipMemcpyHostToDevice, s->stream));
@@ -122,6 +145,22 @@ int reg_schedule_for(const cosm_state &s, int32_t W, int32_t K, int32_t nth, Lds
   return COSM_OK;
 }
 
+int rstream_schedule_for(const cosm_state &s, int32_t W, int32_t nth, LdsSchedule *out) {
+  if (s.p.storage != COSM_STORE_FP32 || s.has_h || s.C > kRStreamClassesMax || s.m == 0 ||
+      s.p.update != COSM_UPDATE_SCS)
+    return set_error(COSM_ERANGE, "the streamed register form needs FP32 storage, at most 32 "
+                                  "classes, edges and no bias fields");
+  LdsSchedule L;
+  if (int rc = build_rstream_schedule(s, W, nth, &L)) return rc;
+  if (!rstream_shape_supported(s.p.storage, W, L.reg_k))
+    return set_error(COSM_ERANGE, "streamed register form: no kernel for this row width and "
+                                  "register count");
+  if (rstream_lds_bytes(L, W, s.C) > (size_t)lds_capacity_bytes())
+    return set_error(COSM_ERANGE, "streamed register form: rows do not fit in LDS");
+  *out = std::move(L);
+  return COSM_OK;
+}
+
 // The register form for a fixed row width: the fewest register rows per
 // thread that hold the whole independent set (with a thread count given,
 // the set may need 2 or 4 rows per thread), else the most that give one.
@@ -171,13 +210,19 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
   // candidates: (W, requested threads, register rows); pair form first
   std::vector<Shape> cands;
   // (the pair form with a long schedule is timed in both streamed forms)
-  if (s->p.lds_form != COSM_LDS_FORM_REGISTER)
+  const int32_t form = s->p.lds_form;
+  if (form == COSM_LDS_FORM_AUTO || form == COSM_LDS_FORM_PAIR)
     for (int32_t W : widths)
       for (int32_t req : {0, 512, 768, 1024})
         for (int32_t classic : {0, 1}) cands.emplace_back(W, req, 0, classic);
-  if (s->p.lds_form != COSM_LDS_FORM_PAIR && reg_form_supported(*s))
+  if ((form == COSM_LDS_FORM_AUTO || form == COSM_LDS_FORM_REGISTER) && reg_form_supported(*s))
     for (int32_t W : widths)
       for (int32_t K : {1, 2, 4}) cands.emplace_back(W, 0, K, 0);
+  // (fewer threads hold more register rows each, and may leave room for a
+  // second workgroup per CU)
+  if (form == COSM_LDS_FORM_AUTO || form == COSM_LDS_FORM_REGISTER_STREAM)
+    for (int32_t W : widths)
+      for (int32_t req : {1024, 768, 640, 512}) cands.emplace_back(W, req, kShapeRStream, 0);
   std::vector<Shape> tried;
   int32_t auto_nth = 0;
   for (const Shape &cand : cands) {
@@ -185,7 +230,7 @@ int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths) {
     const int32_t classic = std::get<3>(cand);
     if (K == 0 && req > 0 && req < auto_nth / 2) continue;  // far too few threads for one pass
     rc = apply_shape(s, W, req, pw, K, classic);
-    if (rc && K > 0) {  // the register form does not apply to this shape
+    if (rc && K != 0) {  // a register form does not apply to this shape
       rc = COSM_OK;
       clear_error();
       continue;

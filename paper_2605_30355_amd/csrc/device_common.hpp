@@ -423,6 +423,41 @@ __device__ __forceinline__ void lds_store_at(uint32_t *base, uint32_t byte, cons
   }
 }
 
+typedef uint32_t su2 __attribute__((ext_vector_type(2)));
+// Row access at an absolute LDS byte address, for kernels whose only LDS is
+// the dynamic allocation (which then starts at address 0), so that a row's
+// byte offset is its address (clang vector types: the HIP vector classes do
+// not take an address-space qualifier).
+typedef uint32_t su4 __attribute__((ext_vector_type(4)));
+template <int W>
+__device__ __forceinline__ void row_load(uint32_t addr, uint32_t (&w)[W]) {
+  if constexpr (W == 4) {
+    typedef __attribute__((address_space(3))) const su4 *P;
+    const su4 q = *(P)(uintptr_t)addr;
+    w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+  } else if constexpr (W == 2) {
+    typedef __attribute__((address_space(3))) const su2 *P;
+    const su2 q = *(P)(uintptr_t)addr;
+    w[0] = q.x; w[1] = q.y;
+  } else {
+    typedef __attribute__((address_space(3))) const uint32_t *P;
+    w[0] = *(P)(uintptr_t)addr;
+  }
+}
+template <int W>
+__device__ __forceinline__ void row_store(uint32_t addr, const uint32_t (&w)[W]) {
+  if constexpr (W == 4) {
+    typedef __attribute__((address_space(3))) su4 *P;
+    *(P)(uintptr_t)addr = su4{w[0], w[1], w[2], w[3]};
+  } else if constexpr (W == 2) {
+    typedef __attribute__((address_space(3))) su2 *P;
+    *(P)(uintptr_t)addr = su2{w[0], w[1]};
+  } else {
+    typedef __attribute__((address_space(3))) uint32_t *P;
+    *(P)(uintptr_t)addr = w[0];
+  }
+}
+
 // Eq. (6) on the W words of an edge's two rows (every replica they hold); aJ
 // is alpha_t J in turns times Fmt<ST>::kStepScale.
 // FIX16: two replicas per word in 16-bit lanes, packed integer arithmetic; the
@@ -621,6 +656,24 @@ struct TwistOps<COSM_STORE_FIX16, W> {
     }
   }
 };
+
+// The twist on one row.  LAZY (FP32 phases wrapped only at the twists): the
+// row is wrapped first, so the window test is that of the wrapped form, and
+// the twisted value x + twist is left unwrapped (it is at most the twist
+// above 1 turn; the host's drift bound counts it).
+template <int ST, int W, bool LAZY>
+__device__ __forceinline__ void twist_row(const TwistOps<ST, W> &op, uint32_t (&w)[W]) {
+  if constexpr (LAZY) {
+    static_assert(ST == COSM_STORE_FP32, "the lazy wrap is an FP32 form");
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      const float x = fract1(__uint_as_float(w[k]));
+      w[k] = __float_as_uint(in_windows(x, op.c[k], op.win2) ? x + op.t[k] : x);
+    }
+  } else {
+    op.apply(w);
+  }
+}
 
 // The twist on the W words of one row.  FIX16: packed 16-bit integers; with
 // t = (2x - c) mod 1 turn in 16-bit lanes, a lane is in the windows iff

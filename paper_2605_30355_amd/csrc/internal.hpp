@@ -136,6 +136,24 @@ struct LdsSchedule {
   std::vector<uint32_t> sdesc;
   std::vector<float> sjmag;
   std::vector<int32_t> last_lanes;
+  // Streamed register-owner form (rstream = true; the large graphs): reg_k
+  // (8, 10, 12 or 16) register rows per thread as above, with the schedule
+  // streamed from memory instead of held in registers.  Only the classes in
+  // which at least half of the register set has an edge have register slots
+  // (register classes); a vertex with an edge in another class stays in LDS.
+  // rs_words [register classes][reg_k][nth][2]: per register slot (row byte
+  // offset of the LDS endpoint | flip << 31, J as a float, 0 for a lane
+  // without an edge there, whose row is then a dummy row); rs_pwords
+  // [C][kRStreamPairs][nth][2]: up to kRStreamPairs slots of edges between two
+  // LDS rows per class (u row offset | J << 18, v row offset; |J| < 2^13),
+  // dummy-row pairs with J = 0 where a lane has none; rs_act [C][nth / 64]:
+  // per class and wave, bit 0 set in a register class and bit 1 + p when pair
+  // slot p holds an edge in some lane of the wave (a wave skips the others).
+  // Row offsets are below 2^18 bytes.
+  bool rstream = false;
+  std::vector<uint32_t> rs_words;
+  std::vector<uint32_t> rs_pwords;
+  std::vector<uint32_t> rs_act;
   int32_t reg_k = 0;
   int32_t reg_free = 0;
   std::vector<int32_t> reg_vertex;
@@ -144,6 +162,11 @@ struct LdsSchedule {
   int64_t reg_conflicts = 0;    // lane groups whose rows share a bank (extra LDS cycles)
 };
 constexpr int32_t kRegKMax = 4;
+// Streamed register-owner form: register rows per thread (one of 8, 12, 16),
+// pair slots per class, classes.
+constexpr int32_t kRStreamKMax = 16;
+constexpr int32_t kRStreamPairs = 4;
+constexpr int32_t kRStreamClassesMax = 32;
 constexpr int32_t kRegClassesMax = 8;
 constexpr int32_t kRegRowsSlack = 4096;  // slot_vertex capacity beyond n
 constexpr int32_t kRegisterSlotsMax = 16;  // schedules this short stay in registers
@@ -161,7 +184,10 @@ struct DeviceBuffers {
   int32_t *class_off = nullptr; // [2C + 1]: slots per class, then (streamed form) last_lanes
   float *jmag = nullptr;        // streamed word form: |J| per schedule entry (non-uniform |J|)
   int32_t *slot_vertex = nullptr; // [n_slots] vertex held by each LDS slot
-  int32_t *reg_vertex = nullptr;  // [kRegKMax * 1024] register-owner form
+  int32_t *reg_vertex = nullptr;  // [kRStreamKMax * 1024] register-owner forms
+  uint32_t *rs_words = nullptr;   // streamed register-owner form: its three tables
+  uint32_t *rs_pwords = nullptr;
+  uint32_t *rs_act = nullptr;
   int32_t *h_slot = nullptr;    // [n_slots] bias field of the vertex in each slot (with h)
   int32_t *eu = nullptr;        // [m] (original ids)
   int32_t *ev = nullptr;
@@ -282,12 +308,25 @@ int launch_sweeps_stream(cosm_state *s, int64_t n_sweeps);
 // than one slot per class holds, too many rows).
 int build_reg_schedule(const cosm_state &s, int32_t W, int32_t K, int32_t nth_request,
                        LdsSchedule *out);
+// The streamed register-owner schedule (reg_k = 8, 12 or 16 register rows per
+// thread, the fewest that hold the independent set, at most kRStreamKMax).
+int build_rstream_schedule(const cosm_state &s, int32_t W, int32_t nth_request,
+                           LdsSchedule *out);
+// The LDS bytes of the streamed register-owner sweep for a schedule.
+size_t rstream_lds_bytes(const LdsSchedule &L, int W, int32_t C);
+// Whether the streamed register-owner kernel exists for this storage, row
+// width and register count (sweep_rstream.hip).
+bool rstream_shape_supported(int32_t storage, int32_t W, int32_t K);
+int launch_sweeps_rstream(cosm_state *s, int64_t n_sweeps);
 // Whether the register form applies (storage, classes, fields, update), a
 // register schedule checked against the LDS capacity, and the fewest register
 // rows per thread that give one for row width W.
 bool reg_form_supported(const cosm_state &s);
 int reg_schedule_for(const cosm_state &s, int32_t W, int32_t K, int32_t nth, LdsSchedule *out);
 int pick_reg_schedule(cosm_state *s, int32_t W, int32_t nth);
+// The streamed register-owner schedule checked against the kernels that exist
+// and the LDS capacity.
+int rstream_schedule_for(const cosm_state &s, int32_t W, int32_t nth, LdsSchedule *out);
 // Measure candidate LDS shapes (row widths in words) and keep the fastest.
 int autotune_lds_shape(cosm_state *s, const std::vector<int32_t> &widths);
 // Uploads the bias field in LDS-slot order (no-op without bias fields).

@@ -1088,6 +1088,7 @@ template <int ST> struct SweepFn {
     switch (s->shape.residency) {
       case COSM_RES_LDS:
         if (s->lds.stream) return launch_sweeps_stream(s, n);
+        if (s->lds.rstream) return launch_sweeps_rstream(s, n);
         return sweeps_lds_st<ST>(s, n);
       case COSM_RES_HBM: return sweeps_hbm_st<ST>(s, n);
       case COSM_RES_PLAIN: return sweeps_plain_st<ST>(s, n);

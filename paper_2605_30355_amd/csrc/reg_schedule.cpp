@@ -26,6 +26,7 @@
 // The class order and the edge set per class are unchanged: only which thread
 // applies an update, and in which register or LDS row the phases sit, differ.
 #include <algorithm>
+#include <map>
 #include <numeric>
 
 #include "internal.hpp"
@@ -116,18 +117,54 @@ void greedy_independent(int32_t n, const std::vector<std::vector<Adj>> &adj,
 
 inline uint64_t bit(int32_t r) { return 1ull << r; }
 
-// One attempt.  pre: every LDS vertex takes residue (its rank among the LDS
-// vertices, in vertex order) mod G before the packing, which keeps lattice
-// neighbourhoods aligned; otherwise residues are chosen during the packing.
-int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_request, bool pre,
-                   LdsSchedule *out) {
-  const int32_t n = s.n, C = s.C;
+// Options of one attempt.  pre: every LDS vertex takes residue (its rank among
+// the LDS vertices, in vertex order) mod G before the packing, which keeps
+// lattice neighbourhoods aligned; otherwise residues are chosen during the
+// packing.  rstream: the streamed form (up to kRStreamKMax register rows and
+// kRStreamPairs pair slots per class, and its own encoding); the register
+// vertices are then ordered by their pattern (the classes they have an edge
+// in, and those where they are the edge's v), most common pattern first, so
+// that vertices with the same pattern share waves and a class leaves the
+// register slots of the rare patterns (the seams of an odd torus) to a few
+// waves.
+struct RegOptions {
+  int32_t W = 0, K = 0, nth_request = 0;
+  bool pre = false;
+  bool rstream = false;
+};
+
+// One lane's entry in a register slot: the LDS endpoint's row (or a dummy
+// row), whether the register vertex is the edge's v, and J (0: no edge).
+struct RegEntry {
+  int32_t row = 0;
+  bool flip = false;
+  int32_t J = 0;
+};
+// One lane's entry in a pair slot (rows of u and v, J; 0: dummy rows).
+struct PairEntry {
+  int32_t ru = 0, rv = 0;
+  int32_t J = 0;
+};
+
+int build_reg_impl(const cosm_state &s, const RegOptions &o, LdsSchedule *out) {
+  const int32_t n = s.n, C = s.C, W = o.W, K = o.K;
   const int64_t m = s.m;
+  const int32_t P = o.rstream ? kRStreamPairs : 1;  // pair slots per class
   if (W != 1 && W != 2 && W != 4) return set_error(COSM_EINVAL, "bad row width");
-  if (K < 1 || K > kRegKMax) return set_error(COSM_EINVAL, "bad register count");
-  if (C > kRegClassesMax) return set_error(COSM_ERANGE, "too many classes for the register form");
+  if (K < 1 || K > (o.rstream ? kRStreamKMax : kRegKMax))
+    return set_error(COSM_EINVAL, "bad register count");
+  if (C > (o.rstream ? kRStreamClassesMax : kRegClassesMax))
+    return set_error(COSM_ERANGE, "too many classes for the register form");
   if (s.has_h) return set_error(COSM_ERANGE, "the register form runs without bias fields");
   if (m == 0) return set_error(COSM_ERANGE, "no edges");
+  if (o.rstream) {
+    // the pair slots' words hold J in 14 bits and row offsets in 18
+    for (int64_t k = 0; k < m; k++)
+      if (s.h_J[(size_t)k] >= 8192 || s.h_J[(size_t)k] < -8192)
+        return set_error(COSM_ERANGE, "the streamed register form needs |J| < 2^13");
+    if ((size_t)(n + kRegRowsSlack) * 4 * W > ((size_t)1 << 18))
+      return set_error(COSM_ERANGE, "the streamed register form needs rows below 2^18 bytes");
+  }
   const int32_t G = W == 1 ? 32 : 64 / W;  // lanes and residues of a read group
   const int32_t H = 32 / W;                // lanes and residues of a write half
 
@@ -144,7 +181,7 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
   std::vector<int32_t> cand;
   for (int32_t v = 0; v < n; v++)
     if (inI[(size_t)v]) cand.push_back(v);
-  int32_t nth = nth_request;
+  int32_t nth = o.nth_request;
   if (nth <= 0) {
     const int64_t need = ((int64_t)cand.size() + K - 1) / K;
     nth = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(64, (need + 63) / 64 * 64));
@@ -160,6 +197,52 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
     for (size_t i = (size_t)cap; i < cand.size(); i++) inI[(size_t)cand[i]] = 0;
     cand.resize((size_t)cap);
     std::sort(cand.begin(), cand.end());
+  }
+  std::vector<uint8_t> rclass((size_t)C, 1);  // classes with register slots
+  if (o.rstream) {
+    // The streamed form runs a class's register slots on every wave or on
+    // none: only classes where at least half of the register set has an edge
+    // get them, and a vertex with an edge in another class (the seams of an
+    // odd torus) goes back to LDS.
+    for (int iter = 0; iter < 8; iter++) {
+      std::vector<int64_t> cnt((size_t)C, 0);
+      for (int32_t v : cand)
+        for (const Adj &a : adj[(size_t)v]) cnt[(size_t)a.cls]++;
+      bool changed = false;
+      for (int32_t c = 0; c < C; c++) {
+        const uint8_t r = cnt[(size_t)c] * 2 >= (int64_t)cand.size() ? 1 : 0;
+        if (r != rclass[(size_t)c]) changed = true;
+        rclass[(size_t)c] = r;
+      }
+      std::vector<int32_t> keep;
+      for (int32_t v : cand) {
+        bool ok = true;
+        for (const Adj &a : adj[(size_t)v])
+          if (!rclass[(size_t)a.cls]) ok = false;
+        if (ok) keep.push_back(v);
+        else inI[(size_t)v] = 0;
+      }
+      if (keep.size() != cand.size()) changed = true;
+      cand.swap(keep);
+      if (!changed) break;
+    }
+    if (cand.empty()) return set_error(COSM_ERANGE, "no register set for the streamed form");
+    std::vector<uint64_t> pattern((size_t)n, 0);
+    std::map<uint64_t, int64_t> freq;
+    for (int32_t v : cand) {
+      uint64_t sig = 0, flips = 0;
+      for (const Adj &a : adj[(size_t)v]) {
+        sig |= 1ull << a.cls;
+        if (s.h_ev[(size_t)a.edge] == v) flips |= 1ull << a.cls;
+      }
+      pattern[(size_t)v] = sig << 32 | flips;
+      freq[pattern[(size_t)v]]++;
+    }
+    std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+      const uint64_t pa = pattern[(size_t)a], pb = pattern[(size_t)b];
+      const int64_t fa = freq[pa], fb = freq[pb];
+      return fa != fb ? fa > fb : pa < pb;
+    });
   }
 
   // 2. pack the register vertices into lane groups, choosing residues
@@ -179,7 +262,7 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
     }
     return best;
   };
-  if (pre) {
+  if (o.pre) {
     int32_t rank = 0;
     for (int32_t v = 0; v < n; v++) {
       if (inI[(size_t)v]) continue;
@@ -241,7 +324,7 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
     else reg_edges += (int64_t)adj[(size_t)v].size();
   }
 
-  // 3. edges between two LDS rows: one slot per class
+  // 3. edges between two LDS rows: P slots per class
   std::vector<std::vector<int32_t>> free_edges((size_t)C);
   for (int64_t k = 0; k < m; k++) {
     const int32_t u = s.h_eu[(size_t)k], v = s.h_ev[(size_t)k];
@@ -249,61 +332,75 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
   }
   int32_t reg_free = 0;
   for (int32_t c = 0; c < C; c++) {
-    if ((int64_t)free_edges[(size_t)c].size() > nth)
+    if ((int64_t)free_edges[(size_t)c].size() > (int64_t)P * nth)
       return set_error(COSM_ERANGE, "too many edges outside the register set");
     if (!free_edges[(size_t)c].empty()) reg_free = 1;
   }
-  // per class: lane of each free edge; u-rows and v-rows conflict-free per group
-  std::vector<int32_t> free_at((size_t)C * nth, -1);
-  std::vector<uint64_t> fG((size_t)C * groups_per_k * 2, 0), fH((size_t)C * groups_per_k * 4, 0);
+  // per class and pair slot: lane of each free edge; u-rows and v-rows
+  // conflict-free per group (masks per class, slot and group; halves apart)
+  const size_t nps = (size_t)C * P;  // (class, pair slot) pairs
+  std::vector<int32_t> free_at(nps * nth, -1);
+  std::vector<uint64_t> fG(nps * groups_per_k * 2, 0), fH(nps * groups_per_k * 4, 0);
+  auto fmask = [&](size_t cp, int32_t tg, int32_t half, uint64_t **gU, uint64_t **gV,
+                   uint64_t **hU, uint64_t **hV) {
+    *gU = &fG[(cp * groups_per_k + tg) * 2];
+    *gV = *gU + 1;
+    *hU = &fH[((cp * groups_per_k + tg) * 2 + half) * 2];
+    *hV = *hU + 1;
+  };
   int64_t conflicts = 0;
   for (int32_t c = 0; c < C; c++) {
     std::vector<int32_t> &list = free_edges[(size_t)c];
     std::vector<uint8_t> done(list.size(), 0);
     size_t left = list.size();
-    for (int32_t tg = 0; tg < groups_per_k && left > 0; tg++) {
-      for (int32_t p = 0; p < G && left > 0; p++) {
-        const int32_t half = p / H;
-        uint64_t *gU = &fG[((size_t)c * groups_per_k + tg) * 2], *gV = gU + 1;
-        uint64_t *hU = &fH[(((size_t)c * groups_per_k + tg) * 2 + half) * 2], *hV = hU + 1;
-        int32_t chosen = -1;
-        for (size_t i = 0; i < list.size(); i++) {
-          if (done[i]) continue;
-          const int32_t e = list[i];
-          const int32_t u = s.h_eu[(size_t)e], v = s.h_ev[(size_t)e];
-          const int32_t ru = res[(size_t)u], rv = res[(size_t)v];
-          const bool uok = ru >= 0 ? !(((*gU >> ru) & 1u) || ((*hU >> (ru % H)) & 1u))
-                                   : pick_free(*gU, *hU) >= 0;
-          const bool vok = rv >= 0 ? !(((*gV >> rv) & 1u) || ((*hV >> (rv % H)) & 1u))
-                                   : pick_free(*gV, *hV) >= 0;
-          if (uok && vok) {
-            chosen = (int32_t)i;
-            break;
+    for (int32_t ps = 0; ps < P && left > 0; ps++) {
+      const size_t cp = (size_t)c * P + ps;
+      for (int32_t tg = 0; tg < groups_per_k && left > 0; tg++) {
+        for (int32_t p = 0; p < G && left > 0; p++) {
+          const int32_t half = p / H;
+          uint64_t *gU, *gV, *hU, *hV;
+          fmask(cp, tg, half, &gU, &gV, &hU, &hV);
+          int32_t chosen = -1;
+          for (size_t i = 0; i < list.size(); i++) {
+            if (done[i]) continue;
+            const int32_t e = list[i];
+            const int32_t u = s.h_eu[(size_t)e], v = s.h_ev[(size_t)e];
+            const int32_t ru = res[(size_t)u], rv = res[(size_t)v];
+            const bool uok = ru >= 0 ? !(((*gU >> ru) & 1u) || ((*hU >> (ru % H)) & 1u))
+                                     : pick_free(*gU, *hU) >= 0;
+            const bool vok = rv >= 0 ? !(((*gV >> rv) & 1u) || ((*hV >> (rv % H)) & 1u))
+                                     : pick_free(*gV, *hV) >= 0;
+            if (uok && vok) {
+              chosen = (int32_t)i;
+              break;
+            }
           }
+          if (chosen < 0) continue;  // leave this lane for a dummy
+          done[(size_t)chosen] = 1;
+          left--;
+          const int32_t e = list[(size_t)chosen];
+          free_at[cp * nth + tg * G + p] = e;
+          int32_t &ru = res[(size_t)s.h_eu[(size_t)e]];
+          if (ru < 0) { ru = pick_free(*gU, *hU); load[(size_t)ru]++; }
+          *gU |= bit(ru); *hU |= bit(ru % H);
+          int32_t &rv = res[(size_t)s.h_ev[(size_t)e]];
+          if (rv < 0) { rv = pick_free(*gV, *hV); load[(size_t)rv]++; }
+          *gV |= bit(rv); *hV |= bit(rv % H);
         }
-        if (chosen < 0) continue;  // leave this lane for a dummy
-        done[(size_t)chosen] = 1;
-        left--;
-        const int32_t e = list[(size_t)chosen];
-        free_at[(size_t)c * nth + tg * G + p] = e;
-        int32_t &ru = res[(size_t)s.h_eu[(size_t)e]];
-        if (ru < 0) { ru = pick_free(*gU, *hU); load[(size_t)ru]++; }
-        *gU |= bit(ru); *hU |= bit(ru % H);
-        int32_t &rv = res[(size_t)s.h_ev[(size_t)e]];
-        if (rv < 0) { rv = pick_free(*gV, *hV); load[(size_t)rv]++; }
-        *gV |= bit(rv); *hV |= bit(rv % H);
       }
     }
     // edges no conflict-free lane took: any empty lane, counted as conflicts
     for (size_t i = 0; i < list.size(); i++) {
       if (done[i]) continue;
-      int32_t t = 0;
-      while (free_at[(size_t)c * nth + t] >= 0) t++;  // fits: at most nth edges
+      size_t at = (size_t)c * P * nth;
+      while (free_at[at] >= 0) at++;  // fits: at most P nth edges
       const int32_t e = list[i];
-      free_at[(size_t)c * nth + t] = e;
+      free_at[at] = e;
+      const size_t cp = at / (size_t)nth;
+      const int32_t t = (int32_t)(at % (size_t)nth);
       const int32_t tg = t / G, half = (t % G) / H;
-      uint64_t *gU = &fG[((size_t)c * groups_per_k + tg) * 2], *gV = gU + 1;
-      uint64_t *hU = &fH[(((size_t)c * groups_per_k + tg) * 2 + half) * 2], *hV = hU + 1;
+      uint64_t *gU, *gV, *hU, *hV;
+      fmask(cp, tg, half, &gU, &gV, &hU, &hV);
       for (int q = 0; q < 2; q++) {
         int32_t &r = res[(size_t)(q == 0 ? s.h_eu[(size_t)e] : s.h_ev[(size_t)e])];
         uint64_t *gm = q == 0 ? gU : gV, *hm = q == 0 ? hU : hV;
@@ -346,12 +443,11 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
     L.slot_vertex[(size_t)row[(size_t)v]] = v;
   }
 
-  // 5. descriptors: [C][K + 1][nth]
-  const int32_t per_class = K + 1;
-  L.total_slots = C * per_class;
-  L.desc.assign((size_t)L.total_slots * nth, EdgeDesc{0u, 0.0f});
-  L.K.assign((size_t)C, per_class);
-  L.padded.assign((size_t)C, per_class * nth);
+  // 5. the entries: register slots [C][K][nth] and pair slots [C][P][nth];
+  // lanes without an edge take dummy rows whose residues are free in their
+  // group and half, so every access of a slot stays conflict-free
+  std::vector<RegEntry> reg((size_t)C * K * nth);
+  std::vector<PairEntry> pair((size_t)C * P * nth);
   for (int32_t k = 0; k < K; k++) {
     for (int32_t tg = 0; tg < groups_per_k; tg++) {
       const int32_t gi = k * groups_per_k + tg;
@@ -365,15 +461,12 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
           if (v >= 0)
             for (const Adj &a : adj[(size_t)v])
               if (a.cls == c) e = a.edge;
-          EdgeDesc &d = L.desc[((size_t)c * per_class + k) * nth + t];
-          if (e >= 0) {
-            const bool flip = s.h_ev[(size_t)e] == v;
-            const int32_t w = flip ? s.h_eu[(size_t)e] : s.h_ev[(size_t)e];
-            d.slots = (uint32_t)row[(size_t)w] | (flip ? 1u << 16 : 0u);
-            d.J = (float)s.h_J[(size_t)e];
-          }
+          if (e < 0) continue;
+          RegEntry &d = reg[((size_t)c * K + k) * nth + t];
+          d.flip = s.h_ev[(size_t)e] == v;
+          d.row = row[(size_t)(d.flip ? s.h_eu[(size_t)e] : s.h_ev[(size_t)e])];
+          d.J = s.h_J[(size_t)e];
         }
-        // dummy rows: residues free in the group and the half
         for (int32_t half = 0; half < 2 && half * H < G; half++) {
           for (int32_t p = half * H; p < (half + 1) * H && p < G; p++) {
             const int32_t t = tg * G + p;
@@ -389,27 +482,28 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
             if (r < 0) return set_error(COSM_ERANGE, "no free dummy row");
             gm |= bit(r);
             hm[half] |= bit(r % H);
-            EdgeDesc &d = L.desc[((size_t)c * per_class + k) * nth + t];
-            d.slots = (uint32_t)(n_rows + r);
-            d.J = 0.0f;
+            RegEntry &d = reg[((size_t)c * K + k) * nth + t];
+            d.row = (int32_t)n_rows + r;
+            d.flip = false;
+            d.J = 0;
           }
         }
       }
     }
   }
-  for (int32_t c = 0; c < C; c++) {
+  for (size_t cp = 0; cp < nps; cp++) {
     for (int32_t tg = 0; tg < groups_per_k; tg++) {
-      uint64_t gU = fG[((size_t)c * groups_per_k + tg) * 2], gV = fG[((size_t)c * groups_per_k + tg) * 2 + 1];
+      uint64_t gU = fG[(cp * groups_per_k + tg) * 2], gV = fG[(cp * groups_per_k + tg) * 2 + 1];
       for (int32_t p = 0; p < G; p++) {
         const int32_t t = tg * G + p, half = p / H;
-        uint64_t &hU = fH[(((size_t)c * groups_per_k + tg) * 2 + half) * 2];
-        uint64_t &hV = fH[(((size_t)c * groups_per_k + tg) * 2 + half) * 2 + 1];
-        EdgeDesc &d = L.desc[((size_t)c * per_class + K) * nth + t];
-        const int32_t e = free_at[(size_t)c * nth + t];
+        uint64_t &hU = fH[((cp * groups_per_k + tg) * 2 + half) * 2];
+        uint64_t &hV = fH[((cp * groups_per_k + tg) * 2 + half) * 2 + 1];
+        PairEntry &d = pair[cp * nth + t];
+        const int32_t e = free_at[cp * nth + t];
         if (e >= 0) {
-          d.slots = (uint32_t)row[(size_t)s.h_eu[(size_t)e]] |
-                    ((uint32_t)row[(size_t)s.h_ev[(size_t)e]] << 16);
-          d.J = (float)s.h_J[(size_t)e];
+          d.ru = row[(size_t)s.h_eu[(size_t)e]];
+          d.rv = row[(size_t)s.h_ev[(size_t)e]];
+          d.J = s.h_J[(size_t)e];
           continue;
         }
         int32_t ru = -1, rv = -1;
@@ -423,22 +517,69 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
         }
         gU |= bit(ru); hU |= bit(ru % H);
         gV |= bit(rv); hV |= bit(rv % H);
-        d.slots = (uint32_t)(n_rows + ru) | ((uint32_t)(n_rows + rv) << 16);
-        d.J = 0.0f;
+        d.ru = (int32_t)n_rows + ru;
+        d.rv = (int32_t)n_rows + rv;
+        d.J = 0;
       }
     }
   }
-  L.reg_k = K;
-  L.reg_free = reg_free;
-  L.reg_vertex = pos_vertex;
-  L.reg_set = set_size;
-  L.reg_edges = reg_edges;
-  L.reg_conflicts = conflicts;
-  // The twist can run inside the last class when that class touches every
-  // vertex row exactly once (each row is then final for the sweep right after
-  // its update there), as on the even tori, where every vertex has an edge in
-  // every class.
-  {
+
+  // 6. the encoding
+  if (o.rstream) {
+    const uint32_t rowb = 4u * (uint32_t)W;
+    const int32_t nw = nth / 64;
+    int32_t nr = 0;
+    for (int32_t c = 0; c < C; c++) nr += rclass[(size_t)c];
+    L.rs_words.assign((size_t)nr * K * nth * 2, 0u);
+    L.rs_pwords.assign((size_t)C * P * nth * 2, 0u);
+    L.rs_act.assign((size_t)C * nw, 0u);
+    int32_t j = 0;  // register classes so far
+    for (int32_t c = 0; c < C; c++) {
+      if (rclass[(size_t)c]) {
+        for (int32_t k = 0; k < K; k++)
+          for (int32_t t = 0; t < nth; t++) {
+            const RegEntry &d = reg[((size_t)c * K + k) * nth + t];
+            const size_t i = ((size_t)j * K + k) * nth + t;
+            L.rs_words[2 * i] = (uint32_t)d.row * rowb | (d.flip ? 0x80000000u : 0u);
+            L.rs_words[2 * i + 1] = __builtin_bit_cast(uint32_t, (float)d.J);
+          }
+        for (int32_t w = 0; w < nw; w++) L.rs_act[(size_t)c * nw + w] |= 1u;
+        j++;
+      }
+      for (int32_t ps = 0; ps < P; ps++)
+        for (int32_t t = 0; t < nth; t++) {
+          const size_t i = ((size_t)c * P + ps) * nth + t;
+          const PairEntry &d = pair[i];
+          // u row offset with J in the top 14 bits (|J| < 2^13), v row offset
+          L.rs_pwords[2 * i] = (uint32_t)d.ru * rowb | (uint32_t)d.J << 18;
+          L.rs_pwords[2 * i + 1] = (uint32_t)d.rv * rowb;
+          if (d.J != 0) L.rs_act[(size_t)c * nw + t / 64] |= 2u << ps;
+        }
+    }
+    L.rstream = true;
+    L.fuse = false;
+  } else {
+    // descriptors: [C][K + 1][nth], a register slot's row with the flip in
+    // bit 16, then the pair slot (u | v << 16)
+    const int32_t per_class = K + 1;
+    L.desc.assign((size_t)C * per_class * nth, EdgeDesc{0u, 0.0f});
+    for (int32_t c = 0; c < C; c++) {
+      for (int32_t k = 0; k < K; k++)
+        for (int32_t t = 0; t < nth; t++) {
+          const RegEntry &d = reg[((size_t)c * K + k) * nth + t];
+          L.desc[((size_t)c * per_class + k) * nth + t] =
+              EdgeDesc{(uint32_t)d.row | (d.flip ? 1u << 16 : 0u), (float)d.J};
+        }
+      for (int32_t t = 0; t < nth; t++) {
+        const PairEntry &d = pair[(size_t)c * nth + t];
+        L.desc[((size_t)c * per_class + K) * nth + t] =
+            EdgeDesc{(uint32_t)d.ru | ((uint32_t)d.rv << 16), (float)d.J};
+      }
+    }
+    // The twist can run inside the last class when that class touches every
+    // vertex row exactly once (each row is then final for the sweep right after
+    // its update there), as on the even tori, where every vertex has an edge in
+    // every class.
     std::vector<int32_t> hit((size_t)n_rows, 0);
     const int32_t c = C - 1;
     for (int32_t k = 0; k <= K; k++)
@@ -457,6 +598,15 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
       if (L.slot_vertex[(size_t)r] >= 0 && hit[(size_t)r] != 1) all = false;
     L.fuse = all;
   }
+  L.total_slots = C * (K + P);
+  L.K.assign((size_t)C, K + P);
+  L.padded.assign((size_t)C, (K + P) * nth);
+  L.reg_k = K;
+  L.reg_free = reg_free;
+  L.reg_vertex = pos_vertex;
+  L.reg_set = set_size;
+  L.reg_edges = reg_edges;
+  L.reg_conflicts = conflicts;
   L.fuse_k = 0;
   L.dummy_pairs = true;
   *out = std::move(L);
@@ -467,17 +617,64 @@ int build_reg_impl(const cosm_state &s, int32_t W, int32_t K, int32_t nth_reques
 
 int build_reg_schedule(const cosm_state &s, int32_t W, int32_t K, int32_t nth_request,
                        LdsSchedule *out) {
-  LdsSchedule a, b;
-  const int ra = build_reg_impl(s, W, K, nth_request, true, &a);
-  const int rb = build_reg_impl(s, W, K, nth_request, false, &b);
+  RegOptions a, b;
+  a.W = b.W = W;
+  a.K = b.K = K;
+  a.nth_request = b.nth_request = nth_request;
+  a.pre = true;
+  LdsSchedule la, lb;
+  const int ra = build_reg_impl(s, a, &la);
+  const int rb = build_reg_impl(s, b, &lb);
   if (ra && rb) return ra;
   clear_error();
   // more edges in registers first, then fewer bank conflicts
-  const bool take_a = rb || (ra == 0 && (a.reg_edges > b.reg_edges ||
-                                         (a.reg_edges == b.reg_edges &&
-                                          a.reg_conflicts <= b.reg_conflicts)));
-  *out = std::move(take_a ? a : b);
+  const bool take_a = rb || (ra == 0 && (la.reg_edges > lb.reg_edges ||
+                                         (la.reg_edges == lb.reg_edges &&
+                                          la.reg_conflicts <= lb.reg_conflicts)));
+  *out = std::move(take_a ? la : lb);
   return COSM_OK;
+}
+
+int build_rstream_schedule(const cosm_state &s, int32_t W, int32_t nth_request,
+                           LdsSchedule *out) {
+  // the fewest register rows (8, 10, 12 or 16) that hold the independent set
+  // at the thread count asked for (1024 when none is)
+  const int32_t nth = nth_request > 0 ? nth_request : 1024;
+  std::vector<std::vector<Adj>> adj((size_t)s.n);
+  for (int64_t k = 0; k < s.m; k++) {
+    adj[(size_t)s.h_eu[(size_t)k]].push_back({s.h_ev[(size_t)k], (int32_t)k, 0});
+    adj[(size_t)s.h_ev[(size_t)k]].push_back({s.h_eu[(size_t)k], (int32_t)k, 0});
+  }
+  std::vector<uint8_t> inI;
+  if (!bipartite_side(s.n, adj, &inI)) greedy_independent(s.n, adj, &inI);
+  int64_t set = 0;
+  for (uint8_t b : inI) set += b;
+  int32_t K = kRStreamKMax;
+  for (int32_t k : {8, 10, 12, 16})
+    if ((int64_t)k * nth >= set) {
+      K = k;
+      break;
+    }
+  RegOptions a, b;
+  a.W = b.W = W;
+  a.K = b.K = K;
+  a.nth_request = b.nth_request = nth;
+  a.rstream = b.rstream = true;
+  a.pre = true;
+  LdsSchedule la, lb;
+  const int ra = build_reg_impl(s, a, &la);
+  const int rb = build_reg_impl(s, b, &lb);
+  if (ra && rb) return ra;
+  clear_error();
+  const bool take_a = rb || (ra == 0 && (la.reg_edges > lb.reg_edges ||
+                                         (la.reg_edges == lb.reg_edges &&
+                                          la.reg_conflicts <= lb.reg_conflicts)));
+  *out = std::move(take_a ? la : lb);
+  return COSM_OK;
+}
+
+size_t rstream_lds_bytes(const LdsSchedule &L, int W, int32_t C) {
+  return lds_sweep_bytes(L.n_rows, W, C) + (size_t)C * (L.nth / 64) * 4;
 }
 
 }  // namespace cosm

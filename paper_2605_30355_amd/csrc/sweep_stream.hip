@@ -32,6 +32,10 @@
 namespace cosm {
 namespace {
 
+// v_bitop3 truth table of (a & c) | (b & ~c): the bits of a where c is set,
+// the bits of b elsewhere.
+constexpr int kSelectBits = 0xe4;
+
 struct StreamArgs {
   void *phases;
   const uint32_t *desc;       // [entries][2] schedule words
@@ -46,49 +50,16 @@ struct StreamArgs {
   uint32_t k0, k1, rid0;
 };
 
-typedef uint32_t su2 __attribute__((ext_vector_type(2)));
-
-// Row access at an absolute LDS byte address (clang vector types: the HIP
-// vector classes do not take an address-space qualifier).
-typedef uint32_t su4 __attribute__((ext_vector_type(4)));
-template <int W>
-__device__ __forceinline__ void row_load(uint32_t addr, uint32_t (&w)[W]) {
-  if constexpr (W == 4) {
-    typedef __attribute__((address_space(3))) const su4 *P;
-    const su4 q = *(P)(uintptr_t)addr;
-    w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
-  } else if constexpr (W == 2) {
-    typedef __attribute__((address_space(3))) const su2 *P;
-    const su2 q = *(P)(uintptr_t)addr;
-    w[0] = q.x; w[1] = q.y;
-  } else {
-    typedef __attribute__((address_space(3))) const uint32_t *P;
-    w[0] = *(P)(uintptr_t)addr;
-  }
-}
-template <int W>
-__device__ __forceinline__ void row_store(uint32_t addr, const uint32_t (&w)[W]) {
-  if constexpr (W == 4) {
-    typedef __attribute__((address_space(3))) su4 *P;
-    *(P)(uintptr_t)addr = su4{w[0], w[1], w[2], w[3]};
-  } else if constexpr (W == 2) {
-    typedef __attribute__((address_space(3))) su2 *P;
-    *(P)(uintptr_t)addr = su2{w[0], w[1]};
-  } else {
-    typedef __attribute__((address_space(3))) uint32_t *P;
-    *(P)(uintptr_t)addr = w[0];
-  }
-}
-
 // Eq. (6) on an edge's two rows of FP32 phases, without the wrap to [0, 1)
 // turn (the lazy form).  On the grid schedule every phase is a multiple of
 // 2^-23 turn and every step a multiple of 2^-22; while all phases stay inside
 // (-1/2, 3/2) turn, each phase, each step result and each difference x_u - x_v
 // (|.| < 2) is exact in FP32, so fract(x_u - x_v) and every later phase mod 1
 // equal those of the wrapped form bit for bit.  The host enables this form
-// only when the phases provably stay there: between two twists (which wrap
-// every row first) a phase moves by at most period * alpha_max * (largest sum
-// of |J| at one vertex) < 1/2 turn.
+// only when the phases provably stay there: a twist wraps every row and adds
+// at most twist_max, and until the next one a phase moves by at most
+// period * alpha_max * (largest sum of |J| at one vertex), with the two
+// together below 1/2 turn.
 template <int W>
 __device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
 #pragma unroll
@@ -98,17 +69,6 @@ __device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&
     wu[k] = __float_as_uint(xu - dl);
     wv[k] = __float_as_uint(xv + dl);
   }
-}
-
-// The twist on one row; the lazy form wraps the row first, so the window test
-// and the twisted value are those of the wrapped form.
-template <int ST, int W, bool LAZY>
-__device__ __forceinline__ void twist_row(const TwistOps<ST, W> &op, uint32_t (&w)[W]) {
-  if constexpr (LAZY) {
-#pragma unroll
-    for (int k = 0; k < W; k++) w[k] = __float_as_uint(fract1(__uint_as_float(w[k])));
-  }
-  op.apply(w);
 }
 
 // One slot in flight: its rows, their addresses and the step alpha_t J.
@@ -182,6 +142,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
   dm[1] = mag(1);
   Slot<W> sl[2];
 
+  int32_t k_next = cls[0], last_next = cls[a.C];
   SweepSchedule sc = a.sch;
   const uint32_t nsw = (uint32_t)a.nsw;
   uint32_t t = (uint32_t)a.t0;
@@ -220,9 +181,11 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       // (both addresses are new values: the refill below may reuse the words'
       // registers at once, with no copy and no wait)
       x.au = dw[p].x & 0x7fffffffu;
-      x.av = dw[p].y & 0x7fffffffu;
+      x.av = dw[p].y;
       const float m = JU ? amag : amag * dm[p];
-      x.aJ = __uint_as_float((dw[p].x & 0x80000000u) | __float_as_uint(m));
+      // (the sign bit from the word, the rest from m: one v_bitop3)
+      x.aJ = __uint_as_float(
+          __builtin_amdgcn_bitop3_b32(dw[p].x, __float_as_uint(m), 0x80000000u, kSelectBits));
       row_load<W>(x.au, x.u);
       row_load<W>(x.av, x.v);
       dw[p] = word(jsw + 2);
@@ -289,9 +252,14 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
     };
 
     for (int c = 0; c < a.C; c++) {
-      const int K = __builtin_amdgcn_readfirstlane(cls[c]);
+      // this class's slot count and last lanes, read one class ahead
+      const int K = __builtin_amdgcn_readfirstlane(k_next);
+      const int last = __builtin_amdgcn_readfirstlane(last_next);
+      const int cn = c + 1 == a.C ? 0 : c + 1;
+      k_next = cls[cn];
+      last_next = cls[a.C + cn];
       if (K == 0) continue;
-      const bool act_final = wave_base < __builtin_amdgcn_readfirstlane(cls[a.C + c]);
+      const bool act_final = wave_base < last;
       if (FUSE && twist_now && c == a.C - 1) {
         run_class(K, act_final, std::true_type{});
         // the rows that no edge of the last class touches
@@ -408,13 +376,17 @@ int launch_stream_st(cosm_state *s, int64_t n_sweeps) {
 }  // namespace
 
 bool lds_lazy_wrap(const cosm_state &s) {
-  if (s.shape.residency != COSM_RES_LDS || !s.lds.stream || s.p.storage != COSM_STORE_FP32 ||
+  if (s.shape.residency != COSM_RES_LDS || !(s.lds.stream || s.lds.rstream) ||
+      s.p.storage != COSM_STORE_FP32 ||
       !s.sched.grid || s.sched.dwt_period <= 0)
     return false;
-  // the largest step in turns, then the largest drift of one phase between
-  // two twists (exact products of small integers and a power of two)
+  // the largest step and the largest twist in turns, then the largest drift
+  // of one phase from [0, 1) between two twists: the twist left unwrapped
+  // plus every step of `period` sweeps (exact products of small integers and
+  // powers of two)
   const double alpha_max = (double)s.sched.a0_units * (double)s.sched.aunit;
-  return (double)s.sched.dwt_period * alpha_max * (double)s.wdeg_max < 0.5;
+  const double twist_max = (double)s.sched.twist_num2 * (double)s.sched.a0_units * (double)s.sched.tunit;
+  return twist_max + (double)s.sched.dwt_period * alpha_max * (double)s.wdeg_max < 0.5;
 }
 
 int launch_sweeps_stream(cosm_state *s, int64_t n_sweeps) {

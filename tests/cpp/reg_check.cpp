@@ -1,5 +1,6 @@
 // Host-only check of the register-owner schedule built by reg_schedule.cpp.
-// Input on stdin: "n m C" then m lines "u v J colour"; arguments: W K.
+// Input on stdin: "n m C" then m lines "u v J colour"; arguments: W K (K = 0:
+// the streamed register-owner schedule, which picks its own K).
 // Prints one summary line; exit status 0 when the schedule was built (1-2:
 // bad input or the form does not apply, printed as "ERANGE").  The caller
 // checks equal=1 (every edge exactly once, in its class, with its own u / v
@@ -12,6 +13,7 @@
 #include "internal.hpp"
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <set>
 #include <tuple>
 #include <vector>
@@ -19,7 +21,8 @@ int cosm::set_error(int st, const std::string &m) { fprintf(stderr, "err %s\n", 
 void cosm::clear_error() {}
 int main(int argc, char **argv) {
   if (argc < 3) return 1;
-  const int W = atoi(argv[1]), K = atoi(argv[2]);
+  const int W = atoi(argv[1]);
+  int K = atoi(argv[2]);
   int n; long m; int C;
   if (scanf("%d %ld %d", &n, &m, &C) != 3) return 1;
   cosm_state s; s.n = n; s.m = m; s.C = C;
@@ -29,7 +32,13 @@ int main(int argc, char **argv) {
     s.h_eu.push_back(u); s.h_ev.push_back(v); s.h_J.push_back(J); s.h_colour.push_back(c);
   }
   cosm::LdsSchedule L;
-  if (cosm::build_reg_schedule(s, W, K, 0, &L)) { puts("ERANGE"); return 2; }
+  // K = 0: the streamed register-owner schedule (it picks its own K)
+  const bool rstream = K == 0;
+  if (rstream ? cosm::build_rstream_schedule(s, W, 0, &L) : cosm::build_reg_schedule(s, W, K, 0, &L)) {
+    puts("ERANGE");
+    return 2;
+  }
+  if (rstream) K = L.reg_k;
   const int nth = L.nth, nr = L.n_rows;
   // register vertices: each once, independent
   std::vector<int> isreg(n, 0);
@@ -64,8 +73,79 @@ int main(int argc, char **argv) {
         for (int q = 0; q < 64; q++) conflicts += b[q] > 1 ? b[q] - 1 : 0;
       }
   };
-  if ((int)L.desc.size() != C * (K + 1) * nth) bad_dummy++;
-  for (int c = 0; c < C && !bad_dummy; c++) {
+  long mask_bad = 0;
+  int rclasses = 0;
+  if (rstream) {
+    // register classes (bit 0 of every wave's mask), their K slots of word
+    // pairs (row offset | flip << 31, J as a float), then kRStreamPairs pair
+    // slots per class (u offset | J << 18, v offset) with per-wave mask bits
+    const int nw = nth / 64, P = cosm::kRStreamPairs;
+    const uint32_t rowb = 4u * W;
+    if ((int)L.rs_act.size() != C * nw || (int)L.rs_pwords.size() != C * P * nth * 2) bad_dummy++;
+    std::vector<int> rc(C, 0);
+    for (int c = 0; c < C && !bad_dummy; c++) {
+      rc[c] = L.rs_act[(size_t)c * nw] & 1u;
+      for (int w = 1; w < nw; w++) if ((int)(L.rs_act[(size_t)c * nw + w] & 1u) != rc[c]) mask_bad++;
+      rclasses += rc[c];
+    }
+    if ((long)L.rs_words.size() != (long)rclasses * K * nth * 2) bad_dummy++;
+    int j = 0;
+    for (int c = 0; c < C && !bad_dummy; c++) {
+      if (rc[c]) {
+        for (int k = 0; k < K; k++) {
+          std::vector<int> rows(nth);
+          for (int t = 0; t < nth; t++) {
+            const size_t i = ((size_t)j * K + k) * nth + t;
+            const uint32_t x = L.rs_words[2 * i], y = L.rs_words[2 * i + 1];
+            float J;
+            memcpy(&J, &y, 4);
+            const uint32_t off = x & 0x7fffffffu;
+            const int flip = (int)(x >> 31), row = (int)(off / rowb);
+            rows[t] = row;
+            if (off % rowb) bad_dummy++;
+            if (J == 0.0f) {
+              if (row < nr || row >= nr + cosm::kDummyRows || flip) bad_dummy++;
+              continue;
+            }
+            if (row >= nr) { bad_dummy++; continue; }
+            const int v = L.reg_vertex[(size_t)k * nth + t], w = L.slot_vertex[row];
+            if (v < 0 || w < 0) { bad_dummy++; continue; }
+            reg_active++;
+            got.insert({c, flip ? w : v, flip ? v : w, J});
+          }
+          banks(rows);
+        }
+        j++;
+      }
+      for (int p = 0; p < P; p++) {
+        std::vector<int> ru(nth), rv(nth);
+        for (int t = 0; t < nth; t++) {
+          const size_t i = ((size_t)c * P + p) * nth + t;
+          const uint32_t x = L.rs_pwords[2 * i], y = L.rs_pwords[2 * i + 1];
+          const uint32_t ou = x & ((1u << 18) - 1u);
+          const int J = (int32_t)x >> 18;
+          ru[t] = (int)(ou / rowb);
+          rv[t] = (int)(y / rowb);
+          if (ou % rowb || y % rowb) bad_dummy++;
+          if (J == 0) {
+            if (ru[t] < nr || rv[t] < nr || ru[t] >= nr + cosm::kDummyRows ||
+                rv[t] >= nr + cosm::kDummyRows) bad_dummy++;
+            continue;
+          }
+          if (!((L.rs_act[(size_t)c * nw + t / 64] >> (1 + p)) & 1u)) mask_bad++;
+          if (ru[t] >= nr || rv[t] >= nr) { bad_dummy++; continue; }
+          const int u = L.slot_vertex[ru[t]], v = L.slot_vertex[rv[t]];
+          if (u < 0 || v < 0) { bad_dummy++; continue; }
+          free_active++;
+          got.insert({c, u, v, (float)J});
+        }
+        banks(ru);
+        banks(rv);
+      }
+    }
+  }
+  if (!rstream && (int)L.desc.size() != C * (K + 1) * nth) bad_dummy++;
+  for (int c = 0; c < C && !bad_dummy && !rstream; c++) {
     for (int k = 0; k < K; k++) {
       std::vector<int> rows(nth);
       for (int t = 0; t < nth; t++) {
@@ -116,8 +196,10 @@ int main(int argc, char **argv) {
       if (L.slot_vertex[r] >= 0 && hit[r] != 1) fuse_ok = 0;
   }
   printf("W=%d K=%d nth=%d rows=%d reg_edges=%ld reg_active=%ld free=%ld reg_free=%d "
-         "conflicts=%ld equal=%d indep=%d rows_ok=%d bad_dummy=%ld fuse=%d fuse_ok=%d\n",
+         "conflicts=%ld equal=%d indep=%d rows_ok=%d bad_dummy=%ld fuse=%d fuse_ok=%d "
+         "rstream=%d rclasses=%d mask_bad=%ld\n",
          W, K, nth, nr, (long)L.reg_edges, reg_active, free_active, L.reg_free, conflicts,
-         (int)(want == got), indep, rows_ok, bad_dummy, (int)L.fuse, fuse_ok);
+         (int)(want == got), indep, rows_ok, bad_dummy, (int)L.fuse, fuse_ok, (int)rstream,
+         rclasses, mask_bad);
   return 0;
 }

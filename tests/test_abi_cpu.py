@@ -171,9 +171,10 @@ def test_params_validation_on_host():
     assert status(storage=cosm.STORE_FIX32)[0] == 0
     assert status(storage=cosm.STORE_FIX32, schedule=cosm.SCHED_CONTINUOUS)[0] == -1
     assert status(storage=5)[0] == -1
-    for form in (cosm.LDS_FORM_AUTO, cosm.LDS_FORM_PAIR, cosm.LDS_FORM_REGISTER):
+    for form in (cosm.LDS_FORM_AUTO, cosm.LDS_FORM_PAIR, cosm.LDS_FORM_REGISTER,
+                 cosm.LDS_FORM_REGISTER_STREAM):
         assert status(lds_form=form)[0] == 0
-    assert status(lds_form=3)[0] == -1
+    assert status(lds_form=4)[0] == -1
     # FIX32 phases take 4 bytes per replica-vertex, FIX16 2
     assert status(storage=cosm.STORE_FIX32)[1] > status(storage=cosm.STORE_FIX16)[1]
 

@@ -95,16 +95,18 @@ def test_row_widths(rw):
     assert info["streamed"] == 1 and info["replicas_per_wg"] == rw
 
 
-@pytest.mark.parametrize("case", [(14.9, 3, 1, 0), (14.9, 3, 1, cosm.ORDER_LARGEST_LAST),
-                                  (14.0, 4, 0, 0)],
-                         ids=["lazy-drift-0.497", "lazy-fused-twist", "eager-drift-0.622"])
+@pytest.mark.parametrize("case", [(14.3, 3, 1, 0), (14.3, 3, 1, cosm.ORDER_LARGEST_LAST),
+                                  (14.5, 3, 0, 0), (14.0, 4, 0, 0)],
+                         ids=["lazy-drift-0.4965", "lazy-fused-twist", "eager-drift-0.5035",
+                              "eager-drift-0.642"])
 def test_lazy_wrap_bound(case):
     """FP32 phases wrapped to [0, 1) turn only at the twists stay exact while no
-    phase can drift by 1/2 turn between two twists (period x alpha0 x 4 on a
-    +-1 torus).  alpha0 = 14.9 deg with a twist every 3 sweeps sits just inside
-    the bound (0.497 turn), also with the twist inside the last class; every 4
-    sweeps at 14 deg lies outside it (0.622) and keeps the wrap at every update.
-    All bit-exact against the oracle."""
+    phase can drift by 1/2 turn from [0, 1) between two twists: the twist
+    (ratio x alpha0, left unwrapped) plus period x alpha0 x 4 on a +-1 torus.
+    alpha0 = 14.3 deg with a twist every 3 sweeps and ratio 1/2 sits just
+    inside the bound (0.4965 turn), also with the twist inside the last class;
+    14.5 deg (0.5035) and every 4 sweeps at 14 deg (0.642) lie outside it and
+    keep the wrap at every update.  All bit-exact against the oracle."""
     a0, T, lazy, order = case
     inst = ci.torus(101, seed=9)
     colour, C, prob = make(inst, cosm.COLOR_TORUS | order, [101, 101])

@@ -103,3 +103,36 @@ def test_degenerate_graphs(checker, txt, W, K):
     f = fields(r.stdout)
     assert f["equal"] == "1" and f["indep"] == "1" and f["rows_ok"] == "1", r.stdout
     assert f["bad_dummy"] == "0" and f["conflicts"] == "0", r.stdout
+
+
+# The streamed register-owner schedule (K = 0 asks the checker for it): every
+# edge exactly once in its class, with its own roles, from the register words
+# of the register classes and the pair words; per-wave masks that cover every
+# pair slot with an edge; no bank conflicts on the tori.
+RSTREAM_CASES = [
+    (ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141], 2, 10, 4),
+    (ci.torus(100, seed=3), cosm.COLOR_TORUS, [100, 100], 4, 8, 4),
+    (ci.torus(101, seed=6, weights="pm12"), cosm.COLOR_TORUS, [101, 101], 2, 8, 4),
+    (ci.random_regular(20000, 5, seed=1000, weights="pm1"), cosm.COLOR_BALANCED, None, 2, 8, 6),
+]
+
+
+@pytest.mark.parametrize("case", RSTREAM_CASES, ids=lambda c: f"{c[0].name}-W{c[3]}")
+def test_rstream_schedule_complete(checker, case):
+    inst, method, sides, W, K, rclasses = case
+    r = run(checker, inst, method, sides, W, 0)
+    assert r.returncode == 0, r.stdout + r.stderr
+    f = fields(r.stdout)
+    assert f["rstream"] == "1" and f["K"] == str(K) and f["rclasses"] == str(rclasses), r.stdout
+    assert f["equal"] == "1" and f["indep"] == "1" and f["rows_ok"] == "1", r.stdout
+    assert f["bad_dummy"] == "0" and f["mask_bad"] == "0", r.stdout
+    if sides:  # the tori: conflict-free and nearly every edge in registers
+        assert f["conflicts"] == "0", r.stdout
+        assert int(f["reg_edges"]) >= 0.9 * inst.m, r.stdout
+
+
+def test_rstream_row_offsets_bounded(checker):
+    """Row offsets must stay below 2^18 bytes: 16-byte rows of a 19881-vertex
+    graph are refused."""
+    r = run(checker, ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141], 4, 0)
+    assert r.returncode == 2 and "ERANGE" in r.stdout
