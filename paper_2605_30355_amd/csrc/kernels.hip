@@ -1105,6 +1105,9 @@ template <int ST> struct SweepFn {
 // schedule that lists the rows outside the last class (lds.fuse).
 bool lds_twist_fused(const cosm_state &s) {
   if (s.shape.residency != COSM_RES_LDS || s.sched.dwt_period <= 0 || !s.lds.fuse) return false;
+  // (the streamed word form runs its twist as a pass: measured faster than
+  // the fused twist there, whose extra arithmetic lengthens the last class)
+  if (s.lds.stream) return false;
   if (s.lds.reg_k > 0) return s.C == 4;
   if (s.has_h) return false;
   const int slots = s.lds.total_slots;

@@ -21,7 +21,9 @@
 // to an even number of slots (a padding slot's words are passed, never run),
 // so that a class starts in the same register set whatever came before it.
 // The last slot of a class may hold fewer lanes than the workgroup: waves past
-// them skip it.
+// them skip it.  The twist runs as a pass of its own after the last class
+// (four rows in flight per thread); folded into a class's slots instead, its
+// arithmetic lengthened that class by more than the pass costs.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -42,7 +44,7 @@ struct StreamArgs {
   const float *jmag;          // [entries] |J| (when |J| varies), else null
   const int32_t *cls;         // [2C]: slots per thread of each class, then last_lanes
   const int32_t *slot_vertex; // [n_rows]
-  int32_t R, n_rows, C, total_slots, fuse_k;  // total_slots: padded slots of a sweep
+  int32_t R, n_rows, C, total_slots;  // total_slots: padded slots of a sweep
   uint32_t desc_bytes, jmag_bytes;
   float jscale;               // |J| of every edge (uniform magnitude)
   int64_t t0, nsw;
@@ -79,7 +81,7 @@ struct Slot {
   float aJ;
 };
 
-template <int ST, int W, bool JU, bool FUSE, bool LAZY>
+template <int ST, int W, bool JU, bool LAZY>
 __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
   static_assert(!LAZY || ST == COSM_STORE_FP32, "the lazy wrap is an FP32 form");
   extern __shared__ uint32_t lds[];
@@ -181,7 +183,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       // (both addresses are new values: the refill below may reuse the words'
       // registers at once, with no copy and no wait)
       x.au = dw[p].x & 0x7fffffffu;
-      x.av = dw[p].y;
+      x.av = dw[p].y & 0x7fffffffu;
       const float m = JU ? amag : amag * dm[p];
       // (the sign bit from the word, the rest from m: one v_bitop3)
       x.aJ = __uint_as_float(
@@ -192,34 +194,30 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       dm[p] = mag(jsw + 2);
       jsw++;
     };
-    // Eq. (6) on the slot in set p and store; twr: the fused twist
-    auto finish = [&](int p, auto twr) {
+    // Eq. (6) on the slot in set p and store
+    auto finish = [&](int p) {
       Slot<W> &x = sl[p];
       if constexpr (LAZY) {
         update_words_lazy<W>(x.u, x.v, x.aJ);
       } else {
         update_words<ST, W>(x.u, x.v, x.aJ);
       }
-      if constexpr (decltype(twr)::value) {
-        twist_row<ST, W, LAZY>(op, x.u);
-        twist_row<ST, W, LAZY>(op, x.v);
-      }
       row_store<W>(x.au, x.u);
       row_store<W>(x.av, x.v);
     };
     // npairs pairs of slots of one class: slot 2i in set 0, 2i + 1 in set 1;
     // the rows of the next slot are read before the current one is written
-    auto run_pairs = [&](int npairs, auto twr) {
+    auto run_pairs = [&](int npairs) {
       read(0);  // slot 0
       read(1);  // slot 1
-      finish(0, twr);
+      finish(0);
       for (int i = 1; i < npairs; i++) {
-        read(0);  // slot 2i
-        finish(1, twr);  // slot 2i - 1
-        read(1);  // slot 2i + 1
-        finish(0, twr);  // slot 2i
+        read(0);    // slot 2i
+        finish(1);  // slot 2i - 1
+        read(1);    // slot 2i + 1
+        finish(0);  // slot 2i
       }
-      finish(1, twr);
+      finish(1);
     };
     // a pair this wave skips: its words are still consumed in order
     auto skip_pair = [&] {
@@ -232,16 +230,16 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
 
     // one class of K slots (the stream pads it to an even number): its pairs,
     // then, for odd K, its last slot alone (the padding slot's words passed)
-    auto run_class = [&](int K, bool act_final, auto twr) {
+    auto run_class = [&](int K, bool act_final) {
       const int full = K >> 1;  // pairs of real slots
       const bool odd = (K & 1) != 0;
       // with even K every wave runs every pair; with odd K the last slot holds
       // entries in its first last_lanes lanes only
-      if (full > 0) run_pairs(full, twr);
+      if (full > 0) run_pairs(full);
       if (odd) {
         if (act_final) {
           read(0);
-          finish(0, twr);
+          finish(0);
           dw[1] = word(jsw + 2);  // past the padding slot
           dm[1] = mag(jsw + 2);
           jsw++;
@@ -260,28 +258,13 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       last_next = cls[a.C + cn];
       if (K == 0) continue;
       const bool act_final = wave_base < last;
-      if (FUSE && twist_now && c == a.C - 1) {
-        run_class(K, act_final, std::true_type{});
-        // the rows that no edge of the last class touches
-        for (int q = 0; q < a.fuse_k; q++) {
-          const uint32_t off =
-              a.desc[2 * ((size_t)(a.total_slots + kWordRepeat + q) * nth + tid)];
-          if (off != kEmptySlot) {
-            uint32_t w[W];
-            row_load<W>(off, w);
-            twist_row<ST, W, LAZY>(op, w);
-            row_store<W>(off, w);
-          }
-        }
-      } else {
-        run_class(K, act_final, std::false_type{});
-      }
+      run_class(K, act_final);
       __syncthreads();
     }
     jsw -= (uint32_t)a.total_slots;  // the next sweep's first words are in flight
 
     // Dual window twist every `period` sweeps, after the last class
-    if (!FUSE && twist_now) {
+    if (twist_now) {
       for (int s0 = tid; s0 < a.n_rows; s0 += 4 * nth) {
         uint32_t w[4][W];
 #pragma unroll
@@ -312,12 +295,12 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
   }
 }
 
-template <int ST, int W, bool JU, bool FUSE, bool LAZY>
+template <int ST, int W, bool JU, bool LAZY>
 int launch_stream_k(cosm_state *s, const StreamArgs &a) {
   const size_t lds = s->shape.lds_bytes;
-  (void)hipFuncSetAttribute((const void *)k_sweep_stream<ST, W, JU, FUSE, LAZY>,
+  (void)hipFuncSetAttribute((const void *)k_sweep_stream<ST, W, JU, LAZY>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_sweep_stream<ST, W, JU, FUSE, LAZY>), dim3(s->shape.blocks),
+  hipLaunchKernelGGL((k_sweep_stream<ST, W, JU, LAZY>), dim3(s->shape.blocks),
                      dim3(s->shape.threads), lds, s->stream, a);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess)
@@ -327,12 +310,8 @@ int launch_stream_k(cosm_state *s, const StreamArgs &a) {
 
 template <int ST, int W, bool LAZY>
 int launch_stream_l(cosm_state *s, const StreamArgs &a) {
-  const bool fuse = lds_twist_fused(*s);
-  const bool ju = s->lds.junit;
-  if (ju && fuse) return launch_stream_k<ST, W, true, true, LAZY>(s, a);
-  if (ju) return launch_stream_k<ST, W, true, false, LAZY>(s, a);
-  if (fuse) return launch_stream_k<ST, W, false, true, LAZY>(s, a);
-  return launch_stream_k<ST, W, false, false, LAZY>(s, a);
+  if (s->lds.junit) return launch_stream_k<ST, W, true, LAZY>(s, a);
+  return launch_stream_k<ST, W, false, LAZY>(s, a);
 }
 
 template <int ST, int W>
@@ -356,7 +335,6 @@ int launch_stream_st(cosm_state *s, int64_t n_sweeps) {
   a.n_rows = L.n_rows;
   a.C = s->C;
   a.total_slots = L.stotal;
-  a.fuse_k = L.fuse_k;
   a.desc_bytes = (uint32_t)(L.sdesc.size() * 4);
   a.jmag_bytes = (uint32_t)(L.sjmag.size() * 4);
   a.jscale = L.jscale;

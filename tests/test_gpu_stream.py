@@ -2,7 +2,7 @@
 against the oracle's grid schedules on sampled replicas: uniform and varying
 |J| (a second stream of magnitudes), classes with an odd number of slots (a
 padding slot of dummy pairs) and final pairs that only the first waves run,
-the twist fused into the last class, one, two and four FP32 replicas per
+the twist as a pass after the last class, one, two and four FP32 replicas per
 workgroup, the fixed-point and 16-bit storage formats, and FP32 phases wrapped
 only at the twists (at the edge of the drift bound that keeps them exact)."""
 import numpy as np
@@ -71,15 +71,15 @@ def test_varying_coupling_magnitude():
     run_case(inst, colour, C, prob, p, 7, 64, 300, [0, 31, 63])
 
 
-def test_fused_twist_five_regular():
+def test_five_regular_twist_pass():
     """5-regular N = 20000, equalised colouring: the rows outside the last class
-    are few enough for the twist to run inside it."""
+    are few, but the streamed form keeps the twist as a pass of its own."""
     inst = ci.random_regular(20000, 5, seed=1000, weights="pm1")
     colour, C, prob = make(inst, cosm.COLOR_BALANCED)
     p = cosm.Params(sweeps_per_trial=150, dwt_ratio=1.5, dwt_period=3, replicas_per_wg=2,
                     threads_per_wg=1024, residency=cosm.RES_LDS)
     info = run_case(inst, colour, C, prob, p, 8, 64, 150, [0, 63])
-    assert info["twist_fused"] == 1
+    assert info["twist_fused"] == 0
 
 
 @pytest.mark.parametrize("rw", [1, 4])
@@ -97,14 +97,14 @@ def test_row_widths(rw):
 
 @pytest.mark.parametrize("case", [(14.3, 3, 1, 0), (14.3, 3, 1, cosm.ORDER_LARGEST_LAST),
                                   (14.5, 3, 0, 0), (14.0, 4, 0, 0)],
-                         ids=["lazy-drift-0.4965", "lazy-fused-twist", "eager-drift-0.5035",
+                         ids=["lazy-drift-0.4965", "lazy-largest-last", "eager-drift-0.5035",
                               "eager-drift-0.642"])
 def test_lazy_wrap_bound(case):
     """FP32 phases wrapped to [0, 1) turn only at the twists stay exact while no
     phase can drift by 1/2 turn from [0, 1) between two twists: the twist
     (ratio x alpha0, left unwrapped) plus period x alpha0 x 4 on a +-1 torus.
     alpha0 = 14.3 deg with a twist every 3 sweeps and ratio 1/2 sits just
-    inside the bound (0.4965 turn), also with the twist inside the last class;
+    inside the bound (0.4965 turn), also with the classes reordered;
     14.5 deg (0.5035) and every 4 sweeps at 14 deg (0.642) lie outside it and
     keep the wrap at every update.  All bit-exact against the oracle."""
     a0, T, lazy, order = case
@@ -114,4 +114,4 @@ def test_lazy_wrap_bound(case):
                     replicas_per_wg=2, threads_per_wg=1024, residency=cosm.RES_LDS)
     info = run_case(inst, colour, C, prob, p, 11, 64, 300, [0, 31, 63])
     assert info["lazy_wrap"] == lazy
-    assert info["twist_fused"] == (1 if order else 0)
+    assert info["twist_fused"] == 0
