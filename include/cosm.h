@@ -352,10 +352,13 @@ typedef struct {
                               read and written per update instead of two) */
   int32_t streamed;        /* 1: the LDS sweep streams its lane schedule from memory, two
                               slots in flight per wave (long schedules: the large graphs) */
-  int32_t lazy_wrap;       /* 1: the streamed FP32 sweep wraps phases to [0, 1) turn only at
-                              the twists (grid schedule; the result is the same bit for
-                              bit, since no phase can drift by 1/2 turn between twists:
-                              twist + period x alpha0 x largest sum of |J| < 1/2 turn) */
+  int32_t lazy_wrap;       /* 1: phases are wrapped only at the twists, not after every
+                              update, because no phase can drift by 1/2 turn from its
+                              wrapped range between two twists (twist + period x alpha0 x
+                              largest sum of |J| and |h| at a vertex < 1/2 turn): FP32 in
+                              the streamed LDS forms on the grid schedule (the result is
+                              the same bit for bit), FP16 / BF16 in every form (the
+                              centred value y then lies in (-1, 1) between twists) */
 } cosm_info;
 int cosm_get_info(const cosm_state *s, cosm_info *out);
 

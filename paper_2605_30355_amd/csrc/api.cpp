@@ -443,6 +443,8 @@ int init_state(cosm_state **out, int32_t n, int64_t m, const int32_t *eu, const 
       wdeg[(size_t)eu[k]] += a;
       wdeg[(size_t)ev[k]] += a;
     }
+    if (h != nullptr)
+      for (int32_t i = 0; i < n; i++) wdeg[(size_t)i] += std::llabs((int64_t)h[i]);
     s->wdeg_max = 0;
     for (int64_t w : wdeg) s->wdeg_max = std::max(s->wdeg_max, w);
   }

@@ -42,6 +42,7 @@ struct GraphDev {
   uint32_t k0, k1, rid0;
   ReadoutArgs ro;
   int32_t grid;
+  int32_t lazy;               // FP16 / BF16 phases wrapped at the twists only
   uint32_t ishift;            // initial phases: (draw >> ishift) * iscale
   float iscale;
 };
@@ -93,6 +94,8 @@ __global__ void __launch_bounds__(256) k_batch_init(const GraphDev *graphs, cons
 template <int ST, int W>
 __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
   using F = Fmt<ST>;
+  // FP16 / BF16: wrapped at the twists only when the graph's drift bound holds
+  constexpr bool kLazy16 = ST == COSM_STORE_FP16 || ST == COSM_STORE_BF16;
   constexpr int RW = W * F::kPerWord;
   constexpr uint32_t ROWB = 4 * W;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -136,11 +139,19 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
     float alpha, twist;
     chunk.get((t - 1) & 63u, alpha, twist);
     const float alpha_s = alpha * F::kStepScale;
-    if (g.total_slots > 0)
-      stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
-        edge_rows_sets<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, set_bytes,
-                              nsets, alpha_s * d.J);
-      });
+    if (g.total_slots > 0) {
+      if (kLazy16 && g.lazy) {
+        stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
+          edge_rows_sets<ST, W, kLazy16>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
+                                         set_bytes, nsets, alpha_s * d.J);
+        });
+      } else {
+        stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
+          edge_rows_sets<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, set_bytes,
+                                nsets, alpha_s * d.J);
+        });
+      }
+    }
     if (sc.period > 0 && ++sc.phase == sc.period) {
       sc.phase = 0;
       const int slot = tw % nch;
@@ -170,7 +181,8 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
 #pragma unroll
           for (int q = 0; q < 2; q++) {
             if (s0 + q * nth < g.n) {
-              op.apply(w[q]);
+              if (kLazy16 && g.lazy) twist_row<ST, W, kLazy16>(op, w[q]);
+              else op.apply(w[q]);
               lds_store<W>(set, s0 + q * nth, w[q]);
             }
           }
@@ -191,7 +203,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
     F::template unpack<W>(w, v);
 #pragma unroll
     for (int q = 0; q < RW; q++)
-      if (q < nvalid) F::store_elem(g.phases, base + q, v[q]);
+      if (q < nvalid) F::store_elem(g.phases, base + q, kLazy16 && g.lazy ? F::wrap(v[q]) : v[q]);
   }
 }
 
@@ -422,6 +434,14 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
   s.h_J.assign(J, J + m);
   s.h_colour.assign(colour, colour + m);
   s.n_slots = n;
+  {
+    std::vector<int64_t> wdeg((size_t)n, 0);
+    for (int64_t k = 0; k < m; k++) {
+      wdeg[(size_t)eu[k]] += std::abs((int64_t)J[k]);
+      wdeg[(size_t)ev[k]] += std::abs((int64_t)J[k]);
+    }
+    for (int64_t w : wdeg) s.wdeg_max = std::max(s.wdeg_max, w);
+  }
   int rc = make_schedule(s.p, max_abs_J, &s.sched);
   // row width: the widest that leaves room for at least one replica set
   const int32_t pw = (b->storage == COSM_STORE_FP32 || b->storage == COSM_STORE_FIX32) ? 1 : 2;
@@ -483,6 +503,7 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
   d.k1 = (uint32_t)(seed >> 32);
   d.rid0 = 0;
   d.grid = sc.grid;
+  d.lazy = lazy16(s) ? 1 : 0;
   d.ishift = (uint32_t)sc.ishift;
   d.iscale = sc.iscale;
   ReadoutArgs &ro = d.ro;

@@ -280,22 +280,24 @@ __device__ __forceinline__ void lds_store(uint32_t *base, int slot, const uint32
 }
 
 // Eq. (6) for one (edge, replica): values in the storage's convention.
-template <int ST>
+// LAZY: no wrap (phases wrapped at the twists only; fract(x_u - x_v) does not
+// need wrapped operands).
+template <int ST, bool LAZY = false>
 __device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ) {
   const float f = fract1(xu - xv);
   const float dl = (f < 0.5f) ? aJ : -aJ;
-  xu = Fmt<ST>::wrap(xu - dl);
-  xv = Fmt<ST>::wrap(xv + dl);
+  xu = LAZY ? xu - dl : Fmt<ST>::wrap(xu - dl);
+  xv = LAZY ? xv + dl : Fmt<ST>::wrap(xv + dl);
 }
 
 // Eq. (6) between x (storage convention) and a fixed virtual spin at phase 0
 // coupled with h (the bias field read as one more edge): s = +1 iff x lies in
 // [0, 1/2) turn, x <- wrap(x - alpha h s).
-template <int ST>
+template <int ST, bool LAZY = false>
 __device__ __forceinline__ void field_update(float &v, float ah) {
   const float f = fract1(Fmt<ST>::to_turn(v));
   const float d = (f < 0.5f) ? ah : -ah;
-  v = Fmt<ST>::wrap(v - d);
+  v = LAZY ? v - d : Fmt<ST>::wrap(v - d);
 }
 
 // Dual window twist membership: mod_{1/2}(x - theta + w/2) < w, evaluated as
@@ -465,7 +467,7 @@ __device__ __forceinline__ void row_store(uint32_t addr, const uint32_t (&w)[W])
 // whose sign bit selects -step or +step, and the updates wrap by overflow.
 // FIX32: the same on one 32-bit integer per replica.
 // Other formats: unpack, the FP32 update, pack.
-template <int ST, int W>
+template <int ST, int W, bool LAZY = false>
 __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
   if constexpr (ST == COSM_STORE_FIX32) {
     // aJ is an integer of magnitude below 2^31 (|alpha J| < 1/2 turn on the
@@ -498,7 +500,7 @@ __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W
     F::template unpack<W>(wu, xu);
     F::template unpack<W>(wv, xv);
 #pragma unroll
-    for (int k = 0; k < RW; k++) pair_update<ST>(xu[k], xv[k], aJ);
+    for (int k = 0; k < RW; k++) pair_update<ST, LAZY>(xu[k], xv[k], aJ);
     F::template pack<W>(xu, wu);
     F::template pack<W>(xv, wv);
   }
@@ -560,12 +562,12 @@ __device__ __forceinline__ void update_reg_words(uint32_t (&r)[W], uint32_t (&w)
 }
 
 // Eq. (6) on every replica of one edge: rows at byte offsets bu, bv.
-template <int ST, int W>
+template <int ST, int W, bool LAZY = false>
 __device__ __forceinline__ void edge_rows(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ) {
   uint32_t wu[W], wv[W];
   lds_load_at<W>(lds, bu, wu);
   lds_load_at<W>(lds, bv, wv);
-  update_words<ST, W>(wu, wv, aJ);
+  update_words<ST, W, LAZY>(wu, wv, aJ);
   lds_store_at<W>(lds, bu, wu);
   lds_store_at<W>(lds, bv, wv);
 }
@@ -657,19 +659,29 @@ struct TwistOps<COSM_STORE_FIX16, W> {
   }
 };
 
-// The twist on one row.  LAZY (FP32 phases wrapped only at the twists): the
-// row is wrapped first, so the window test is that of the wrapped form, and
-// the twisted value x + twist is left unwrapped (it is at most the twist
-// above 1 turn; the host's drift bound counts it).
+// Storage formats with a lazy wrap (phases wrapped only at the twists).
+constexpr bool lazy_storage(int st) {
+  return st == COSM_STORE_FP32 || st == COSM_STORE_FP16 || st == COSM_STORE_BF16;
+}
+
+// The twist on one row.  LAZY (phases wrapped only at the twists): the row is
+// wrapped first, so the window test is that of the wrapped form, and the
+// twisted value x + twist is left unwrapped (it is at most the twist past the
+// wrapped range; the host's drift bound counts it).
 template <int ST, int W, bool LAZY>
 __device__ __forceinline__ void twist_row(const TwistOps<ST, W> &op, uint32_t (&w)[W]) {
   if constexpr (LAZY) {
-    static_assert(ST == COSM_STORE_FP32, "the lazy wrap is an FP32 form");
+    static_assert(lazy_storage(ST), "the lazy wrap is a floating-point form");
+    using F = Fmt<ST>;
+    constexpr int RW = W * F::kPerWord;
+    float x[RW];
+    F::template unpack<W>(w, x);
 #pragma unroll
-    for (int k = 0; k < W; k++) {
-      const float x = fract1(__uint_as_float(w[k]));
-      w[k] = __float_as_uint(in_windows(x, op.c[k], op.win2) ? x + op.t[k] : x);
+    for (int k = 0; k < RW; k++) {
+      const float y = F::wrap(x[k]);
+      x[k] = in_windows(y, op.c[k], op.win2) ? y + op.t[k] : y;
     }
+    F::template pack<W>(x, w);
   } else {
     op.apply(w);
   }
@@ -695,25 +707,25 @@ __device__ __forceinline__ void twist_words(uint32_t (&w)[W],
 // twist of both endpoints: their phases are final for the sweep once the
 // update is done, so the twist needs no pass of its own for them.  The twist
 // sees the stored (rounded) phases, as a pass of its own would.
-template <int ST, int W>
+template <int ST, int W, bool LAZY = false>
 __device__ __forceinline__ void edge_rows_twist(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ,
                                                 const TwistOps<ST, W> &op) {
   uint32_t wu[W], wv[W];
   lds_load_at<W>(lds, bu, wu);
   lds_load_at<W>(lds, bv, wv);
-  update_words<ST, W>(wu, wv, aJ);
-  op.apply(wu);
-  op.apply(wv);
+  update_words<ST, W, LAZY>(wu, wv, aJ);
+  twist_row<ST, W, LAZY>(op, wu);
+  twist_row<ST, W, LAZY>(op, wv);
   lds_store_at<W>(lds, bu, wu);
   lds_store_at<W>(lds, bv, wv);
 }
 
 // The twist of one row that no edge of the last class touches.
-template <int ST, int W>
+template <int ST, int W, bool LAZY = false>
 __device__ __forceinline__ void row_twist(uint32_t *lds, uint32_t b, const TwistOps<ST, W> &op) {
   uint32_t w[W];
   lds_load_at<W>(lds, b, w);
-  op.apply(w);
+  twist_row<ST, W, LAZY>(op, w);
   lds_store_at<W>(lds, b, w);
 }
 
@@ -743,7 +755,7 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *scratch /* >= 1
 // The sets are disjoint, so the rows of four sets are read before any is
 // written back, which lets the LDS latency of one set overlap the arithmetic
 // of the others.
-template <int ST, int W>
+template <int ST, int W, bool LAZY = false>
 __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint32_t bv,
                                                uint32_t set_bytes, int nsets, float aJ) {
   int k = 0;
@@ -755,14 +767,15 @@ __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint3
       lds_load_at<W>(lds, bv + (uint32_t)(k + q) * set_bytes, wv[q]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; q++) update_words<ST, W>(wu[q], wv[q], aJ);
+    for (int q = 0; q < 4; q++) update_words<ST, W, LAZY>(wu[q], wv[q], aJ);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       lds_store_at<W>(lds, bu + (uint32_t)(k + q) * set_bytes, wu[q]);
       lds_store_at<W>(lds, bv + (uint32_t)(k + q) * set_bytes, wv[q]);
     }
   }
-  for (; k < nsets; k++) edge_rows<ST, W>(lds, bu + (uint32_t)k * set_bytes, bv + (uint32_t)k * set_bytes, aJ);
+  for (; k < nsets; k++)
+    edge_rows<ST, W, LAZY>(lds, bu + (uint32_t)k * set_bytes, bv + (uint32_t)k * set_bytes, aJ);
 }
 
 // One workgroup's pass over the classes of one sweep with the lane schedule

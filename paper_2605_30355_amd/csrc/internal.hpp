@@ -244,7 +244,7 @@ struct cosm_state {
   std::vector<int32_t> lds_widths;  // row widths (words) that fit, for the autotuner
   bool has_h = false;
   int64_t sumJ = 0;                 // sum of J over the edges
-  int64_t wdeg_max = 0;             // largest sum of |J| over the edges of one vertex
+  int64_t wdeg_max = 0;             // largest sum of |J| (and |h|) at one vertex
   size_t opt_temp_bytes = 0;        // segmented sort workspace (optimal readout)
   std::vector<int32_t> h_eu, h_ev, h_J, h_h, h_colour;
   std::vector<int32_t> h_slot;       // h of the vertex in each LDS slot (host copy)
@@ -278,9 +278,15 @@ int launch_sweeps(cosm_state *s, int64_t n_sweeps);
 // Whether the LDS sweep of s runs the twist inside the last class's sub-sweep
 // (the launchers pick the fused kernel forms by this test).
 bool lds_twist_fused(const cosm_state &s);
-// Whether the streamed LDS sweep of s keeps FP32 phases unwrapped between
-// twists (sweep_stream.hip).
+// Whether the sweeps of s keep phases unwrapped between twists: FP32 in the
+// streamed LDS forms on the grid schedule (exact), FP16 / BF16 in every form
+// (lazy16) -- in both cases only while no phase can drift by 1/2 turn from its
+// wrapped range between two twists (sweep_stream.hip, kernels.hip).
 bool lds_lazy_wrap(const cosm_state &s);
+bool lazy16(const cosm_state &s);
+// That drift bound in turns: the largest twist plus period x the largest step
+// x the largest sum of |J| and |h| at one vertex.
+double wrap_drift_turns(const cosm_state &s);
 int launch_readout(cosm_state *s);
 // Optimal-bisector readout (readout_opt.hip); h must be absent.
 int launch_readout_optimal(cosm_state *s);

@@ -3,7 +3,10 @@
 // Phases are turns (1 turn = 360 degrees).  FP32 storage keeps x in [0, 1) and
 // wraps with v_fract_f32; FP16 / BF16 storage keeps the centred value
 // y = x - 1/2 in [-1/2, 1/2] and wraps with y - rint(y) (one more bit of
-// resolution than storing x); arithmetic is FP32.  FIX16 storage keeps x as a
+// resolution than storing x); arithmetic is FP32.  When no phase can drift by
+// 1/2 turn between two twists, FP16 / BF16 (every form) and FP32 (the
+// streamed LDS forms, grid schedule) wrap at the twists only (lazy16,
+// lds_lazy_wrap).  FIX16 storage keeps x as a
 // 16-bit integer k (x = k 2^-16) and the LDS sweep updates it with packed
 // 16-bit integer ops (other forms go through FP32, exact on that grid).  On
 // the 2^-23 turn grid (2^-16 for FIX16) every add, subtract, fma by 2 and
@@ -67,8 +70,9 @@ __global__ void __launch_bounds__(256) k_init(void *phases, int32_t n, int32_t R
 // EXACT: one slot per class (EMAX of them), no bounds checks.  FUSE (EXACT or
 // streamed, no bias fields): the twist runs inside the last class's sub-sweep.
 // ---------------------------------------------------------------------------
-template <int ST, int W, int EMAX, bool EXACT, bool FUSE>
+template <int ST, int W, int EMAX, bool EXACT, bool FUSE, bool LAZY>
 __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
+  static_assert(!LAZY || lazy_storage(ST), "the lazy wrap is a floating-point form");
   static_assert(!FUSE || EXACT || EMAX == 0,
                 "the fused twist runs in the one-slot-per-class and the streamed forms");
   extern __shared__ uint32_t lds[];
@@ -180,36 +184,36 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       }
 #pragma unroll
       for (int j = 0; j < EMAX - 1; j++) {
-        edge_rows<ST, W>(lds, ua[j], va[j], alpha_s * jr[j]);
+        edge_rows<ST, W, LAZY>(lds, ua[j], va[j], alpha_s * jr[j]);
         __syncthreads();
       }
       if (fuse_now) {
-        edge_rows_twist<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1], op);
+        edge_rows_twist<ST, W, LAZY>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1], op);
 #pragma unroll
         for (int q = 0; q < kFuseRowsMax; q++)
-          if (q < a.fuse_k && fr[q] != kEmptySlot) row_twist<ST, W>(lds, fr[q], op);
+          if (q < a.fuse_k && fr[q] != kEmptySlot) row_twist<ST, W, LAZY>(lds, fr[q], op);
       } else {
-        edge_rows<ST, W>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1]);
+        edge_rows<ST, W, LAZY>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1]);
       }
       __syncthreads();
     } else if constexpr (EXACT) {
       // EMAX slots, one class each
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
-        edge_rows<ST, W>(lds, ua[j], va[j], alpha_s * jr[j]);
+        edge_rows<ST, W, LAZY>(lds, ua[j], va[j], alpha_s * jr[j]);
         __syncthreads();
       }
     } else if constexpr (EMAX > 0) {
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
         if (j < a.total_slots) {
-          edge_rows<ST, W>(lds, ua[j], va[j], alpha_s * jr[j]);
+          edge_rows<ST, W, LAZY>(lds, ua[j], va[j], alpha_s * jr[j]);
           if ((a.bar_mask >> j) & 1u) __syncthreads();
         }
       }
     } else if (a.total_slots > 0) {
       auto edge = [&](const EdgeDesc &d) {
-        edge_rows<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha_s * d.J);
+        edge_rows<ST, W, LAZY>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha_s * d.J);
       };
       if constexpr (FUSE) {
         // streamed form: on a twist sweep the last class twists the rows it
@@ -237,13 +241,13 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         stream_classes(
             a.desc, Ks, a.C, a.total_slots, dA, dB, jslot, edge,
             [&](const EdgeDesc &d) {
-              edge_rows_twist<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
+              edge_rows_twist<ST, W, LAZY>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
                                      alpha_s * d.J, op);
             },
             [&] {
               for (int q = 0; q < a.fuse_k; q++) {
                 const uint32_t row = rest[(size_t)q * nth].slots;
-                if (row != kEmptySlot) row_twist<ST, W>(lds, row * ROWB, op);
+                if (row != kEmptySlot) row_twist<ST, W, LAZY>(lds, row * ROWB, op);
               }
             },
             fuse_now);
@@ -269,7 +273,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
             F::template unpack<W>(w[q], v);
             const float ah = alpha * (float)hv[q];
 #pragma unroll
-            for (int k = 0; k < RW; k++) field_update<ST>(v[k], ah);
+            for (int k = 0; k < RW; k++) field_update<ST, LAZY>(v[k], ah);
             F::template pack<W>(v, w[q]);
             lds_store<W>(lds, s0 + q * nth, w[q]);
           }
@@ -308,7 +312,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           if (s0 + q * nth < a.n_rows) {
-            op.apply(w[q]);
+            twist_row<ST, W, LAZY>(op, w[q]);
             lds_store<W>(lds, s0 + q * nth, w[q]);
           }
         }
@@ -326,7 +330,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     F::template unpack<W>(w, v);
 #pragma unroll
     for (int k = 0; k < RW; k++)
-      if (k < nvalid) F::store_elem(a.phases, base + k, v[k]);
+      if (k < nvalid) F::store_elem(a.phases, base + k, LAZY ? F::wrap(v[k]) : v[k]);
   }
 }
 
@@ -612,7 +616,7 @@ template <int ST, int VEC>
 __global__ void __launch_bounds__(256) k_class_hbm(void *phases, const int32_t *peu,
                                                    const int32_t *pev, const float *pJ,
                                                    int32_t beg, int32_t cnt, int32_t R,
-                                                   int32_t rchunks, float alpha) {
+                                                   int32_t rchunks, float alpha, int32_t lazy) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t e = wave / rchunks;
@@ -623,8 +627,14 @@ __global__ void __launch_bounds__(256) k_class_hbm(void *phases, const int32_t *
   float xu[VEC], xv[VEC];
   load_vec<ST, VEC>(phases, (size_t)u * R + r, xu);
   load_vec<ST, VEC>(phases, (size_t)v * R + r, xv);
+  // (lazy: FP16 / BF16 wrapped at the twists only)
+  if (lazy) {
 #pragma unroll
-  for (int k = 0; k < VEC; k++) pair_update<ST>(xu[k], xv[k], aJ);
+    for (int k = 0; k < VEC; k++) pair_update<ST, true>(xu[k], xv[k], aJ);
+  } else {
+#pragma unroll
+    for (int k = 0; k < VEC; k++) pair_update<ST>(xu[k], xv[k], aJ);
+  }
   store_vec<ST, VEC>(phases, (size_t)u * R + r, xu);
   store_vec<ST, VEC>(phases, (size_t)v * R + r, xv);
 }
@@ -636,7 +646,7 @@ __global__ void __launch_bounds__(256) k_dwt_hbm(void *phases, int32_t n, int32_
                                                  int32_t rcount, int32_t strip, uint32_t t,
                                                  float twist, float win, float win2, uint32_t k0,
                                                  uint32_t k1, uint32_t rid0, int32_t drawn_dir,
-                                                 uint32_t tshift, float tscale) {
+                                                 uint32_t tshift, float tscale, int32_t lazy) {
   using F = Fmt<ST>;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t rchunks = (rcount + 64 * VEC - 1) / (64 * VEC);
@@ -658,10 +668,13 @@ __global__ void __launch_bounds__(256) k_dwt_hbm(void *phases, int32_t n, int32_
     const size_t idx = (size_t)i * R + r;
     float v[VEC];
     load_vec<ST, VEC>(phases, idx, v);
-    bool any = false;
+    bool any = lazy != 0;  // lazy: every phase is wrapped here, the twist added unwrapped
 #pragma unroll
     for (int k = 0; k < VEC; k++) {
-      if (in_windows(v[k], c[k], win2)) {
+      if (lazy) {
+        const float y = F::wrap(v[k]);
+        v[k] = in_windows(y, c[k], win2) ? y + tw[k] : y;
+      } else if (in_windows(v[k], c[k], win2)) {
         v[k] = F::wrap(v[k] + tw[k]);
         any = true;
       }
@@ -674,7 +687,7 @@ __global__ void __launch_bounds__(256) k_dwt_hbm(void *phases, int32_t n, int32_
 template <int ST>
 __global__ void __launch_bounds__(256) k_field_hbm(void *phases, const int32_t *h, int32_t n,
                                                    int32_t R, int32_t rbeg, int32_t rcount,
-                                                   float alpha) {
+                                                   float alpha, int32_t lazy) {
   using F = Fmt<ST>;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)n * rcount) return;
@@ -683,7 +696,8 @@ __global__ void __launch_bounds__(256) k_field_hbm(void *phases, const int32_t *
   if (hv == 0) return;
   const size_t idx = (size_t)i * R + r;
   float v = F::load_elem(phases, idx);
-  field_update<ST>(v, alpha * (float)hv);
+  if (lazy) field_update<ST, true>(v, alpha * (float)hv);
+  else field_update<ST>(v, alpha * (float)hv);
   F::store_elem(phases, idx, v);
 }
 
@@ -691,7 +705,7 @@ template <int ST>
 __global__ void __launch_bounds__(256) k_class_plain(void *phases, const int32_t *peu,
                                                      const int32_t *pev, const float *pJ,
                                                      int32_t beg, int32_t cnt, int32_t R,
-                                                     int32_t r, float alpha) {
+                                                     int32_t r, float alpha, int32_t lazy) {
   using F = Fmt<ST>;
   const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= cnt) return;
@@ -699,7 +713,8 @@ __global__ void __launch_bounds__(256) k_class_plain(void *phases, const int32_t
   const float aJ = alpha * pJ[beg + e];
   float xu = F::load_elem(phases, (size_t)u * R + r);
   float xv = F::load_elem(phases, (size_t)v * R + r);
-  pair_update<ST>(xu, xv, aJ);
+  if (lazy) pair_update<ST, true>(xu, xv, aJ);
+  else pair_update<ST>(xu, xv, aJ);
   F::store_elem(phases, (size_t)u * R + r, xu);
   F::store_elem(phases, (size_t)v * R + r, xv);
 }
@@ -808,14 +823,24 @@ float host_twist(const Schedule &sc, int64_t t) {
   return sc.dwt_ratio * host_alpha(sc, t);
 }
 
-template <int ST, int W, int EMAX, bool EXACT, bool FUSE = false>
-int launch_lds(cosm_state *s, const LdsArgs &a) {
+template <int ST, int W, int EMAX, bool EXACT, bool FUSE, bool LAZY>
+int launch_lds_k(cosm_state *s, const LdsArgs &a) {
   const size_t lds = s->shape.lds_bytes;
-  (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, W, EMAX, EXACT, FUSE>,
+  (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, W, EMAX, EXACT, FUSE, LAZY>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_sweep_lds<ST, W, EMAX, EXACT, FUSE>), dim3(s->shape.blocks),
+  hipLaunchKernelGGL((k_sweep_lds<ST, W, EMAX, EXACT, FUSE, LAZY>), dim3(s->shape.blocks),
                      dim3(s->shape.threads), lds, s->stream, a);
   return launch_check("k_sweep_lds");
+}
+
+// FP16 / BF16 phases are wrapped at the twists only when the drift bound
+// holds (lazy16); the other formats here wrap at every update.
+template <int ST, int W, int EMAX, bool EXACT, bool FUSE = false>
+int launch_lds(cosm_state *s, const LdsArgs &a) {
+  if constexpr (ST == COSM_STORE_FP16 || ST == COSM_STORE_BF16) {
+    if (lazy16(*s)) return launch_lds_k<ST, W, EMAX, EXACT, FUSE, true>(s, a);
+  }
+  return launch_lds_k<ST, W, EMAX, EXACT, FUSE, false>(s, a);
 }
 
 template <int ST, int W, int K, int CM, int CLASSES = 0, bool FUSE = false>
@@ -933,7 +958,8 @@ int dwt_hbm_vec(cosm_state *s, int64_t t, int32_t rbeg, int32_t rcount) {
   hipLaunchKernelGGL((k_dwt_hbm<ST, VEC>), grid, block, 0, s->stream, s->d.phases, s->n, s->R,
                      rbeg, rcount, strip, (uint32_t)t, host_twist(sc, t), sc.window, sc.window2,
                      (uint32_t)(s->seed & 0xffffffffu), (uint32_t)(s->seed >> 32),
-                     (uint32_t)s->rid0, (int32_t)s->has_h, (uint32_t)sc.tshift, sc.tscale);
+                     (uint32_t)s->rid0, (int32_t)s->has_h, (uint32_t)sc.tshift, sc.tscale,
+                     (int32_t)lazy16(*s));
   return launch_check("k_dwt_hbm");
 }
 
@@ -950,7 +976,8 @@ template <int ST>
 int field_hbm_st(cosm_state *s, float alpha, int32_t rbeg, int32_t rcount) {
   const int64_t threads = (int64_t)s->n * rcount;
   hipLaunchKernelGGL((k_field_hbm<ST>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                     s->stream, s->d.phases, s->d.h, s->n, s->R, rbeg, rcount, alpha);
+                     s->stream, s->d.phases, s->d.h, s->n, s->R, rbeg, rcount, alpha,
+                     (int32_t)lazy16(*s));
   return launch_check("k_field_hbm");
 }
 
@@ -960,7 +987,7 @@ int class_hbm_vec(cosm_state *s, int32_t beg, int32_t cnt, float alpha) {
   const int64_t threads = (int64_t)cnt * rchunks * 64;
   hipLaunchKernelGGL((k_class_hbm<ST, VEC>), dim3((unsigned)((threads + 255) / 256)), dim3(256),
                      0, s->stream, s->d.phases, s->d.peu, s->d.pev, s->d.pJ, beg, cnt, s->R,
-                     rchunks, alpha);
+                     rchunks, alpha, (int32_t)lazy16(*s));
   return launch_check("k_class_hbm");
 }
 
@@ -1006,7 +1033,7 @@ int sweeps_plain_st(cosm_state *s, int64_t n_sweeps) {
         if (cnt == 0) continue;
         hipLaunchKernelGGL((k_class_plain<ST>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
                            s->stream, s->d.phases, s->d.peu, s->d.pev, s->d.pJ, beg, cnt, s->R, r,
-                           alpha);
+                           alpha, (int32_t)lazy16(*s));
         if (int rc = launch_check("k_class_plain")) return rc;
       }
       if (s->has_h)
@@ -1115,6 +1142,24 @@ bool lds_twist_fused(const cosm_state &s) {
   for (int32_t k : s.lds.K) one_each = one_each && k == 1;
   if (one_each && (slots == 4 || slots == 8)) return true;
   return slots > kRegisterSlotsMax;
+}
+
+double wrap_drift_turns(const cosm_state &s) {
+  // the largest step and the largest twist in turns (grid: exact products of
+  // small integers and powers of two), then the largest drift of one phase
+  // from its wrapped range between two twists: the twist left unwrapped plus
+  // every step of `period` sweeps, J and h alike
+  const Schedule &sc = s.sched;
+  const double alpha_max = sc.grid ? (double)sc.a0_units * (double)sc.aunit : (double)sc.alpha0_turns;
+  const double twist_max = sc.grid ? (double)sc.twist_num2 * (double)sc.a0_units * (double)sc.tunit
+                                   : (double)sc.dwt_ratio * alpha_max;
+  return twist_max + (double)sc.dwt_period * alpha_max * (double)s.wdeg_max;
+}
+
+bool lazy16(const cosm_state &s) {
+  const int32_t st = s.p.storage;
+  return (st == COSM_STORE_FP16 || st == COSM_STORE_BF16) && s.p.update == COSM_UPDATE_SCS &&
+         s.sched.dwt_period > 0 && wrap_drift_turns(s) < 0.5;
 }
 
 size_t readout_lds_bytes(int32_t n, int32_t B) {

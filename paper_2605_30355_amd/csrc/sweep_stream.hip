@@ -62,15 +62,25 @@ struct StreamArgs {
 // at most twist_max, and until the next one a phase moves by at most
 // period * alpha_max * (largest sum of |J| at one vertex), with the two
 // together below 1/2 turn.
-template <int W>
+// FP16 / BF16 (centred values y = x - 1/2) use the same form to save the two
+// wraps y - rint(y) of every update: no exactness is claimed there, and a
+// value that has drifted to |y| in [1/2, 1) is stored with one bit less of
+// fraction (2^-11 turn for FP16, 2^-8 for BF16) until the next twist wraps it.
+template <int ST, int W>
 __device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
+  using F = Fmt<ST>;
+  constexpr int RW = W * F::kPerWord;
+  float xu[RW], xv[RW];
+  F::template unpack<W>(wu, xu);
+  F::template unpack<W>(wv, xv);
 #pragma unroll
-  for (int k = 0; k < W; k++) {
-    const float xu = __uint_as_float(wu[k]), xv = __uint_as_float(wv[k]);
-    const float dl = (fract1(xu - xv) < 0.5f) ? aJ : -aJ;
-    wu[k] = __float_as_uint(xu - dl);
-    wv[k] = __float_as_uint(xv + dl);
+  for (int k = 0; k < RW; k++) {
+    const float dl = (fract1(xu[k] - xv[k]) < 0.5f) ? aJ : -aJ;
+    xu[k] -= dl;
+    xv[k] += dl;
   }
+  F::template pack<W>(xu, wu);
+  F::template pack<W>(xv, wv);
 }
 
 // One slot in flight: its rows, their addresses and the step alpha_t J.
@@ -83,7 +93,7 @@ struct Slot {
 
 template <int ST, int W, bool JU, bool LAZY>
 __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
-  static_assert(!LAZY || ST == COSM_STORE_FP32, "the lazy wrap is an FP32 form");
+  static_assert(!LAZY || lazy_storage(ST), "the lazy wrap is a floating-point form");
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
@@ -198,7 +208,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
     auto finish = [&](int p) {
       Slot<W> &x = sl[p];
       if constexpr (LAZY) {
-        update_words_lazy<W>(x.u, x.v, x.aJ);
+        update_words_lazy<ST, W>(x.u, x.v, x.aJ);
       } else {
         update_words<ST, W>(x.u, x.v, x.aJ);
       }
@@ -291,7 +301,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
     F::template unpack<W>(w, v);
 #pragma unroll
     for (int k = 0; k < RW; k++)
-      if (k < nvalid) F::store_elem(a.phases, base + k, LAZY ? fract1(v[k]) : v[k]);
+      if (k < nvalid) F::store_elem(a.phases, base + k, LAZY ? F::wrap(v[k]) : v[k]);
   }
 }
 
@@ -316,7 +326,7 @@ int launch_stream_l(cosm_state *s, const StreamArgs &a) {
 
 template <int ST, int W>
 int launch_stream_w(cosm_state *s, const StreamArgs &a) {
-  if constexpr (ST == COSM_STORE_FP32) {
+  if constexpr (lazy_storage(ST)) {
     if (lds_lazy_wrap(*s)) return launch_stream_l<ST, W, true>(s, a);
   }
   return launch_stream_l<ST, W, false>(s, a);
@@ -354,17 +364,11 @@ int launch_stream_st(cosm_state *s, int64_t n_sweeps) {
 }  // namespace
 
 bool lds_lazy_wrap(const cosm_state &s) {
-  if (s.shape.residency != COSM_RES_LDS || !(s.lds.stream || s.lds.rstream) ||
-      s.p.storage != COSM_STORE_FP32 ||
-      !s.sched.grid || s.sched.dwt_period <= 0)
-    return false;
-  // the largest step and the largest twist in turns, then the largest drift
-  // of one phase from [0, 1) between two twists: the twist left unwrapped
-  // plus every step of `period` sweeps (exact products of small integers and
-  // powers of two)
-  const double alpha_max = (double)s.sched.a0_units * (double)s.sched.aunit;
-  const double twist_max = (double)s.sched.twist_num2 * (double)s.sched.a0_units * (double)s.sched.tunit;
-  return twist_max + (double)s.sched.dwt_period * alpha_max * (double)s.wdeg_max < 0.5;
+  const int32_t st = s.p.storage;
+  if (st == COSM_STORE_FP16 || st == COSM_STORE_BF16) return lazy16(s);
+  // FP32: exact on the grid schedule, in the streamed forms
+  return st == COSM_STORE_FP32 && s.sched.grid && s.shape.residency == COSM_RES_LDS &&
+         (s.lds.stream || s.lds.rstream) && s.sched.dwt_period > 0 && wrap_drift_turns(s) < 0.5;
 }
 
 int launch_sweeps_stream(cosm_state *s, int64_t n_sweeps) {
