@@ -389,7 +389,7 @@ def stream_bench():
     t0 = time.perf_counter()
     reqs = ci.request_stream(STREAM["requests"], STREAM["n_min"], STREAM["n_max"], STREAM["seed"])
     b = cosm.Batch(max_graphs=STREAM["requests"], max_n=STREAM["n_max"] + 1)
-    ids, updates = [], 0
+    ids, updates, lds_bytes = [], 0, 0
     for k, (_, inst) in enumerate(reqs):
         fam = inst.meta["family"]
         if fam == "torus":
@@ -401,7 +401,15 @@ def stream_bench():
         ids.append(b.add(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=k,
                          replicas=STREAM["replicas"]))
         updates += inst.m * STREAM["sweeps"] * STREAM["replicas"]
-    log(f"stream: {len(ids)} requests prepared in {time.perf_counter() - t0:.1f} s")
+        # algorithmic LDS bytes (FP32): 16 per edge update, 8 per vertex and twist
+        lds_bytes += (16 * inst.m + 8 * inst.n / FAMILY_PARAMS[fam]["dwt_period"]) \
+            * STREAM["sweeps"] * STREAM["replicas"]
+    shapes = [b.shape(g) for g in ids]
+    widths = {}
+    for sh in shapes:
+        widths[str(sh["replicas_per_set"])] = widths.get(str(sh["replicas_per_set"]), 0) + 1
+    log(f"stream: {len(ids)} requests prepared in {time.perf_counter() - t0:.1f} s "
+        f"(replicas per set: {widths})")
     b.run(ids[:4])  # warm-up (captures the graph)
     b.wait()
     # burst: every request at t = 0, one launch
@@ -415,7 +423,7 @@ def stream_bench():
     rng = np.random.default_rng(STREAM["seed"])
     arrivals = np.cumsum(rng.exponential(1.0 / (STREAM["load"] * capacity), size=len(ids)))
     done = np.zeros(len(ids))
-    nxt, launches = 0, 0
+    nxt, launches, pois_dev_ms = 0, 0, 0.0
     start = time.perf_counter()
     while nxt < len(ids):
         now = time.perf_counter() - start
@@ -429,7 +437,7 @@ def stream_bench():
         for k in batch:
             b.set_seed(ids[k], 1000 + k, 0)
         b.run([ids[k] for k in batch])
-        b.wait()
+        pois_dev_ms += b.wait()
         launches += 1
         done[batch] = time.perf_counter() - start
     lat = (done - arrivals) * 1e3
@@ -440,15 +448,22 @@ def stream_bench():
         "workload": STREAM["name"], "requests": len(ids), "replicas_per_request": STREAM["replicas"],
         "sweeps_per_request": STREAM["sweeps"], "n_range": [STREAM["n_min"], STREAM["n_max"]],
         "families": list(FAMILY_PARAMS), "total_edge_updates": updates,
+        "shapes": {"replicas_per_set": widths,
+                   "tuned_by_probes": sum(1 for sh in shapes if sh["tuned"] == 1),
+                   "from_cache": sum(1 for sh in shapes if sh["tuned"] == 2)},
         "burst": {"seconds": round(burst_s, 3), "device_ms": round(dev_ms, 1),
                   "requests_per_s": round(capacity, 2),
-                  "edge_updates_per_s": round(updates / burst_s, 1)},
+                  "edge_updates_per_s": round(updates / burst_s, 1),
+                  "lds_roofline_frac": round(lds_bytes / (dev_ms * 1e-3) / (LDS_PEAK_GBS * 1e9), 4)},
         "poisson": {"rate_per_s": round(STREAM["load"] * capacity, 2), "launches": launches,
                     "p50_ms": round(float(np.percentile(lat, 50)), 1),
                     "p99_ms": round(float(np.percentile(lat, 99)), 1),
                     "mean_ms": round(float(lat.mean()), 1),
                     "requests_per_s": round(len(ids) / span, 2),
-                    "edge_updates_per_s": round(updates / span, 1)},
+                    "edge_updates_per_s": round(updates / span, 1),
+                    "device_ms": round(pois_dev_ms, 1),
+                    "lds_roofline_frac": round(lds_bytes / (pois_dev_ms * 1e-3)
+                                               / (LDS_PEAK_GBS * 1e9), 4)},
     }
 
 

@@ -286,11 +286,24 @@ int cosm_batch_create(cosm_batch **out, int32_t storage, int32_t max_graphs, int
                       int32_t max_bisectors, void *hip_stream);
 int cosm_batch_destroy(cosm_batch *b);
 /* Add an instance (arguments as cosm_init; p->storage must match the batch).
- * Uploads it, builds its lane schedule, and returns its id (0, 1, ...). */
+ * Uploads it, builds its lane schedule, and returns its id (0, 1, ...).  The
+ * replicas per set (row width) are p->replicas_per_wg when given, else the
+ * width with the least time per replica among those that fit, measured by
+ * short probe runs of one full work item of the instance (as many replica
+ * sets as fit one workgroup, up to 128 sweeps; the stream is synchronised;
+ * results are cached per process by the instance's sizes, storage, replicas,
+ * sweeps and a hash of its edges and colouring). */
 int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
                          const int32_t *ev, const int32_t *J, const int32_t *colour,
                          int32_t num_colours, const cosm_params *p, uint64_t seed,
                          int32_t replicas, int32_t *graph_id_out);
+/* The shape an instance runs in: replicas per set, sets per work item, and
+ * how it was chosen (tuned: 0 one width fits or was requested, 1 timed probes,
+ * 2 the probe cache) with the chosen width's probe time (ms, one work item;
+ * 0 when not probed).
+ * Any output pointer may be NULL. */
+int cosm_batch_graph_shape(const cosm_batch *b, int32_t graph_id, int32_t *replicas_per_set,
+                           int32_t *sets_per_item, int32_t *tuned, double *probe_ms);
 /* Seed and global index of replica 0 used by the next run of that instance. */
 int cosm_batch_set_seed(cosm_batch *b, int32_t graph_id, uint64_t seed, int64_t replica_offset);
 /* Enqueue one whole trial (init, S sweeps, readout) of every listed instance.

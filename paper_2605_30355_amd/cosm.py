@@ -32,6 +32,7 @@ ABI_FUNCTIONS = (
     "cosm_last_error", "cosm_version", "cosm_lds_probe", "cosm_qubo_to_ising",
     "cosm_batch_create", "cosm_batch_destroy", "cosm_batch_add_graph", "cosm_batch_set_seed",
     "cosm_batch_run", "cosm_batch_wait", "cosm_batch_poll", "cosm_batch_results",
+    "cosm_batch_graph_shape",
 )
 
 
@@ -118,6 +119,8 @@ def load_library():
         "cosm_batch_wait": (I32, [P, ctypes.POINTER(ctypes.c_double)]),
         "cosm_batch_poll": (I32, [P, ctypes.POINTER(ctypes.c_int32)]),
         "cosm_batch_results": (I32, [P, I32, P, P, P]),
+        "cosm_batch_graph_shape": (I32, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                         ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]),
         "cosm_version": (ctypes.c_char_p, []),
         "cosm_lds_probe": (I32, [I32, I32, P, ctypes.POINTER(ctypes.c_double)]),
         "cosm_qubo_to_ising": (I32, [I32, I64, P, P, P, P, P, P, ctypes.POINTER(ctypes.c_int64), P,
@@ -381,6 +384,18 @@ class Batch:
             ctypes.byref(cp), int(seed) & ((1 << 64) - 1), int(replicas), ctypes.byref(gid)))
         self._sizes.append((int(n), int(replicas)))
         return int(gid.value)
+
+    def shape(self, graph_id):
+        """replicas per set, sets per work item, how they were chosen (0: one
+        width fits or was requested, 1: timed probes, 2: the probe cache) and
+        the chosen width's probe time in ms."""
+        rw, sets, tuned = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        ms = ctypes.c_double(0.0)
+        _check(load_library().cosm_batch_graph_shape(self._b, int(graph_id), ctypes.byref(rw),
+                                                     ctypes.byref(sets), ctypes.byref(tuned),
+                                                     ctypes.byref(ms)))
+        return {"replicas_per_set": rw.value, "sets_per_item": sets.value, "tuned": tuned.value,
+                "probe_ms": ms.value}
 
     def set_seed(self, graph_id, seed, replica_offset=0):
         _check(load_library().cosm_batch_set_seed(self._b, int(graph_id),

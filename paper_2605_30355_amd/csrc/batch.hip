@@ -16,6 +16,8 @@
 // replayed for every run.
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 
 #include "device_common.hpp"
@@ -267,6 +269,8 @@ struct BatchGraphHost {
   void *mem = nullptr;      // one hipMalloc holding every buffer below
   GraphDev dev{};
   int32_t sets_max = 1;     // replica sets that fit one workgroup's LDS
+  int32_t tuned = 0;        // 1: the row width was chosen by timed probes (2: from the cache)
+  float probe_ms = 0.0f;    // the chosen width's probe time
 };
 
 struct cosm_batch {
@@ -307,6 +311,197 @@ void set_attrs(cosm_batch *b) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
   (void)hipFuncSetAttribute((const void *)k_batch_readout<ST>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->readout_lds);
+}
+
+// The run's tables (work items, per-graph descriptors and prefix sums), on
+// the device and synchronised, for the graphs ids (valid ids of b->graphs).
+int prepare_run(cosm_batch *b, const std::vector<int32_t> &ids, bool fill = true) {
+  const int32_t count = (int32_t)ids.size();
+  // work items: split every graph's replicas into items of up to sets_max sets,
+  // shrinking the sets (fill) while the run would leave CUs without an item
+  std::vector<int32_t> sets(ids.size());
+  for (size_t k = 0; k < ids.size(); k++) sets[k] = b->graphs[(size_t)ids[k]]->sets_max;
+  const int32_t pw = (b->storage == COSM_STORE_FP32 || b->storage == COSM_STORE_FIX32) ? 1 : 2;
+  auto count_items = [&]() {
+    int64_t total = 0;
+    for (size_t k = 0; k < ids.size(); k++) {
+      const GraphDev &d = b->graphs[(size_t)ids[k]]->dev;
+      const int32_t rw = d.W * pw;
+      total += (d.R + rw * sets[k] - 1) / (rw * sets[k]);
+    }
+    return total;
+  };
+  while (fill && count_items() < 2 * (int64_t)b->cus) {
+    bool shrunk = false;
+    for (auto &v : sets)
+      if (v > 1) {
+        v = (v + 1) / 2;
+        shrunk = true;
+      }
+    if (!shrunk) break;
+  }
+  std::vector<Item> items;
+  std::vector<double> cost;
+  for (size_t k = 0; k < ids.size(); k++) {
+    const GraphDev &d = b->graphs[(size_t)ids[k]]->dev;
+    const int32_t rw = d.W * pw;
+    for (int32_t r0 = 0; r0 < d.R; r0 += rw * sets[k]) {
+      const int32_t ns = std::min(sets[k], (d.R - r0 + rw - 1) / rw);
+      items.push_back(Item{ids[k], r0, ns, 0});
+      cost.push_back((double)ns * (double)(b->graphs[(size_t)ids[k]]->meta.m + d.n) * (double)d.S);
+    }
+  }
+  if ((int64_t)items.size() > b->max_items) {
+    // grow the item table; the captured graph points at the old one, so drop it
+    COSM_HIP_CHECK(hipStreamSynchronize(b->stream));
+    const int32_t cap = (int32_t)std::min<int64_t>((int64_t)items.size() * 2, 1 << 28);
+    Item *fresh = nullptr;
+    if (hipMalloc(&fresh, sizeof(Item) * (size_t)cap) != hipSuccess)
+      return set_error(COSM_ENOMEM, "hipMalloc of the work-item table failed");
+    (void)hipFree(b->d_items);
+    b->d_items = fresh;
+    b->max_items = cap;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+  }
+  // largest items first (longest-processing-time order)
+  std::vector<size_t> order(items.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return cost[a] > cost[c]; });
+  std::vector<Item> sorted;
+  for (size_t k : order) sorted.push_back(items[k]);
+  RunDesc rd{};
+  rd.n_items = (int32_t)sorted.size();
+  rd.n_run = count;
+  std::vector<int64_t> phase_prefix((size_t)count + 1, 0);
+  std::vector<int32_t> rep_prefix((size_t)count + 1, 0);
+  for (int32_t k = 0; k < count; k++) {
+    const GraphDev &d = b->graphs[(size_t)ids[(size_t)k]]->dev;
+    phase_prefix[(size_t)k + 1] = phase_prefix[(size_t)k] + (int64_t)d.n * d.R;
+    rep_prefix[(size_t)k + 1] = rep_prefix[(size_t)k] + d.R;
+  }
+  rd.total_phases = phase_prefix[(size_t)count];
+  rd.total_replicas = rep_prefix[(size_t)count];
+  std::vector<GraphDev> gd;
+  for (BatchGraphHost *g : b->graphs) gd.push_back(g->dev);
+  int rc = COSM_OK;
+  auto up = [&](void *dst, const void *src, size_t bytes) {
+    if (rc == COSM_OK && bytes &&
+        hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+      rc = set_error(COSM_EDEVICE, "hipMemcpyAsync");
+  };
+  up(b->d_graphs, gd.data(), gd.size() * sizeof(GraphDev));
+  up(b->d_items, sorted.data(), sorted.size() * sizeof(Item));
+  up(b->d_run, &rd, sizeof rd);
+  up(b->d_run_graphs, ids.data(), ids.size() * 4);
+  up(b->d_rep_prefix, rep_prefix.data(), rep_prefix.size() * 4);
+  up(b->d_phase_prefix, phase_prefix.data(), phase_prefix.size() * 8);
+  if (rc) return rc;
+  // the host tables above are read by the copies: wait before they go out of scope
+  COSM_HIP_CHECK(hipStreamSynchronize(b->stream));
+  return COSM_OK;
+}
+
+int launch_run(cosm_batch *b) {
+  switch (b->storage) {
+    case COSM_STORE_FP32: enqueue_run<COSM_STORE_FP32>(b); break;
+    case COSM_STORE_FP16: enqueue_run<COSM_STORE_FP16>(b); break;
+    case COSM_STORE_BF16: enqueue_run<COSM_STORE_BF16>(b); break;
+    case COSM_STORE_FIX16: enqueue_run<COSM_STORE_FIX16>(b); break;
+    default: enqueue_run<COSM_STORE_FIX32>(b); break;
+  }
+  return check_launch("batch run");
+}
+
+// The row width of a graph by measurement.  Each candidate's lane schedule is
+// installed (install(k)) and a probe is timed with events through the run
+// path: one work item of the graph as a full batch lays it out (as many
+// replica sets as fit, never shrunk to fill the chip), up to 128 sweeps.  A
+// busy batch keeps every CU on one such item at a time, so the time per
+// replica of that item is the graph's cost per replica in the batch; the
+// width with the least is kept.  (Timing the graph alone with all its
+// replicas would instead favour the narrow rows that spread a lone graph over
+// more CUs.)  The choice is cached by the instance's signature (sizes,
+// storage, replicas, sweeps and an FNV-1a hash of the edge list and
+// colouring), so later graphs with the same signature skip the probes.  The
+// probe overwrites only the graph's own first replicas' phases and results,
+// which every run initialises afresh.
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, std::pair<int32_t, float>> g_tune_cache;  // width, probe ms
+
+template <typename Install>
+int tune_batch_graph(cosm_batch *b, BatchGraphHost *g, const std::vector<int32_t> &widths,
+                     Install install) {
+  const cosm_state &s = g->meta;
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](uint32_t v) {
+    for (int q = 0; q < 4; q++) h = (h ^ ((v >> (8 * q)) & 0xffu)) * 1099511628211ull;
+  };
+  for (int64_t k = 0; k < s.m; k++) {
+    mix((uint32_t)s.h_eu[(size_t)k]);
+    mix((uint32_t)s.h_ev[(size_t)k]);
+    mix((uint32_t)s.h_colour[(size_t)k]);
+  }
+  const std::vector<int64_t> key{s.n, s.m, s.C, s.R, b->storage, s.p.sweeps_per_trial, (int64_t)h};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end())
+      for (size_t k = 0; k < widths.size(); k++)
+        if (widths[k] == it->second.first) {
+          install(k);
+          g->tuned = 2;
+          g->probe_ms = it->second.second;
+          return COSM_OK;
+        }
+  }
+  COSM_HIP_CHECK(hipStreamSynchronize(b->stream));
+  const int64_t full_S = g->dev.S;
+  const int32_t full_R = g->dev.R;
+  const int32_t pw = (b->storage == COSM_STORE_FP32 || b->storage == COSM_STORE_FIX32) ? 1 : 2;
+  g->dev.S = std::min<int64_t>(full_S, 128);
+  const int32_t gid = (int32_t)b->graphs.size();
+  b->graphs.push_back(g);  // (for the probes only)
+  int rc = COSM_OK;
+  float best_ms = 0.0f;
+  double best_per_replica = 0.0;
+  size_t best = 0;
+  for (size_t k = 0; k < widths.size() && rc == COSM_OK; k++) {
+    install(k);
+    // one full work item: the first replicas only
+    g->dev.R = std::min<int32_t>(full_R, g->dev.W * pw * g->sets_max);
+    g->dev.ro.R = g->dev.R;
+    rc = prepare_run(b, {gid}, false);
+    float ms = 0.0f, ms_min = 0.0f;
+    for (int rep = 0; rep < 3 && rc == COSM_OK; rep++) {  // a warm-up, then two timed probes
+      if (hipEventRecord(b->e0, b->stream) != hipSuccess) rc = set_error(COSM_EDEVICE, "event");
+      if (rc == COSM_OK) rc = launch_run(b);
+      if (rc == COSM_OK && (hipEventRecord(b->e1, b->stream) != hipSuccess ||
+                            hipEventSynchronize(b->e1) != hipSuccess))
+        rc = set_error(COSM_EDEVICE, "event");
+      if (rc == COSM_OK) (void)hipEventElapsedTime(&ms, b->e0, b->e1);
+      if (rep == 1 || (rep == 2 && ms < ms_min)) ms_min = ms;
+    }
+    const double per_replica = (double)ms_min / (double)g->dev.R;
+    if (rc == COSM_OK && (k == 0 || per_replica < best_per_replica)) {
+      best_per_replica = per_replica;
+      best_ms = ms_min;
+      best = k;
+    }
+  }
+  b->graphs.pop_back();
+  g->dev.S = full_S;
+  g->dev.R = full_R;
+  g->dev.ro.R = full_R;
+  if (rc) return rc;
+  install(best);
+  g->tuned = 1;
+  g->probe_ms = best_ms;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = {widths[best], best_ms};
+  return COSM_OK;
 }
 
 }  // namespace
@@ -443,21 +638,39 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
     for (int64_t w : wdeg) s.wdeg_max = std::max(s.wdeg_max, w);
   }
   int rc = make_schedule(s.p, max_abs_J, &s.sched);
-  // row width: the widest that leaves room for at least one replica set
+  // Row widths: those that leave room for at least one replica set (a
+  // requested replicas_per_wg picks one); each gets its lane schedule.  With
+  // more than one, the shape is chosen by timed probes (below).
   const int32_t pw = (b->storage == COSM_STORE_FP32 || b->storage == COSM_STORE_FIX32) ? 1 : 2;
-  int32_t W = 0;
-  for (int32_t w : {4, 2, 1})
-    if (W == 0 && (size_t)n * w * 4 + 2 * kMaxSetReplicas * 4 + (size_t)num_colours * 4 <= b->lds_budget) W = w;
-  if (rc == COSM_OK && W == 0) rc = set_error(COSM_ERANGE, "graph does not fit one workgroup's LDS");
-  if (rc == COSM_OK) rc = build_lds_schedule(s, W, kBatchThreads, &s.lds);
+  std::vector<int32_t> widths;
+  for (int32_t w : {4, 2, 1}) {
+    if ((size_t)n * w * 4 + 2 * kMaxSetReplicas * 4 + (size_t)num_colours * 4 > b->lds_budget) continue;
+    if (p->replicas_per_wg > 0 && p->replicas_per_wg != w * pw) continue;
+    widths.push_back(w);
+  }
+  if (rc == COSM_OK && widths.empty())
+    rc = set_error(COSM_ERANGE, p->replicas_per_wg > 0
+                                    ? "requested replicas per set do not fit one workgroup's LDS"
+                                    : "graph does not fit one workgroup's LDS");
+  std::vector<LdsSchedule> scheds(widths.size());
+  size_t desc_max = 0;
+  for (size_t k = 0; k < widths.size() && rc == COSM_OK; k++) {
+    rc = build_lds_schedule(s, widths[k], kBatchThreads, &scheds[k]);
+    desc_max = std::max(desc_max, scheds[k].desc.size());
+  }
   if (rc) {
     delete g;
     return rc;
   }
-  const int32_t RW = W * pw;
-  g->sets_max = (int32_t)std::max<size_t>(
-      1, std::min<size_t>((b->lds_budget - 2 * kMaxSetReplicas * 4 - (size_t)num_colours * 4) / ((size_t)n * W * 4),
-                          kMaxSetReplicas / RW));
+  int32_t W = widths[0];
+  s.lds = scheds[0];
+  auto sets_for = [&](int32_t w) {
+    return (int32_t)std::max<size_t>(
+        1, std::min<size_t>((b->lds_budget - 2 * kMaxSetReplicas * 4 - (size_t)num_colours * 4) /
+                                ((size_t)n * w * 4),
+                            (size_t)kMaxSetReplicas / (size_t)(w * pw)));
+  };
+  g->sets_max = sets_for(W);
   // device memory: phases, schedule, K, slot map, edges, spins, H, cut, best_p
   const size_t nr = (size_t)n * replicas, sb = pw == 1 ? 4 : 2;
   size_t off = 0;
@@ -466,7 +679,7 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
     off = (off + std::max<size_t>(bytes, 1) + 255) / 256 * 256;
     return at;
   };
-  const size_t o_ph = take(nr * sb), o_desc = take(s.lds.desc.size() * sizeof(EdgeDesc)),
+  const size_t o_ph = take(nr * sb), o_desc = take(desc_max * sizeof(EdgeDesc)),
                o_K = take((size_t)num_colours * 4), o_sv = take((size_t)n * 4),
                o_eu = take((size_t)m * 4), o_ev = take((size_t)m * 4), o_J = take((size_t)m * 4),
                o_sp = take(nr), o_H = take((size_t)replicas * 8), o_cut = take((size_t)replicas * 8),
@@ -480,9 +693,6 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
     if (rc == COSM_OK && bytes && hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
       rc = set_error(COSM_EDEVICE, "hipMemcpy");
   };
-  up(o_desc, s.lds.desc.data(), s.lds.desc.size() * sizeof(EdgeDesc));
-  up(o_K, s.lds.K.data(), s.lds.K.size() * 4);
-  up(o_sv, s.lds.slot_vertex.data(), s.lds.slot_vertex.size() * 4);
   up(o_eu, eu, (size_t)m * 4);
   up(o_ev, ev, (size_t)m * 4);
   up(o_J, J, (size_t)m * 4);
@@ -522,6 +732,23 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
   ro.B = s.p.n_bisectors;
   ro.grid = sc.grid;
   ro.m = m;
+  // the lane schedule of candidate k: its descriptors, slot counts and slot
+  // map on the device, its width and replica sets in the descriptor
+  auto install = [&](size_t k) {
+    s.lds = scheds[k];
+    W = widths[k];
+    d.W = W;
+    d.total_slots = s.lds.total_slots;
+    g->sets_max = sets_for(W);
+    up(o_desc, s.lds.desc.data(), s.lds.desc.size() * sizeof(EdgeDesc));
+    up(o_K, s.lds.K.data(), s.lds.K.size() * 4);
+    up(o_sv, s.lds.slot_vertex.data(), s.lds.slot_vertex.size() * 4);
+  };
+  install(0);
+  if (rc == COSM_OK && widths.size() > 1) {
+    const int rt = tune_batch_graph(b, g, widths, install);
+    if (rc == COSM_OK) rc = rt;  // (a failed upload inside install set rc itself)
+  }
   if (rc) {
     (void)hipFree(g->mem);
     delete g;
@@ -530,6 +757,20 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
   *graph_id_out = (int32_t)b->graphs.size();
   b->graphs.push_back(g);
   b->graphs_dirty = true;
+  return COSM_OK;
+}
+
+int cosm_batch_graph_shape(const cosm_batch *b, int32_t graph_id, int32_t *replicas_per_set,
+                           int32_t *sets_per_item, int32_t *tuned, double *probe_ms) {
+  clear_error();
+  if (b == nullptr || graph_id < 0 || graph_id >= (int32_t)b->graphs.size())
+    return set_error(COSM_EINVAL, "bad graph id");
+  const BatchGraphHost *g = b->graphs[(size_t)graph_id];
+  const int32_t pw = (b->storage == COSM_STORE_FP32 || b->storage == COSM_STORE_FIX32) ? 1 : 2;
+  if (replicas_per_set) *replicas_per_set = g->dev.W * pw;
+  if (sets_per_item) *sets_per_item = g->sets_max;
+  if (tuned) *tuned = g->tuned;
+  if (probe_ms) *probe_ms = g->probe_ms;
   return COSM_OK;
 }
 
@@ -554,90 +795,7 @@ int cosm_batch_run(cosm_batch *b, const int32_t *graph_ids, int32_t count) {
   std::vector<int32_t> ids(graph_ids, graph_ids + count);
   for (int32_t id : ids)
     if (id < 0 || id >= (int32_t)b->graphs.size()) return set_error(COSM_EINVAL, "bad graph id");
-  // work items: split every graph's replicas into items of up to sets_max sets,
-  // shrinking the sets while the run would leave CUs without an item
-  std::vector<int32_t> sets(ids.size());
-  for (size_t k = 0; k < ids.size(); k++) sets[k] = b->graphs[(size_t)ids[k]]->sets_max;
-  const int32_t pw = (b->storage == COSM_STORE_FP32 || b->storage == COSM_STORE_FIX32) ? 1 : 2;
-  auto count_items = [&]() {
-    int64_t total = 0;
-    for (size_t k = 0; k < ids.size(); k++) {
-      const GraphDev &d = b->graphs[(size_t)ids[k]]->dev;
-      const int32_t rw = d.W * pw;
-      total += (d.R + rw * sets[k] - 1) / (rw * sets[k]);
-    }
-    return total;
-  };
-  while (count_items() < 2 * (int64_t)b->cus) {
-    bool shrunk = false;
-    for (auto &v : sets)
-      if (v > 1) {
-        v = (v + 1) / 2;
-        shrunk = true;
-      }
-    if (!shrunk) break;
-  }
-  std::vector<Item> items;
-  std::vector<double> cost;
-  for (size_t k = 0; k < ids.size(); k++) {
-    const GraphDev &d = b->graphs[(size_t)ids[k]]->dev;
-    const int32_t rw = d.W * pw;
-    for (int32_t r0 = 0; r0 < d.R; r0 += rw * sets[k]) {
-      const int32_t ns = std::min(sets[k], (d.R - r0 + rw - 1) / rw);
-      items.push_back(Item{ids[k], r0, ns, 0});
-      cost.push_back((double)ns * (double)(b->graphs[(size_t)ids[k]]->meta.m + d.n) * (double)d.S);
-    }
-  }
-  if ((int64_t)items.size() > b->max_items) {
-    // grow the item table; the captured graph points at the old one, so drop it
-    COSM_HIP_CHECK(hipStreamSynchronize(b->stream));
-    const int32_t cap = (int32_t)std::min<int64_t>((int64_t)items.size() * 2, 1 << 28);
-    Item *fresh = nullptr;
-    if (hipMalloc(&fresh, sizeof(Item) * (size_t)cap) != hipSuccess)
-      return set_error(COSM_ENOMEM, "hipMalloc of the work-item table failed");
-    (void)hipFree(b->d_items);
-    b->d_items = fresh;
-    b->max_items = cap;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
-  }
-  // largest items first (longest-processing-time order)
-  std::vector<size_t> order(items.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return cost[a] > cost[c]; });
-  std::vector<Item> sorted;
-  for (size_t k : order) sorted.push_back(items[k]);
-  RunDesc rd{};
-  rd.n_items = (int32_t)sorted.size();
-  rd.n_run = count;
-  std::vector<int64_t> phase_prefix((size_t)count + 1, 0);
-  std::vector<int32_t> rep_prefix((size_t)count + 1, 0);
-  for (int32_t k = 0; k < count; k++) {
-    const GraphDev &d = b->graphs[(size_t)ids[(size_t)k]]->dev;
-    phase_prefix[(size_t)k + 1] = phase_prefix[(size_t)k] + (int64_t)d.n * d.R;
-    rep_prefix[(size_t)k + 1] = rep_prefix[(size_t)k] + d.R;
-  }
-  rd.total_phases = phase_prefix[(size_t)count];
-  rd.total_replicas = rep_prefix[(size_t)count];
-  std::vector<GraphDev> gd;
-  for (BatchGraphHost *g : b->graphs) gd.push_back(g->dev);
-  int rc = COSM_OK;
-  auto up = [&](void *dst, const void *src, size_t bytes) {
-    if (rc == COSM_OK && bytes &&
-        hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
-      rc = set_error(COSM_EDEVICE, "hipMemcpyAsync");
-  };
-  up(b->d_graphs, gd.data(), gd.size() * sizeof(GraphDev));
-  up(b->d_items, sorted.data(), sorted.size() * sizeof(Item));
-  up(b->d_run, &rd, sizeof rd);
-  up(b->d_run_graphs, ids.data(), ids.size() * 4);
-  up(b->d_rep_prefix, rep_prefix.data(), rep_prefix.size() * 4);
-  up(b->d_phase_prefix, phase_prefix.data(), phase_prefix.size() * 8);
-  if (rc) return rc;
-  // the host tables above are read by the copies: wait before they go out of scope
-  COSM_HIP_CHECK(hipStreamSynchronize(b->stream));
+  if (int rc = prepare_run(b, ids)) return rc;
   if (b->exec == nullptr) {
     COSM_HIP_CHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     switch (b->storage) {

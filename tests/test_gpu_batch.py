@@ -95,3 +95,32 @@ def test_batch_matches_oracle_sample():
     op = oracle.Params(sweeps=p.sweeps_per_trial, dwt_ratio=p.dwt_ratio, dwt_period=p.dwt_period)
     _, so, Ho, co = oracle.solve(prob, op, seed, 0, R)
     assert np.array_equal(H, Ho) and np.array_equal(cut, co) and np.array_equal(sp, so)
+
+
+def test_batch_shape_tuned_and_cached():
+    """The row width of each instance is measured when more than one fits,
+    taken from the per-process cache for an identical instance, and fixed by
+    replicas_per_wg when given; the tuned shape still gives the single-state
+    trajectory."""
+    # an instance and sweep count no other test in the process adds (the cache
+    # lives as long as the process)
+    t = ci.torus(22, seed=41)
+    c, C = cosm.build_partitions(t.n, t.eu, t.ev, cosm.COLOR_TORUS, [22, 22])
+    p = cosm.Params(sweeps_per_trial=301, dwt_ratio=0.5, dwt_period=3)
+    with cosm.Batch(max_graphs=4, max_n=500) as b:
+        g0 = b.add(t.n, t.eu, t.ev, t.J, c, C, p, seed=3, replicas=64)
+        g1 = b.add(t.n, t.eu, t.ev, t.J, c, C, p, seed=3, replicas=64)
+        q = cosm.Params(sweeps_per_trial=301, dwt_ratio=0.5, dwt_period=3, replicas_per_wg=1)
+        g2 = b.add(t.n, t.eu, t.ev, t.J, c, C, q, seed=3, replicas=64)
+        s0, s1, s2 = b.shape(g0), b.shape(g1), b.shape(g2)
+        say(f"[gpu] shapes {s0} {s1} {s2}")
+        assert s0["tuned"] == 1 and s0["probe_ms"] > 0.0
+        assert s1["tuned"] == 2 and s1["replicas_per_set"] == s0["replicas_per_set"]
+        assert s1["probe_ms"] == s0["probe_ms"]
+        assert s2["tuned"] == 0 and s2["replicas_per_set"] == 1
+        b.run([g0, g1, g2])
+        b.wait()
+        Hs, cs, ss = single(t, c, C, p, 3, 64)
+        for gid in (g0, g1, g2):
+            H, cut, sp = b.results(gid, return_spins=True)
+            assert np.array_equal(H, Hs) and np.array_equal(cut, cs) and np.array_equal(sp, ss)
