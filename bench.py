@@ -579,7 +579,7 @@ def lds_bytes(info, inst, R, S, period, storage_bytes):
     b = storage_bytes
     twists = S // period if period > 0 else 0
     algo = R * (S * 4 * b * inst.m + twists * 2 * b * inst.n)
-    if info.get("lds_form") == 2:
+    if info.get("lds_form") in (2, 3):
         er, nr = info["register_edges"], info["register_vertices"]
         moved = R * (S * b * (2 * er + 4 * (inst.m - er)) + twists * 2 * b * (inst.n - nr))
     else:
@@ -589,7 +589,7 @@ def lds_bytes(info, inst, R, S, period, storage_bytes):
 
 def large_bench(cases_wanted=None, S=None, reps=None):
     """The large-graph configurations: the 100x100 and 141x141 +-1 tori at 4096
-    replicas (FP32, FIX32, BF16 and FIX16 storage) and the 5-regular N = 20000 and
+    replicas (FP32, FIX32, FP16, BF16 and FIX16 storage) and the 5-regular N = 20000 and
     capped Erdos-Renyi N = 10000 graphs at 2048 replicas (FP32, FIX32): edge-updates/s
     of the sweep kernel (HIP events around whole sweep calls after a warm-up),
     the shape and layout the autotuner kept, and the LDS roofline fraction of the
@@ -602,16 +602,16 @@ def large_bench(cases_wanted=None, S=None, reps=None):
 
     torch.cuda.set_device(0)
     cases = [("torus-100x100", lambda: ci.torus(100, seed=3), cosm.COLOR_TORUS, [100, 100], 4096,
-              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "bf16", "fix16")),
+              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "fp16", "bf16", "fix16")),
              ("torus-141x141", lambda: ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141], 4096,
-              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "bf16", "fix16")),
+              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "fp16", "bf16", "fix16")),
              ("rr5-n20000", lambda: ci.random_regular(20000, 5, seed=1000, weights="pm1"),
               cosm.COLOR_BALANCED, None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32", "fix32")),
              ("er-n10000", lambda: ci.erdos_renyi_capped(10000, 4, 8, seed=3),
               cosm.COLOR_MISRA_GRIES, None, 2048, dict(dwt_ratio=1.5, dwt_period=3),
               ("fp32", "fix32"))]
-    storages = {"fp32": cosm.STORE_FP32, "fix32": cosm.STORE_FIX32, "bf16": cosm.STORE_BF16,
-                "fix16": cosm.STORE_FIX16}
+    storages = {"fp32": cosm.STORE_FP32, "fix32": cosm.STORE_FIX32, "fp16": cosm.STORE_FP16,
+                "bf16": cosm.STORE_BF16, "fix16": cosm.STORE_FIX16}
     S = S or LARGE["sweeps"]
     reps = reps or LARGE["reps"]
     stream = torch.cuda.current_stream()
@@ -640,14 +640,15 @@ def large_bench(cases_wanted=None, S=None, reps=None):
             info = st.info()
             st.close()
             rate = inst.m * S * R / sec
-            b = 2 if st_name in ("bf16", "fix16") else 4
+            b = 2 if st_name in ("fp16", "bf16", "fix16") else 4
             algo, moved = lds_bytes(info, inst, R, S, kw["dwt_period"], b)
             form = {cosm.RES_LDS: "lds", cosm.RES_HBM: "hbm"}.get(info["residency"], "plain")
             rec = {"workload": name, "n": inst.n, "m": inst.m, "classes": C, "replicas": R,
                    "storage": st_name, "edge_updates_per_s": round(rate, 1),
                    "replica_sweeps_per_s": round(S * R / sec, 1), "form": form,
-                   "layout": {1: "pair", 2: "register"}.get(info["lds_form"], None),
+                   "layout": {1: "pair", 2: "register", 3: "register-stream"}.get(info["lds_form"], None),
                    "register_rows": info["register_rows"], "twist_fused": info["twist_fused"],
+                   "streamed": info["streamed"], "lazy_wrap": info["lazy_wrap"],
                    "replicas_per_wg": info["replicas_per_wg"],
                    "threads_per_wg": info["threads_per_wg"],
                    "lds_roofline_frac": round(algo / sec / (LDS_PEAK_GBS * 1e9), 3),
@@ -689,7 +690,7 @@ def maxcut_legs(args):
     out = {"workload": WORKLOAD["name"], "n": inst.n, "edges": m, "classes": C, "replicas": R,
            "sweeps": S, "colouring": "misra-gries, class sizes equalised",
            "replicas_per_wg": info["replicas_per_wg"], "threads_per_wg": info["threads_per_wg"],
-           "layout": {1: "pair", 2: "register"}.get(info["lds_form"], None),
+           "layout": {1: "pair", 2: "register", 3: "register-stream"}.get(info["lds_form"], None),
            "sweep_kernel_edge_updates_per_s": round(batched_rate, 1),
            "sweep_kernel_lds_roofline_frac": round(algo / kernel_s / (LDS_PEAK_GBS * 1e9), 4)}
     log(f"maxcut batched: {batched_rate:.3e} edge-updates/s, shape {info}")
@@ -775,6 +776,8 @@ def main():
                     help="run the Max-Cut legs only (batched, plain, time to target; own JSON line)")
     ap.add_argument("--large", action="store_true",
                     help="measure the large tori and bounded-degree graphs instead (own JSON line)")
+    ap.add_argument("--only", nargs="+", default=None, metavar="CASE:STORAGE",
+                    help="with --large: just these cases, e.g. torus-141x141:bf16")
     ap.add_argument("--seeds", type=int, nargs="?", const=SEEDS["count"], default=None,
                     help="time to target over N instance seeds of the 5-regular family instead")
     ap.add_argument("--seeds-jsonl", default=None,
@@ -797,7 +800,13 @@ def main():
         print(json.dumps(scaling_bench()), flush=True)
         return
     if args.large:
-        print(json.dumps(large_bench()), flush=True)
+        wanted = None
+        if args.only:
+            wanted = {}
+            for item in args.only:
+                case, st_name = item.split(":")
+                wanted[case] = wanted.get(case, ()) + (st_name,)
+        print(json.dumps(large_bench(wanted)), flush=True)
         return
     if args.maxcut:
         import torch
@@ -869,7 +878,7 @@ def main():
     achieved = algo / avg_kernel_s / 1e9
     row_words = info["replicas_per_wg"]  # FP32: one word per replica
     measured = max(cosm.lds_probe(row_words, bpc) for bpc in (1, 2))
-    layout = {1: "pair", 2: "register"}.get(info["lds_form"], None)
+    layout = {1: "pair", 2: "register", 3: "register-stream"}.get(info["lds_form"], None)
     roofline = {"bound": "lds", "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
                 "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
                 "traffic": traffic_bytes(), "traffic_unit": "HBM bytes per launch",
@@ -911,8 +920,8 @@ def main():
     }
     if not args.no_extra:
         out["maxcut"] = maxcut_legs(args)
-        out["large"] = large_bench({"torus-100x100": ("fp32", "bf16", "fix16"),
-                                    "torus-141x141": ("bf16", "fix16"),
+        out["large"] = large_bench({"torus-100x100": ("fp32", "fp16", "bf16", "fix16"),
+                                    "torus-141x141": ("fp16", "bf16", "fix16"),
                                     "rr5-n20000": ("fp32",), "er-n10000": ("fp32",)})["cases"]
         if "maxcut" in out:
             mc = out["maxcut"]

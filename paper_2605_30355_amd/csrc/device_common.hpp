@@ -279,15 +279,39 @@ __device__ __forceinline__ void lds_store(uint32_t *base, int slot, const uint32
   }
 }
 
+// FP16 value of v (round to nearest even), as an FP32 number.
+__device__ __forceinline__ float round_h(float v) { return (float)(_Float16)v; }
+
 // Eq. (6) for one (edge, replica): values in the storage's convention.
 // LAZY: no wrap (phases wrapped at the twists only; fract(x_u - x_v) does not
 // need wrapped operands).
+// FP16 storage computes in FP16 arithmetic, each step rounded to FP16 as the
+// packed form in update_words does it: e = y_u - y_v; the coupling is positive
+// (fract(e) < 1/2) when round(2e - 1/2) is even, round to nearest even (an
+// exact half-turn difference counts as positive); step +-alpha J rounded to
+// FP16; y_u - step, y_v + step rounded to FP16; the wrap y - rint(y) is then
+// exact.  FP32 steps on FP16 operands give these results: an FP32 result of
+// one operation rounded again to FP16 equals its direct FP16 rounding
+// (24 >= 2 x 11 + 2 bits).
 template <int ST, bool LAZY = false>
 __device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ) {
-  const float f = fract1(xu - xv);
-  const float dl = (f < 0.5f) ? aJ : -aJ;
-  xu = LAZY ? xu - dl : Fmt<ST>::wrap(xu - dl);
-  xv = LAZY ? xv + dl : Fmt<ST>::wrap(xv + dl);
+  if constexpr (ST == COSM_STORE_FP16) {
+    const float e = round_h(xu - xv);
+    const float t = round_h(__builtin_fmaf(2.0f, e, -0.5f));
+    const float st = round_h(aJ);
+    const float dl = ((int32_t)__builtin_rintf(t) & 1) ? -st : st;
+    xu = round_h(xu - dl);
+    xv = round_h(xv + dl);
+    if constexpr (!LAZY) {
+      xu -= __builtin_rintf(xu);
+      xv -= __builtin_rintf(xv);
+    }
+  } else {
+    const float f = fract1(xu - xv);
+    const float dl = (f < 0.5f) ? aJ : -aJ;
+    xu = LAZY ? xu - dl : Fmt<ST>::wrap(xu - dl);
+    xv = LAZY ? xv + dl : Fmt<ST>::wrap(xv + dl);
+  }
 }
 
 // Eq. (6) between x (storage convention) and a fixed virtual spin at phase 0
@@ -466,10 +490,35 @@ __device__ __forceinline__ void row_store(uint32_t addr, const uint32_t (&w)[W])
 // lane difference u - v wraps to the signed difference in [-1/2, 1/2) turn,
 // whose sign bit selects -step or +step, and the updates wrap by overflow.
 // FIX32: the same on one 32-bit integer per replica.
+// FP16: two replicas per word in packed FP16 arithmetic (pair_update's steps):
+// r = (2e - 1/2) + 1536 lies in [1024, 2048), where FP16 has unit spacing, so
+// its lowest bit is the parity of round(2e - 1/2); shifted to the sign bit it
+// flips the step's sign.  The wrap subtracts (y + 1536) - 1536 = rint(y).
 // Other formats: unpack, the FP32 update, pack.
 template <int ST, int W, bool LAZY = false>
 __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
-  if constexpr (ST == COSM_STORE_FIX32) {
+  if constexpr (ST == COSM_STORE_FP16) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const uint32_t sb = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)aJ);
+    const uint32_t step = sb | (sb << 16);
+    const h2 two = {(_Float16)2.0f, (_Float16)2.0f};
+    const h2 mhalf = {(_Float16)-0.5f, (_Float16)-0.5f};
+    const h2 mag = {(_Float16)1536.0f, (_Float16)1536.0f};
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      const h2 u = __builtin_bit_cast(h2, wu[k]), v = __builtin_bit_cast(h2, wv[k]);
+      const h2 r = __builtin_elementwise_fma(u - v, two, mhalf) + mag;
+      const h2 dl = __builtin_bit_cast(h2, step ^ ((__builtin_bit_cast(uint32_t, r) << 15) &
+                                                   0x80008000u));
+      h2 nu = u - dl, nv = v + dl;
+      if constexpr (!LAZY) {
+        nu = nu - ((nu + mag) - mag);
+        nv = nv - ((nv + mag) - mag);
+      }
+      wu[k] = __builtin_bit_cast(uint32_t, nu);
+      wv[k] = __builtin_bit_cast(uint32_t, nv);
+    }
+  } else if constexpr (ST == COSM_STORE_FIX32) {
     // aJ is an integer of magnitude below 2^31 (|alpha J| < 1/2 turn on the
     // grid): the conversion is exact
     const uint32_t st = (uint32_t)(int32_t)aJ, nst = 0u - st;

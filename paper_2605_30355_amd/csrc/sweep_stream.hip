@@ -68,6 +68,10 @@ struct StreamArgs {
 // fraction (2^-11 turn for FP16, 2^-8 for BF16) until the next twist wraps it.
 template <int ST, int W>
 __device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
+  if constexpr (ST == COSM_STORE_FP16) {  // packed FP16 arithmetic
+    update_words<ST, W, true>(wu, wv, aJ);
+    return;
+  }
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
   float xu[RW], xv[RW];

@@ -122,7 +122,8 @@ def test_sixteen_bit_phase_error_first_sweeps(store):
 # ---------------------------------------------------------------------------
 # The large torus (the 100 x 100 +-1 torus, the shape of the G72-like
 # configuration), 1024 replicas a side, 1000 sweeps: FP16 and BF16 storage
-# (FP32 arithmetic, the streamed LDS form at 4 or 8 replicas per workgroup)
+# (FP16 and FP32 arithmetic respectively, the streamed LDS form at 4 or 8
+# replicas per workgroup)
 # against the oracle's grid schedule, and FP32 with the continuous schedule
 # against the oracle's continuous schedule.
 # ---------------------------------------------------------------------------
