@@ -485,8 +485,11 @@ SEED_FAMILIES = {
 }
 
 
-def seeds_bench(count=None, jsonl=None, family="rr5"):
-    """Median and interquartile range of TTT @99% over instance seeds."""
+def seeds_bench(count=None, jsonl=None, family="rr5", sweeps=None):
+    """Median and interquartile range of TTT @99% over instance seeds.  With a
+    JSONL file, each instance's record there also carries the spins of its
+    target trial (packed bits, hex), for tests/golden/verify_seed_targets.py to
+    re-evaluate with the FP64 oracle."""
     import numpy as np
     import torch
 
@@ -497,6 +500,8 @@ def seeds_bench(count=None, jsonl=None, family="rr5"):
     cfg = dict(SEEDS)
     if count is not None:
         cfg["count"] = count
+    if sweeps is not None:
+        cfg["sweeps"] = sweeps
     fam = SEED_FAMILIES[family]
     cfg.update(family=family, n=fam["n"], colouring=fam["colouring"])
     R, S = cfg["replicas"], cfg["sweeps"]
@@ -514,12 +519,14 @@ def seeds_bench(count=None, jsonl=None, family="rr5"):
                         lds_form=cosm.LDS_FORM_PAIR, replicas_per_wg=fam["rw"],
                         threads_per_wg=1024)
         st = cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=1, replicas=R)
-        best = None
+        best, best_spins = None, None
         for b in range(cfg["target_batches"]):
             st.reset(1, b * R)
             st.sweep(S)
-            H, _, _ = st.energy(return_spins=False)
-            best = int(H.min()) if best is None else min(best, int(H.min()))
+            H, _, sp = st.energy(return_spins=True)
+            i = int(np.argmin(H))
+            if best is None or int(H[i]) < best:
+                best, best_spins = int(H[i]), sp[i].copy()
         Hs, ms = [], 0.0
         for b in range(cfg["ttt_batches"]):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -547,7 +554,8 @@ def seeds_bench(count=None, jsonl=None, family="rr5"):
         log(f"seeds {rec}")
         if jsonl is not None:
             with open(jsonl, "a") as f:
-                f.write(json.dumps(rec) + "\n")
+                f.write(json.dumps(dict(rec, family=family, sweeps=S, target_spins_hex=np.packbits(
+                    best_spins > 0).tobytes().hex())) + "\n")
 
     def summary(label):
         # nearest-rank quartiles over every instance, an instance without a hit
@@ -566,6 +574,10 @@ def seeds_bench(count=None, jsonl=None, family="rr5"):
     return {"metric": f"time to target @99% over instance seeds, {family} +-1 graphs, 1 MI355X",
             "config": {k: v for k, v in cfg.items()}, "solver": f"FP32, grid schedule, pair layout "
             f"{fam['rw']} replicas x 1024 threads, alpha0 14, dwt ratio 1.5 period 3, 100 bisectors",
+            "fidelity": f"{S} sweeps per trial; the targets are the best of "
+            f"{cfg['target_batches'] * R} GPU trials per instance, not oracle ground states (their "
+            "spins, written to the JSONL file, are re-evaluated by the FP64 oracle in "
+            "tests/golden/verify_seed_targets.py)",
             "t_trial_s_median": float(np.median([r["t_trial_s"] for r in recs])),
             "target": summary("target"), "relaxed": summary("relaxed"), "instances": recs}
 
@@ -780,6 +792,8 @@ def main():
                     help="with --large: just these cases, e.g. torus-141x141:bf16")
     ap.add_argument("--seeds", type=int, nargs="?", const=SEEDS["count"], default=None,
                     help="time to target over N instance seeds of the 5-regular family instead")
+    ap.add_argument("--sweeps", type=int, default=None,
+                    help="with --seeds: sweeps per trial (default %d)" % SEEDS["sweeps"])
     ap.add_argument("--seeds-jsonl", default=None,
                     help="with --seeds: also append each instance's record to this file")
     ap.add_argument("--family", default="rr5", choices=sorted(SEED_FAMILIES),
@@ -814,7 +828,8 @@ def main():
         print(json.dumps(maxcut_legs(args)), flush=True)
         return
     if args.seeds is not None:
-        print(json.dumps(seeds_bench(args.seeds, args.seeds_jsonl, args.family)), flush=True)
+        print(json.dumps(seeds_bench(args.seeds, args.seeds_jsonl, args.family, args.sweeps)),
+              flush=True)
         return
 
     import torch
