@@ -894,6 +894,8 @@ def main():
     row_words = info["replicas_per_wg"]  # FP32: one word per replica
     measured = max(cosm.lds_probe(row_words, bpc) for bpc in (1, 2))
     layout = {1: "pair", 2: "register", 3: "register-stream"}.get(info["lds_form"], None)
+    if info["streamed"] and info["lds_form"] == 1:
+        layout = "streamed pair"
     roofline = {"bound": "lds", "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
                 "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
                 "traffic": traffic_bytes(), "traffic_unit": "HBM bytes per launch",
@@ -902,7 +904,8 @@ def main():
                                       f"{4 * row_words}-byte rows, no arithmetic or barriers",
                 "frac_of_measured": round(achieved / measured, 4),
                 "moved_frac": round(moved / avg_kernel_s / 1e9 / LDS_PEAK_GBS, 4),
-                "kernel": f"sweep kernel, fp32, {row_words} words/row, {layout} layout",
+                "kernel": f"sweep kernel, fp32, {row_words} words/row, {layout} layout"
+                          + (", wrapped at the twists" if info["lazy_wrap"] else ""),
                 "bytes_per_edge_update": 16,
                 "bytes_per_launch": algo,
                 "kernel_ms": round(avg_kernel_s * 1e3, 4),
