@@ -304,10 +304,12 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
 /* The shape an instance runs in: replicas per set, sets per work item, and
  * how it was chosen (tuned: 0 one width fits or was requested, 1 timed probes,
  * 2 the probe cache) with the chosen width's probe time (ms, one work item;
- * 0 when not probed).
+ * 0 when not probed), and lazy_wrap: 1 when its phases are wrapped at the
+ * twists only (FP16 / BF16 within the drift bound of cosm_info.lazy_wrap).
  * Any output pointer may be NULL. */
 int cosm_batch_graph_shape(const cosm_batch *b, int32_t graph_id, int32_t *replicas_per_set,
-                           int32_t *sets_per_item, int32_t *tuned, double *probe_ms);
+                           int32_t *sets_per_item, int32_t *tuned, double *probe_ms,
+                           int32_t *lazy_wrap);
 /* Seed and global index of replica 0 used by the next run of that instance. */
 int cosm_batch_set_seed(cosm_batch *b, int32_t graph_id, uint64_t seed, int64_t replica_offset);
 /* Enqueue one whole trial (init, S sweeps, readout) of every listed instance.

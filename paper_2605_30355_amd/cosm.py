@@ -120,7 +120,8 @@ def load_library():
         "cosm_batch_poll": (I32, [P, ctypes.POINTER(ctypes.c_int32)]),
         "cosm_batch_results": (I32, [P, I32, P, P, P]),
         "cosm_batch_graph_shape": (I32, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
-                                         ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]),
+                                         ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(I32)]),
         "cosm_version": (ctypes.c_char_p, []),
         "cosm_lds_probe": (I32, [I32, I32, P, ctypes.POINTER(ctypes.c_double)]),
         "cosm_qubo_to_ising": (I32, [I32, I64, P, P, P, P, P, P, ctypes.POINTER(ctypes.c_int64), P,
@@ -387,15 +388,16 @@ class Batch:
 
     def shape(self, graph_id):
         """replicas per set, sets per work item, how they were chosen (0: one
-        width fits or was requested, 1: timed probes, 2: the probe cache) and
-        the chosen width's probe time in ms."""
+        width fits or was requested, 1: timed probes, 2: the probe cache), the
+        chosen width's probe time in ms, and whether the phases are wrapped at
+        the twists only."""
         rw, sets, tuned = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
-        ms = ctypes.c_double(0.0)
+        ms, lazy = ctypes.c_double(0.0), ctypes.c_int32(0)
         _check(load_library().cosm_batch_graph_shape(self._b, int(graph_id), ctypes.byref(rw),
                                                      ctypes.byref(sets), ctypes.byref(tuned),
-                                                     ctypes.byref(ms)))
+                                                     ctypes.byref(ms), ctypes.byref(lazy)))
         return {"replicas_per_set": rw.value, "sets_per_item": sets.value, "tuned": tuned.value,
-                "probe_ms": ms.value}
+                "probe_ms": ms.value, "lazy_wrap": lazy.value}
 
     def set_seed(self, graph_id, seed, replica_offset=0):
         _check(load_library().cosm_batch_set_seed(self._b, int(graph_id),

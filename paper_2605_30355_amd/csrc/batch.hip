@@ -97,7 +97,9 @@ template <int ST, int W>
 __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
   using F = Fmt<ST>;
   // FP16 / BF16: wrapped at the twists only when the graph's drift bound holds
-  constexpr bool kLazy16 = ST == COSM_STORE_FP16 || ST == COSM_STORE_BF16;
+  // (g.lazy, set by the host).  (FP32 on the grid could be too, exactly, but a
+  // second FP32 sweep path in this kernel made the mixed stream 5 % slower.)
+  constexpr bool kLazyOk = ST == COSM_STORE_FP16 || ST == COSM_STORE_BF16;
   constexpr int RW = W * F::kPerWord;
   constexpr uint32_t ROWB = 4 * W;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -142,9 +144,9 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
     chunk.get((t - 1) & 63u, alpha, twist);
     const float alpha_s = alpha * F::kStepScale;
     if (g.total_slots > 0) {
-      if (kLazy16 && g.lazy) {
+      if (kLazyOk && g.lazy) {
         stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
-          edge_rows_sets<ST, W, kLazy16>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
+          edge_rows_sets<ST, W, kLazyOk>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
                                          set_bytes, nsets, alpha_s * d.J);
         });
       } else {
@@ -183,7 +185,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
 #pragma unroll
           for (int q = 0; q < 2; q++) {
             if (s0 + q * nth < g.n) {
-              if (kLazy16 && g.lazy) twist_row<ST, W, kLazy16>(op, w[q]);
+              if (kLazyOk && g.lazy) twist_row<ST, W, kLazyOk>(op, w[q]);
               else op.apply(w[q]);
               lds_store<W>(set, s0 + q * nth, w[q]);
             }
@@ -205,7 +207,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
     F::template unpack<W>(w, v);
 #pragma unroll
     for (int q = 0; q < RW; q++)
-      if (q < nvalid) F::store_elem(g.phases, base + q, kLazy16 && g.lazy ? F::wrap(v[q]) : v[q]);
+      if (q < nvalid) F::store_elem(g.phases, base + q, kLazyOk && g.lazy ? F::wrap(v[q]) : v[q]);
   }
 }
 
@@ -761,7 +763,8 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
 }
 
 int cosm_batch_graph_shape(const cosm_batch *b, int32_t graph_id, int32_t *replicas_per_set,
-                           int32_t *sets_per_item, int32_t *tuned, double *probe_ms) {
+                           int32_t *sets_per_item, int32_t *tuned, double *probe_ms,
+                           int32_t *lazy_wrap) {
   clear_error();
   if (b == nullptr || graph_id < 0 || graph_id >= (int32_t)b->graphs.size())
     return set_error(COSM_EINVAL, "bad graph id");
@@ -771,6 +774,7 @@ int cosm_batch_graph_shape(const cosm_batch *b, int32_t graph_id, int32_t *repli
   if (sets_per_item) *sets_per_item = g->sets_max;
   if (tuned) *tuned = g->tuned;
   if (probe_ms) *probe_ms = g->probe_ms;
+  if (lazy_wrap) *lazy_wrap = g->dev.lazy;
   return COSM_OK;
 }
 

@@ -277,9 +277,23 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
     }
     jsw -= (uint32_t)a.total_slots;  // the next sweep's first words are in flight
 
-    // Dual window twist every `period` sweeps, after the last class
+    // Dual window twist every `period` sweeps, after the last class: whole
+    // groups of four rows per thread with no bounds checks (branch-free, the
+    // four reads in flight together), then the remaining rows checked
     if (twist_now) {
-      for (int s0 = tid; s0 < a.n_rows; s0 += 4 * nth) {
+      const int groups = a.n_rows / (4 * nth);  // uniform
+      int s0 = tid;
+      for (int g = 0; g < groups; g++, s0 += 4 * nth) {
+        uint32_t w[4][W];
+#pragma unroll
+        for (int q = 0; q < 4; q++) lds_load<W>(lds, s0 + q * nth, w[q]);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          twist_row<ST, W, LAZY>(op, w[q]);
+          lds_store<W>(lds, s0 + q * nth, w[q]);
+        }
+      }
+      if (s0 < a.n_rows) {
         uint32_t w[4][W];
 #pragma unroll
         for (int q = 0; q < 4; q++)

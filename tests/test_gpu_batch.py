@@ -52,11 +52,17 @@ def single(inst, c, C, p, seed, R, rid0=0):
 def test_batch_equals_single_states(storage):
     gs = graphs()
     with cosm.Batch(storage=storage, max_graphs=16, max_n=20000) as b:
-        ids = []
+        ids, lazy = [], []
         for inst, c, C, p, seed, R in gs:
             p.storage = storage
             ids.append(b.add(inst.n, inst.eu, inst.ev, inst.J, c, C, p, seed=seed, replicas=R))
-        say(f"[gpu] batch run of {len(ids)} graphs, storage {storage}")
+            lazy.append(b.shape(ids[-1])["lazy_wrap"])
+        say(f"[gpu] batch run of {len(ids)} graphs, storage {storage}, wrapped at the twists only: "
+            f"{lazy}")
+        # 16-bit phases: the tori stay within the drift bound (T = 3, twist 7 deg,
+        # degree 4: 175 deg between wraps), the 3- and 5-regular graphs and the
+        # +-2 graph do not; FP32 phases are wrapped after every update here
+        assert lazy == ([1, 0, 0, 0, 1] if storage == cosm.STORE_BF16 else [0] * 5)
         b.run(ids)
         ms = b.wait()
         say(f"[gpu] batch took {ms:.2f} ms")
