@@ -601,8 +601,9 @@ def lds_bytes(info, inst, R, S, period, storage_bytes):
 
 def large_bench(cases_wanted=None, S=None, reps=None):
     """The large-graph configurations: the 100x100 and 141x141 +-1 tori at 4096
-    replicas (FP32, FIX32, FP16, BF16 and FIX16 storage) and the 5-regular N = 20000 and
-    capped Erdos-Renyi N = 10000 graphs at 2048 replicas (FP32, FIX32): edge-updates/s
+    replicas (FP32, FIX32, FP16, FP16 with FP16 arithmetic, BF16 and FIX16 storage) and
+    the 5-regular N = 20000 and capped Erdos-Renyi N = 10000 graphs at 2048 replicas
+    (FP32, FIX32): edge-updates/s
     of the sweep kernel (HIP events around whole sweep calls after a warm-up),
     the shape and layout the autotuner kept, and the LDS roofline fraction of the
     algorithmic bytes (16 B, or 8 B for 16-bit storage, per edge update plus a
@@ -614,16 +615,16 @@ def large_bench(cases_wanted=None, S=None, reps=None):
 
     torch.cuda.set_device(0)
     cases = [("torus-100x100", lambda: ci.torus(100, seed=3), cosm.COLOR_TORUS, [100, 100], 4096,
-              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "fp16", "bf16", "fix16")),
+              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "fp16", "fp16pk", "bf16", "fix16")),
              ("torus-141x141", lambda: ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141], 4096,
-              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "fp16", "bf16", "fix16")),
+              dict(dwt_ratio=0.5, dwt_period=3), ("fp32", "fix32", "fp16", "fp16pk", "bf16", "fix16")),
              ("rr5-n20000", lambda: ci.random_regular(20000, 5, seed=1000, weights="pm1"),
               cosm.COLOR_BALANCED, None, 2048, dict(dwt_ratio=1.5, dwt_period=3), ("fp32", "fix32")),
              ("er-n10000", lambda: ci.erdos_renyi_capped(10000, 4, 8, seed=3),
               cosm.COLOR_MISRA_GRIES, None, 2048, dict(dwt_ratio=1.5, dwt_period=3),
               ("fp32", "fix32"))]
     storages = {"fp32": cosm.STORE_FP32, "fix32": cosm.STORE_FIX32, "fp16": cosm.STORE_FP16,
-                "bf16": cosm.STORE_BF16, "fix16": cosm.STORE_FIX16}
+                "bf16": cosm.STORE_BF16, "fix16": cosm.STORE_FIX16, "fp16pk": cosm.STORE_FP16_PK}
     S = S or LARGE["sweeps"]
     reps = reps or LARGE["reps"]
     stream = torch.cuda.current_stream()
@@ -652,7 +653,7 @@ def large_bench(cases_wanted=None, S=None, reps=None):
             info = st.info()
             st.close()
             rate = inst.m * S * R / sec
-            b = 2 if st_name in ("fp16", "bf16", "fix16") else 4
+            b = 2 if st_name in ("fp16", "fp16pk", "bf16", "fix16") else 4
             algo, moved = lds_bytes(info, inst, R, S, kw["dwt_period"], b)
             form = {cosm.RES_LDS: "lds", cosm.RES_HBM: "hbm"}.get(info["residency"], "plain")
             rec = {"workload": name, "n": inst.n, "m": inst.m, "classes": C, "replicas": R,
@@ -730,6 +731,7 @@ def maxcut_legs(args):
         return out
     ttt = {"target_H": target, "target_cut": (int(-inst.J.sum()) - target) // 2}
     for name, over in (("batched_fp32", {}), ("batched_fp16", {"storage": cosm.STORE_FP16}),
+                       ("batched_fp16_pk", {"storage": cosm.STORE_FP16_PK}),
                        ("batched_bf16", {"storage": cosm.STORE_BF16}),
                        ("batched_fix16", {"storage": cosm.STORE_FIX16}),
                        ("batched_fix32", {"storage": cosm.STORE_FIX32}),
@@ -947,8 +949,8 @@ def main():
     }
     if not args.no_extra:
         out["maxcut"] = maxcut_legs(args)
-        out["large"] = large_bench({"torus-100x100": ("fp32", "fp16", "bf16", "fix16"),
-                                    "torus-141x141": ("fp16", "bf16", "fix16"),
+        out["large"] = large_bench({"torus-100x100": ("fp32", "fp16", "fp16pk", "bf16", "fix16"),
+                                    "torus-141x141": ("fp16", "fp16pk", "bf16", "fix16"),
                                     "rr5-n20000": ("fp32",), "er-n10000": ("fp32",)})["cases"]
         if "maxcut" in out:
             mc = out["maxcut"]

@@ -63,11 +63,11 @@ enum { COSM_COLOR_GREEDY = 0, COSM_COLOR_MISRA_GRIES = 1, COSM_COLOR_TORUS = 2,
  * deterministic and the returned colouring records it. */
 enum { COSM_ORDER_LARGEST_LAST = 0x100 };
 /* Phase storage.  FP32: x in [0, 1) turn.  FP16 / BF16: the centred value
- * y = x - 1/2.  FP16 computes Eq. (6) in FP16 arithmetic (packed, two replicas
- * per instruction): y_u - y_v, the sign of the coupling from round(2e - 1/2)
- * being even (an exact half-turn difference counts as positive), the step
- * alpha J and both updates each rounded to FP16.  BF16 computes in FP32 and
- * rounds on every store.  The twist computes in FP32.  FIX16: x in 16-bit fixed
+ * y = x - 1/2, FP32 arithmetic, rounded on every store.  FP16_PK: FP16 storage
+ * as FP16, Eq. (6) in FP16 arithmetic (packed, two replicas per instruction):
+ * e = y_u - y_v, the sign of the coupling from round(2e - 1/2) being even (an
+ * exact half-turn difference counts as positive), the step alpha J and both
+ * updates each rounded to FP16; its twist computes in FP32.  FIX16: x in 16-bit fixed
  * point (units of 2^-16 turn), wrapping by integer overflow; needs the GRID
  * schedule, which it runs on the 2^-16 turn grid (steps on 2^-15, initial
  * phases and twist angles the top 16 bits of the same draws), so trajectories
@@ -77,7 +77,7 @@ enum { COSM_ORDER_LARGEST_LAST = 0x100 };
  * trajectory bit for bit with integer instead of floating-point arithmetic
  * (phases set from outside are rounded to 2^-32 turn). */
 enum { COSM_STORE_FP32 = 0, COSM_STORE_FP16 = 1, COSM_STORE_BF16 = 2, COSM_STORE_FIX16 = 3,
-       COSM_STORE_FIX32 = 4 };
+       COSM_STORE_FIX32 = 4, COSM_STORE_FP16_PK = 5 };
 /* Where a replica's phases live during a sweep.  LDS: a workgroup holds whole
  * replicas in LDS for all sweeps of a call.  HBM: phases stay in device memory,
  * one launch per colour class.  PLAIN: one replica per launch, one launch per

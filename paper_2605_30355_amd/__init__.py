@@ -13,7 +13,7 @@ from .cosm import (  # noqa: F401
     RES_AUTO, RES_HBM, RES_LDS, RES_PLAIN,
     READOUT_BISECTORS, READOUT_OPTIMAL,
     SCHED_CONTINUOUS, SCHED_GRID,
-    STORE_BF16, STORE_FIX16, STORE_FIX32, STORE_FP16, STORE_FP32,
+    STORE_BF16, STORE_FIX16, STORE_FIX32, STORE_FP16, STORE_FP16_PK, STORE_FP32,
     UNIT_DEGREES, UNIT_RADIANS, UNIT_TURNS,
     UPDATE_FULL_GRADIENT, UPDATE_SCS,
     Batch, CosmError, Params, State, TTSResult,

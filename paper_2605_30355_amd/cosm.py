@@ -14,7 +14,7 @@ COSM_OK = 0
 STATUS_NAMES = {0: "COSM_OK", -1: "COSM_EINVAL", -2: "COSM_EDUP", -3: "COSM_ECOLOR",
                 -4: "COSM_ERANGE", -5: "COSM_ENOMEM", -6: "COSM_EDEVICE", -7: "COSM_ESTATE"}
 COLOR_GREEDY, COLOR_MISRA_GRIES, COLOR_TORUS, COLOR_BALANCED, COLOR_MINIMUM = 0, 1, 2, 3, 4
-STORE_FP32, STORE_FP16, STORE_BF16, STORE_FIX16, STORE_FIX32 = 0, 1, 2, 3, 4
+STORE_FP32, STORE_FP16, STORE_BF16, STORE_FIX16, STORE_FIX32, STORE_FP16_PK = 0, 1, 2, 3, 4, 5
 ORDER_LARGEST_LAST = 0x100  # OR into a colouring method: the largest class goes last
 RES_AUTO, RES_LDS, RES_HBM, RES_PLAIN = 0, 1, 2, 3
 SCHED_GRID, SCHED_CONTINUOUS = 0, 1

@@ -113,7 +113,7 @@ int check_params(const cosm_params *p) {
   if (p->sweeps_per_trial < 1 || p->sweeps_per_trial > ((int64_t)1 << 31))
     return bad("sweeps_per_trial must be in [1, 2^31]");
   if (p->schedule != COSM_SCHED_GRID && p->schedule != COSM_SCHED_CONTINUOUS) return bad("bad schedule");
-  if (p->storage < COSM_STORE_FP32 || p->storage > COSM_STORE_FIX32) return bad("bad storage");
+  if (p->storage < COSM_STORE_FP32 || p->storage > COSM_STORE_FP16_PK) return bad("bad storage");
   if (p->storage == COSM_STORE_FIX16 && p->schedule != COSM_SCHED_GRID)
     return bad("FIX16 storage needs the GRID schedule");
   if (p->storage == COSM_STORE_FIX32 && p->schedule != COSM_SCHED_GRID)

@@ -99,7 +99,8 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
   // FP16 / BF16: wrapped at the twists only when the graph's drift bound holds
   // (g.lazy, set by the host).  (FP32 on the grid could be too, exactly, but a
   // second FP32 sweep path in this kernel made the mixed stream 5 % slower.)
-  constexpr bool kLazyOk = ST == COSM_STORE_FP16 || ST == COSM_STORE_BF16;
+  constexpr bool kLazyOk =
+      ST == COSM_STORE_FP16 || ST == COSM_STORE_BF16 || ST == COSM_STORE_FP16_PK;
   constexpr int RW = W * F::kPerWord;
   constexpr uint32_t ROWB = 4 * W;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -410,6 +411,7 @@ int launch_run(cosm_batch *b) {
   switch (b->storage) {
     case COSM_STORE_FP32: enqueue_run<COSM_STORE_FP32>(b); break;
     case COSM_STORE_FP16: enqueue_run<COSM_STORE_FP16>(b); break;
+    case COSM_STORE_FP16_PK: enqueue_run<COSM_STORE_FP16_PK>(b); break;
     case COSM_STORE_BF16: enqueue_run<COSM_STORE_BF16>(b); break;
     case COSM_STORE_FIX16: enqueue_run<COSM_STORE_FIX16>(b); break;
     default: enqueue_run<COSM_STORE_FIX32>(b); break;
@@ -515,7 +517,7 @@ int cosm_batch_create(cosm_batch **out, int32_t storage, int32_t max_graphs, int
   clear_error();
   if (out == nullptr) return set_error(COSM_EINVAL, "out must not be NULL");
   *out = nullptr;
-  if (storage < COSM_STORE_FP32 || storage > COSM_STORE_FIX32) return set_error(COSM_EINVAL, "bad storage");
+  if (storage < COSM_STORE_FP32 || storage > COSM_STORE_FP16_PK) return set_error(COSM_EINVAL, "bad storage");
   if (max_graphs < 1 || max_n < 1 || max_n > 65536 || max_bisectors < 1 || max_bisectors > 32767)
     return set_error(COSM_EINVAL, "bad batch limits");
   cosm_batch *b = new cosm_batch();
@@ -568,6 +570,7 @@ int cosm_batch_create(cosm_batch **out, int32_t storage, int32_t max_graphs, int
   switch (storage) {
     case COSM_STORE_FP32: set_attrs<COSM_STORE_FP32>(b); break;
     case COSM_STORE_FP16: set_attrs<COSM_STORE_FP16>(b); break;
+    case COSM_STORE_FP16_PK: set_attrs<COSM_STORE_FP16_PK>(b); break;
     case COSM_STORE_BF16: set_attrs<COSM_STORE_BF16>(b); break;
     case COSM_STORE_FIX16: set_attrs<COSM_STORE_FIX16>(b); break;
     default: set_attrs<COSM_STORE_FIX32>(b); break;
@@ -805,6 +808,7 @@ int cosm_batch_run(cosm_batch *b, const int32_t *graph_ids, int32_t count) {
     switch (b->storage) {
       case COSM_STORE_FP32: enqueue_run<COSM_STORE_FP32>(b); break;
       case COSM_STORE_FP16: enqueue_run<COSM_STORE_FP16>(b); break;
+      case COSM_STORE_FP16_PK: enqueue_run<COSM_STORE_FP16_PK>(b); break;
       case COSM_STORE_BF16: enqueue_run<COSM_STORE_BF16>(b); break;
       case COSM_STORE_FIX16: enqueue_run<COSM_STORE_FIX16>(b); break;
       default: enqueue_run<COSM_STORE_FIX32>(b); break;

@@ -169,6 +169,9 @@ struct Fmt16 {
 };
 template <>
 struct Fmt<COSM_STORE_FP16> : Fmt16<COSM_STORE_FP16> {};
+// FP16 storage with FP16 arithmetic: the FP16 encoding, its own update paths
+template <>
+struct Fmt<COSM_STORE_FP16_PK> : Fmt16<COSM_STORE_FP16> {};
 template <>
 struct Fmt<COSM_STORE_BF16> : Fmt16<COSM_STORE_BF16> {};
 
@@ -285,7 +288,7 @@ __device__ __forceinline__ float round_h(float v) { return (float)(_Float16)v; }
 // Eq. (6) for one (edge, replica): values in the storage's convention.
 // LAZY: no wrap (phases wrapped at the twists only; fract(x_u - x_v) does not
 // need wrapped operands).
-// FP16 storage computes in FP16 arithmetic, each step rounded to FP16 as the
+// FP16_PK storage computes in FP16 arithmetic, each step rounded to FP16 as the
 // packed form in update_words does it: e = y_u - y_v; the coupling is positive
 // (fract(e) < 1/2) when round(2e - 1/2) is even, round to nearest even (an
 // exact half-turn difference counts as positive); step +-alpha J rounded to
@@ -295,7 +298,7 @@ __device__ __forceinline__ float round_h(float v) { return (float)(_Float16)v; }
 // (24 >= 2 x 11 + 2 bits).
 template <int ST, bool LAZY = false>
 __device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ) {
-  if constexpr (ST == COSM_STORE_FP16) {
+  if constexpr (ST == COSM_STORE_FP16_PK) {
     const float e = round_h(xu - xv);
     const float t = round_h(__builtin_fmaf(2.0f, e, -0.5f));
     const float st = round_h(aJ);
@@ -490,14 +493,14 @@ __device__ __forceinline__ void row_store(uint32_t addr, const uint32_t (&w)[W])
 // lane difference u - v wraps to the signed difference in [-1/2, 1/2) turn,
 // whose sign bit selects -step or +step, and the updates wrap by overflow.
 // FIX32: the same on one 32-bit integer per replica.
-// FP16: two replicas per word in packed FP16 arithmetic (pair_update's steps):
+// FP16_PK: two replicas per word in packed FP16 arithmetic (pair_update's steps):
 // r = (2e - 1/2) + 1536 lies in [1024, 2048), where FP16 has unit spacing, so
 // its lowest bit is the parity of round(2e - 1/2); shifted to the sign bit it
 // flips the step's sign.  The wrap subtracts (y + 1536) - 1536 = rint(y).
 // Other formats: unpack, the FP32 update, pack.
 template <int ST, int W, bool LAZY = false>
 __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
-  if constexpr (ST == COSM_STORE_FP16) {
+  if constexpr (ST == COSM_STORE_FP16_PK) {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     const uint32_t sb = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)aJ);
     const uint32_t step = sb | (sb << 16);
@@ -710,7 +713,8 @@ struct TwistOps<COSM_STORE_FIX16, W> {
 
 // Storage formats with a lazy wrap (phases wrapped only at the twists).
 constexpr bool lazy_storage(int st) {
-  return st == COSM_STORE_FP32 || st == COSM_STORE_FP16 || st == COSM_STORE_BF16;
+  return st == COSM_STORE_FP32 || st == COSM_STORE_FP16 || st == COSM_STORE_BF16 ||
+         st == COSM_STORE_FP16_PK;
 }
 
 // The twist on one row.  LAZY (phases wrapped only at the twists): the row is

@@ -837,7 +837,7 @@ int launch_lds_k(cosm_state *s, const LdsArgs &a) {
 // holds (lazy16); the other formats here wrap at every update.
 template <int ST, int W, int EMAX, bool EXACT, bool FUSE = false>
 int launch_lds(cosm_state *s, const LdsArgs &a) {
-  if constexpr (ST == COSM_STORE_FP16 || ST == COSM_STORE_BF16) {
+  if constexpr (ST == COSM_STORE_FP16 || ST == COSM_STORE_BF16 || ST == COSM_STORE_FP16_PK) {
     if (lazy16(*s)) return launch_lds_k<ST, W, EMAX, EXACT, FUSE, true>(s, a);
   }
   return launch_lds_k<ST, W, EMAX, EXACT, FUSE, false>(s, a);
@@ -1085,6 +1085,7 @@ int dispatch_storage(int storage, A &&...args) {
   switch (storage) {
     case COSM_STORE_FP32: return Fn<COSM_STORE_FP32>::run(args...);
     case COSM_STORE_FP16: return Fn<COSM_STORE_FP16>::run(args...);
+    case COSM_STORE_FP16_PK: return Fn<COSM_STORE_FP16_PK>::run(args...);
     case COSM_STORE_BF16: return Fn<COSM_STORE_BF16>::run(args...);
     case COSM_STORE_FIX16: return Fn<COSM_STORE_FIX16>::run(args...);
     case COSM_STORE_FIX32: return Fn<COSM_STORE_FIX32>::run(args...);
@@ -1158,7 +1159,8 @@ double wrap_drift_turns(const cosm_state &s) {
 
 bool lazy16(const cosm_state &s) {
   const int32_t st = s.p.storage;
-  return (st == COSM_STORE_FP16 || st == COSM_STORE_BF16) && s.p.update == COSM_UPDATE_SCS &&
+  return (st == COSM_STORE_FP16 || st == COSM_STORE_BF16 || st == COSM_STORE_FP16_PK) &&
+         s.p.update == COSM_UPDATE_SCS &&
          s.sched.dwt_period > 0 && wrap_drift_turns(s) < 0.5;
 }
 

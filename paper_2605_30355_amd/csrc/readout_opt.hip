@@ -203,6 +203,10 @@ int launch_readout_optimal(cosm_state *s) {
       hipLaunchKernelGGL((k_opt_keys<COSM_STORE_FP16>), dim3((unsigned)((nr + 255) / 256)), blk, 0,
                          s->stream, d.phases, n, R, d.opt_keys, d.opt_vals);
       break;
+    case COSM_STORE_FP16_PK:
+      hipLaunchKernelGGL((k_opt_keys<COSM_STORE_FP16_PK>), dim3((unsigned)((nr + 255) / 256)), blk, 0,
+                         s->stream, d.phases, n, R, d.opt_keys, d.opt_vals);
+      break;
     case COSM_STORE_BF16:
       hipLaunchKernelGGL((k_opt_keys<COSM_STORE_BF16>), dim3((unsigned)((nr + 255) / 256)), blk, 0,
                          s->stream, d.phases, n, R, d.opt_keys, d.opt_vals);

@@ -68,7 +68,7 @@ struct StreamArgs {
 // fraction (2^-11 turn for FP16, 2^-8 for BF16) until the next twist wraps it.
 template <int ST, int W>
 __device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
-  if constexpr (ST == COSM_STORE_FP16) {  // packed FP16 arithmetic
+  if constexpr (ST == COSM_STORE_FP16_PK) {  // packed FP16 arithmetic
     update_words<ST, W, true>(wu, wv, aJ);
     return;
   }
@@ -383,7 +383,7 @@ int launch_stream_st(cosm_state *s, int64_t n_sweeps) {
 
 bool lds_lazy_wrap(const cosm_state &s) {
   const int32_t st = s.p.storage;
-  if (st == COSM_STORE_FP16 || st == COSM_STORE_BF16) return lazy16(s);
+  if (st == COSM_STORE_FP16 || st == COSM_STORE_BF16 || st == COSM_STORE_FP16_PK) return lazy16(s);
   // FP32: exact on the grid schedule, in the streamed forms
   return st == COSM_STORE_FP32 && s.sched.grid && s.shape.residency == COSM_RES_LDS &&
          (s.lds.stream || s.lds.rstream) && s.sched.dwt_period > 0 && wrap_drift_turns(s) < 0.5;
@@ -393,6 +393,7 @@ int launch_sweeps_stream(cosm_state *s, int64_t n_sweeps) {
   switch (s->p.storage) {
     case COSM_STORE_FP32: return launch_stream_st<COSM_STORE_FP32>(s, n_sweeps);
     case COSM_STORE_FP16: return launch_stream_st<COSM_STORE_FP16>(s, n_sweeps);
+    case COSM_STORE_FP16_PK: return launch_stream_st<COSM_STORE_FP16_PK>(s, n_sweeps);
     case COSM_STORE_BF16: return launch_stream_st<COSM_STORE_BF16>(s, n_sweeps);
     case COSM_STORE_FIX16: return launch_stream_st<COSM_STORE_FIX16>(s, n_sweeps);
     case COSM_STORE_FIX32: return launch_stream_st<COSM_STORE_FIX32>(s, n_sweeps);

@@ -170,7 +170,10 @@ def test_params_validation_on_host():
     assert status()[0] == 0 and status()[1] > 0
     assert status(storage=cosm.STORE_FIX32)[0] == 0
     assert status(storage=cosm.STORE_FIX32, schedule=cosm.SCHED_CONTINUOUS)[0] == -1
-    assert status(storage=5)[0] == -1
+    assert status(storage=cosm.STORE_FP16_PK)[0] == 0
+    assert status(storage=6)[0] == -1
+    # FP16 with FP16 arithmetic stores 2 bytes per replica-vertex, as FP16
+    assert status(storage=cosm.STORE_FP16_PK)[1] == status(storage=cosm.STORE_FP16)[1]
     for form in (cosm.LDS_FORM_AUTO, cosm.LDS_FORM_PAIR, cosm.LDS_FORM_REGISTER,
                  cosm.LDS_FORM_REGISTER_STREAM):
         assert status(lds_form=form)[0] == 0

@@ -48,7 +48,7 @@ def single(inst, c, C, p, seed, R, rid0=0):
         return st.energy()
 
 
-@pytest.mark.parametrize("storage", [cosm.STORE_FP32, cosm.STORE_BF16])
+@pytest.mark.parametrize("storage", [cosm.STORE_FP32, cosm.STORE_BF16, cosm.STORE_FP16_PK])
 def test_batch_equals_single_states(storage):
     gs = graphs()
     with cosm.Batch(storage=storage, max_graphs=16, max_n=20000) as b:
@@ -62,7 +62,7 @@ def test_batch_equals_single_states(storage):
         # 16-bit phases: the tori stay within the drift bound (T = 3, twist 7 deg,
         # degree 4: 175 deg between wraps), the 3- and 5-regular graphs and the
         # +-2 graph do not; FP32 phases are wrapped after every update here
-        assert lazy == ([1, 0, 0, 0, 1] if storage == cosm.STORE_BF16 else [0] * 5)
+        assert lazy == ([0] * 5 if storage == cosm.STORE_FP32 else [1, 0, 0, 0, 1])
         b.run(ids)
         ms = b.wait()
         say(f"[gpu] batch took {ms:.2f} ms")

@@ -66,6 +66,7 @@ CASES = [
     ("torus20-pm1", cosm.SCHED_CONTINUOUS, cosm.STORE_FP32),
     ("torus20-pm1", cosm.SCHED_GRID, cosm.STORE_FP16),
     ("torus20-pm1", cosm.SCHED_GRID, cosm.STORE_BF16),
+    ("torus20-pm1", cosm.SCHED_GRID, cosm.STORE_FP16_PK),
     ("torus20-pm1", cosm.SCHED_GRID, cosm.STORE_FIX16),  # 16-bit grid against the 23-bit one
 ]
 
@@ -91,7 +92,8 @@ def test_final_energy_distribution(case):
     assert ks.pvalue > 0.01
 
 
-@pytest.mark.parametrize("store", [cosm.STORE_FP16, cosm.STORE_BF16, cosm.STORE_FIX16])
+@pytest.mark.parametrize("store", [cosm.STORE_FP16, cosm.STORE_BF16, cosm.STORE_FIX16,
+                                   cosm.STORE_FP16_PK])
 def test_sixteen_bit_phase_error_first_sweeps(store):
     """16-bit storage: circular phase error against the FP64 oracle (2^-23
     grid) after 1-8 sweeps stays within a few storage quanta per sweep
@@ -104,8 +106,8 @@ def test_sixteen_bit_phase_error_first_sweeps(store):
     R, seed = 64, 5
     p = cosm.Params(sweeps_per_trial=10000, dwt_ratio=1.0, dwt_period=6, storage=store)
     op = oracle.Params(sweeps=10000, dwt_ratio=1.0, dwt_period=6)
-    quantum = {cosm.STORE_FP16: 2.0 ** -12, cosm.STORE_BF16: 2.0 ** -9,
-               cosm.STORE_FIX16: 2.0 ** -16}[store]  # turns, worst case
+    quantum = {cosm.STORE_FP16: 2.0 ** -12, cosm.STORE_FP16_PK: 2.0 ** -12,
+               cosm.STORE_BF16: 2.0 ** -9, cosm.STORE_FIX16: 2.0 ** -16}[store]  # turns, worst case
     x = oracle.init_phases(inst.n, seed, 0, R)
     with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=seed, replicas=R) as st:
         for k in range(1, 9):
@@ -122,8 +124,8 @@ def test_sixteen_bit_phase_error_first_sweeps(store):
 # ---------------------------------------------------------------------------
 # The large torus (the 100 x 100 +-1 torus, the shape of the G72-like
 # configuration), 1024 replicas a side, 1000 sweeps: FP16 and BF16 storage
-# (FP16 and FP32 arithmetic respectively, the streamed LDS form at 4 or 8
-# replicas per workgroup)
+# (FP32 arithmetic) and FP16 with packed FP16 arithmetic, the streamed LDS form
+# at 4 or 8 replicas per workgroup
 # against the oracle's grid schedule, and FP32 with the continuous schedule
 # against the oracle's continuous schedule.
 # ---------------------------------------------------------------------------
@@ -150,8 +152,10 @@ def _large_oracle_energies(sched):
                                   (cosm.SCHED_GRID, cosm.STORE_FP16, 8),
                                   (cosm.SCHED_GRID, cosm.STORE_BF16, 4),
                                   (cosm.SCHED_GRID, cosm.STORE_BF16, 8),
+                                  (cosm.SCHED_GRID, cosm.STORE_FP16_PK, 4),
                                   (cosm.SCHED_CONTINUOUS, cosm.STORE_FP32, 2)],
-                         ids=["fp16-rw4", "fp16-rw8", "bf16-rw4", "bf16-rw8", "fp32-continuous"])
+                         ids=["fp16-rw4", "fp16-rw8", "bf16-rw4", "bf16-rw8", "fp16pk-rw4",
+                              "fp32-continuous"])
 def test_large_torus_energy_distribution(case):
     """Each case runs the streamed pair form (20 slots per thread at 1024
     threads) at the given replicas per workgroup."""

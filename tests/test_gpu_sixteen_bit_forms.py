@@ -3,7 +3,9 @@ register-resident and streamed LDS forms, the device-memory (HBM) form and the
 plain one-replica form all wrap the centred 16-bit values at the twists only
 (while no phase can drift by 1/2 turn between two twists), or all at every
 update (outside that bound), and round the same FP32 results to 16 bits, so
-their phases, energies and spins agree bit for bit.  (Parity with the FP64
+their phases, energies and spins agree bit for bit.  FP16_PK (FP16 arithmetic)
+computes packed on the LDS words and step by step in FP32 with a rounding to
+FP16 after each step in the element-wise forms; those agree bit for bit too.  (Parity with the FP64
 oracle for these formats is distributional: test_gpu_distribution.py.)"""
 import numpy as np
 import pytest
@@ -23,7 +25,7 @@ def run(inst, colour, C, p, seed, R):
         return x, H, spins, st.info()
 
 
-@pytest.mark.parametrize("storage", [cosm.STORE_FP16, cosm.STORE_BF16])
+@pytest.mark.parametrize("storage", [cosm.STORE_FP16, cosm.STORE_BF16, cosm.STORE_FP16_PK])
 @pytest.mark.parametrize("period,lazy", [(3, 1), (6, 0)], ids=["wrap-at-twists", "wrap-each-update"])
 def test_forms_agree(storage, period, lazy):
     inst = ci.torus(20, seed=1)
@@ -42,7 +44,7 @@ def test_forms_agree(storage, period, lazy):
         assert np.array_equal(out[res][2], out[cosm.RES_LDS][2]), res
 
 
-@pytest.mark.parametrize("storage", [cosm.STORE_FP16, cosm.STORE_BF16])
+@pytest.mark.parametrize("storage", [cosm.STORE_FP16, cosm.STORE_BF16, cosm.STORE_FP16_PK])
 def test_streamed_form_agrees_with_device_memory_form(storage):
     """The 141 x 141 torus: the streamed LDS form against the HBM form."""
     inst = ci.torus(141, seed=4)
