@@ -121,15 +121,23 @@ def load_target():
 
 
 def cpu_model():
-    """The host CPU's model name (as lscpu prints it), from /proc/cpuinfo."""
+    """The host CPU's model name (as lscpu prints it) with its family and model
+    numbers, from /proc/cpuinfo (a virtual machine may report a generic name)."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                key = line.split(":", 1)[0].strip()
+                if key in ("model name", "cpu family", "model") and key not in fields:
+                    fields[key] = line.split(":", 1)[1].strip()
+                if not line.strip() and fields:
+                    break
     except OSError:
-        pass
-    return None
+        return None
+    if "model name" not in fields:
+        return None
+    extra = ", ".join(f"{k} {fields[k]}" for k in ("cpu family", "model") if k in fields)
+    return fields["model name"] + (f" ({extra})" if extra else "")
 
 
 def cpu_baseline(inst, colour, C, work, seconds_goal=12.0):
