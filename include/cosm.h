@@ -305,7 +305,7 @@ int cosm_batch_add_graph(cosm_batch *b, int32_t n, int64_t m, const int32_t *eu,
  * how it was chosen (tuned: 0 one width fits or was requested, 1 timed probes,
  * 2 the probe cache) with the chosen width's probe time (ms, one work item;
  * 0 when not probed), and lazy_wrap: 1 when its phases are wrapped at the
- * twists only (FP16 / BF16 within the drift bound of cosm_info.lazy_wrap).
+ * twists only (FP16 / BF16 / FP16_PK within the drift bound of cosm_info.lazy_wrap).
  * Any output pointer may be NULL. */
 int cosm_batch_graph_shape(const cosm_batch *b, int32_t graph_id, int32_t *replicas_per_set,
                            int32_t *sets_per_item, int32_t *tuned, double *probe_ms,
@@ -376,7 +376,7 @@ typedef struct {
                               wrapped range between two twists (twist + period x alpha0 x
                               largest sum of |J| and |h| at a vertex < 1/2 turn): FP32 in
                               the streamed LDS forms on the grid schedule (the result is
-                              the same bit for bit), FP16 / BF16 in every form (the
+                              the same bit for bit), FP16 / BF16 / FP16_PK in every form (the
                               centred value y then lies in (-1, 1) between twists) */
 } cosm_info;
 int cosm_get_info(const cosm_state *s, cosm_info *out);

@@ -44,7 +44,7 @@ struct GraphDev {
   uint32_t k0, k1, rid0;
   ReadoutArgs ro;
   int32_t grid;
-  int32_t lazy;               // FP16 / BF16 phases wrapped at the twists only
+  int32_t lazy;               // 16-bit float phases wrapped at the twists only
   uint32_t ishift;            // initial phases: (draw >> ishift) * iscale
   float iscale;
 };
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(256) k_batch_init(const GraphDev *graphs, cons
 template <int ST, int W>
 __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
   using F = Fmt<ST>;
-  // FP16 / BF16: wrapped at the twists only when the graph's drift bound holds
+  // FP16 / BF16 / FP16_PK: wrapped at the twists only when the graph's drift bound holds
   // (g.lazy, set by the host).  (FP32 on the grid could be too, exactly, but a
   // second FP32 sweep path in this kernel made the mixed stream 5 % slower.)
   constexpr bool kLazyOk =

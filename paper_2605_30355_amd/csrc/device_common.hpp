@@ -3,7 +3,7 @@
 // dual-window membership test and the per-sweep schedule.
 //
 // Phases are turns (1 turn = 360 degrees).  FP32 storage keeps x in [0, 1) and
-// wraps with v_fract_f32; FP16 / BF16 storage keeps the centred value
+// wraps with v_fract_f32; FP16 / BF16 / FP16_PK storage keeps the centred value
 // y = x - 1/2 in [-1/2, 1/2] and wraps with y - rint(y); FIX16 keeps x in 16-bit
 // fixed point and wraps by integer overflow (update_words, twist_words).
 #pragma once

@@ -279,7 +279,7 @@ int launch_sweeps(cosm_state *s, int64_t n_sweeps);
 // (the launchers pick the fused kernel forms by this test).
 bool lds_twist_fused(const cosm_state &s);
 // Whether the sweeps of s keep phases unwrapped between twists: FP32 in the
-// streamed LDS forms on the grid schedule (exact), FP16 / BF16 in every form
+// streamed LDS forms on the grid schedule (exact), FP16 / BF16 / FP16_PK in every form
 // (lazy16) -- in both cases only while no phase can drift by 1/2 turn from its
 // wrapped range between two twists (sweep_stream.hip, kernels.hip).
 bool lds_lazy_wrap(const cosm_state &s);

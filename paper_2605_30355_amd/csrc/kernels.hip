@@ -3,8 +3,9 @@
 // Phases are turns (1 turn = 360 degrees).  FP32 storage keeps x in [0, 1) and
 // wraps with v_fract_f32; FP16 / BF16 storage keeps the centred value
 // y = x - 1/2 in [-1/2, 1/2] and wraps with y - rint(y) (one more bit of
-// resolution than storing x); arithmetic is FP32.  When no phase can drift by
-// 1/2 turn between two twists, FP16 / BF16 (every form) and FP32 (the
+// resolution than storing x); arithmetic is FP32 (FP16_PK: FP16, packed).
+// When no phase can drift by 1/2 turn between two twists, the 16-bit float
+// formats (every form) and FP32 (the
 // streamed LDS forms, grid schedule) wrap at the twists only (lazy16,
 // lds_lazy_wrap).  FIX16 storage keeps x as a
 // 16-bit integer k (x = k 2^-16) and the LDS sweep updates it with packed
@@ -627,7 +628,7 @@ __global__ void __launch_bounds__(256) k_class_hbm(void *phases, const int32_t *
   float xu[VEC], xv[VEC];
   load_vec<ST, VEC>(phases, (size_t)u * R + r, xu);
   load_vec<ST, VEC>(phases, (size_t)v * R + r, xv);
-  // (lazy: FP16 / BF16 wrapped at the twists only)
+  // (lazy: 16-bit float phases wrapped at the twists only)
   if (lazy) {
 #pragma unroll
     for (int k = 0; k < VEC; k++) pair_update<ST, true>(xu[k], xv[k], aJ);
@@ -833,7 +834,7 @@ int launch_lds_k(cosm_state *s, const LdsArgs &a) {
   return launch_check("k_sweep_lds");
 }
 
-// FP16 / BF16 phases are wrapped at the twists only when the drift bound
+// 16-bit float phases are wrapped at the twists only when the drift bound
 // holds (lazy16); the other formats here wrap at every update.
 template <int ST, int W, int EMAX, bool EXACT, bool FUSE = false>
 int launch_lds(cosm_state *s, const LdsArgs &a) {

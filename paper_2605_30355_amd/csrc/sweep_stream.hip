@@ -62,7 +62,7 @@ struct StreamArgs {
 // at most twist_max, and until the next one a phase moves by at most
 // period * alpha_max * (largest sum of |J| at one vertex), with the two
 // together below 1/2 turn.
-// FP16 / BF16 (centred values y = x - 1/2) use the same form to save the two
+// FP16 / BF16 / FP16_PK (centred values y = x - 1/2) use the same form to save the two
 // wraps y - rint(y) of every update: no exactness is claimed there, and a
 // value that has drifted to |y| in [1/2, 1) is stored with one bit less of
 // fraction (2^-11 turn for FP16, 2^-8 for BF16) until the next twist wraps it.
