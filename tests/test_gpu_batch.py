@@ -130,3 +130,55 @@ def test_batch_shape_tuned_and_cached():
         for gid in (g0, g1, g2):
             H, cut, sp = b.results(gid, return_spins=True)
             assert np.array_equal(H, Hs) and np.array_equal(cut, cs) and np.array_equal(sp, ss)
+
+
+# The mixed request stream's workload at full size: the largest request of each
+# family (256 replicas x 10^4 sweeps, the families' twist parameters, the
+# colourings the stream uses), run together in one batch launch with their
+# tuned row widths; sampled replicas (the first and the last of each request)
+# against the FP64 oracle.
+STREAM_FAMILY_PARAMS = {"torus": dict(dwt_ratio=0.5, dwt_period=3),
+                        "3-regular": dict(dwt_ratio=1.0, dwt_period=6),
+                        "5-regular": dict(dwt_ratio=1.5, dwt_period=3)}
+
+
+def test_stream_requests_full_size_sampled():
+    from concurrent.futures import ThreadPoolExecutor
+
+    reqs = ci.request_stream(256, 400, 20000, 5)
+    largest = {}
+    for k, (_, inst) in enumerate(reqs):
+        fam = inst.meta["family"]
+        if fam not in largest or inst.n > reqs[largest[fam]][1].n:
+            largest[fam] = k
+    S, R = 10000, 256
+    picked = []
+    with cosm.Batch(max_graphs=4, max_n=20001) as b:
+        for fam, k in sorted(largest.items()):
+            inst = reqs[k][1]
+            if fam == "torus":
+                L = inst.meta["Lx"]
+                c, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_TORUS, [L, L])
+            else:
+                c, C = cosm.build_partitions(inst.n, inst.eu, inst.ev, cosm.COLOR_BALANCED)
+            p = cosm.Params(sweeps_per_trial=S, **STREAM_FAMILY_PARAMS[fam])
+            gid = b.add(inst.n, inst.eu, inst.ev, inst.J, c, C, p, seed=k, replicas=R)
+            say(f"[gpu] request {k} ({fam}, n={inst.n}, m={inst.m}): shape {b.shape(gid)}")
+            picked.append((gid, k, inst, c, C, fam))
+        b.run([g[0] for g in picked])
+        say(f"[gpu] batch of {len(picked)} full-size requests took {b.wait():.0f} ms")
+        res = {gid: b.results(gid, return_spins=True) for gid, *_ in picked}
+
+    def oracle_one(job):
+        gid, k, inst, c, C, fam, r = job
+        prob = oracle.Problem(inst.n, inst.eu, inst.ev, inst.J, colour=c, C=C)
+        op = oracle.Params(sweeps=S, **STREAM_FAMILY_PARAMS[fam])
+        _, so, Ho, co = oracle.solve(prob, op, k, r, 1, n_threads=1)
+        return gid, r, so[0], int(Ho[0]), int(co[0])
+
+    jobs = [g + (r,) for g in picked for r in (0, R - 1)]
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        for gid, r, so, Ho, co in ex.map(oracle_one, jobs):
+            H, cut, sp = res[gid]
+            say(f"[oracle] graph {gid} replica {r}: H {Ho} (gpu {int(H[r])})")
+            assert int(H[r]) == Ho and int(cut[r]) == co and np.array_equal(sp[r], so), (gid, r)
