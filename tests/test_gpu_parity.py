@@ -208,13 +208,14 @@ def test_c2_full_size_bench_shape():
 
 def test_torus141_full_width():
     """The 141 x 141 +-1 torus (N = 19881, 6 classes) at 4096 replicas in the
-    benchmark's shape: energies, cuts and spins of replicas sampled from every
-    XCD block of the workgroup map, and their phases, against the oracle."""
+    benchmark's shape and trial length (10^4 sweeps): energies, cuts and spins
+    of replicas sampled from every XCD block of the workgroup map, and their
+    phases, against the oracle."""
     import bench
     cfg = bench.HEADLINE
     inst = bench.headline_instance()
     colour, C, prob = make(inst, cfg["colouring"], cfg["sides"])
-    S = 600
+    S = cfg["sweeps"]
     p = bench.headline_params(cosm, sweeps_per_trial=S)
     R = cfg["replicas"]
     rows = xcd_sample(R, p.replicas_per_wg or 2)
@@ -227,8 +228,8 @@ def test_torus141_full_width():
 
 @pytest.mark.parametrize("order", [0, cosm.ORDER_LARGEST_LAST])
 def test_large_torus_odd_side_sampled(order):
-    """141x141 torus (N=19881, 6 classes): the largest LDS-resident replica block;
-    with the largest class last the streamed sweep folds the twist into it."""
+    """141x141 torus (N=19881, 6 classes): the largest LDS-resident replica block,
+    in the colour order given and with the largest class last."""
     inst = ci.torus(141, seed=4)
     colour, C, prob = make(inst, cosm.COLOR_TORUS | order, [141, 141])
     p = cosm.Params(sweeps_per_trial=200, dwt_ratio=0.5, dwt_period=3)
@@ -241,6 +242,21 @@ def test_five_regular_20000_sampled():
     colour, C, prob = make(inst, cosm.COLOR_GREEDY)
     p = cosm.Params(sweeps_per_trial=100, dwt_ratio=1.5, dwt_period=3)
     check_trial(inst, colour, C, prob, p, seed=6, R=64, sweeps=100, sample=[0, 33, 63])
+
+
+def test_five_regular_20000_seed_study_shape():
+    """The 5-regular N = 20000 +-1 family of the time-to-target study at full
+    size: 2048 replicas x 10^4 sweeps, equalised colouring, the streamed pair
+    form at 2 replicas and 1024 threads per workgroup; replicas sampled from
+    every XCD block against the oracle."""
+    inst = ci.random_regular(20000, 5, seed=1000, weights="pm1")
+    colour, C, prob = make(inst, cosm.COLOR_BALANCED)
+    p = cosm.Params(sweeps_per_trial=10000, dwt_ratio=1.5, dwt_period=3,
+                    lds_form=cosm.LDS_FORM_PAIR, replicas_per_wg=2, threads_per_wg=1024)
+    info = check_trial(inst, colour, C, prob, p, seed=1, R=2048, sweeps=10000,
+                       sample=xcd_sample(2048, 2, per_block=1))
+    assert info["residency"] == cosm.RES_LDS and info["streamed"] == 1
+    assert info["replicas_per_wg"] == 2 and info["threads_per_wg"] == 1024
 
 
 def test_degenerate_instances():
@@ -341,6 +357,21 @@ def test_erdos_renyi_capped_sampled():
     p = cosm.Params(sweeps_per_trial=120, dwt_ratio=1.5, dwt_period=3)
     info = check_trial(inst, colour, C, prob, p, seed=8, R=2048, sweeps=120, sample=[0, 1023, 2047])
     assert info["residency"] == cosm.RES_LDS
+
+
+def test_erdos_renyi_seed_study_shape():
+    """The capped Erdos-Renyi N = 10000 family of the time-to-target study at
+    full size: 2048 replicas x 10^4 sweeps, Misra-Gries colouring, the pair form
+    at 4 replicas and 1024 threads per workgroup; replicas sampled from every
+    XCD block against the oracle."""
+    inst = ci.erdos_renyi_capped(10000, 4, 8, seed=1000)
+    colour, C, prob = make(inst, cosm.COLOR_MISRA_GRIES)
+    p = cosm.Params(sweeps_per_trial=10000, dwt_ratio=1.5, dwt_period=3,
+                    lds_form=cosm.LDS_FORM_PAIR, replicas_per_wg=4, threads_per_wg=1024)
+    info = check_trial(inst, colour, C, prob, p, seed=1, R=2048, sweeps=10000,
+                       sample=xcd_sample(2048, 4, per_block=1))
+    assert info["residency"] == cosm.RES_LDS
+    assert info["replicas_per_wg"] == 4 and info["threads_per_wg"] == 1024
 
 
 def test_beyond_lds_capacity_uses_hbm_form():
