@@ -412,3 +412,21 @@ def test_library_owned_memory_and_small_workspace():
                      None, col.ctypes.data, C, ctypes.byref(cp), 1, 16, None,
                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(need.value // 2))
     assert rc == -5 and not h.value
+
+
+@pytest.mark.parametrize("form", [cosm.LDS_FORM_REGISTER, cosm.LDS_FORM_PAIR])
+def test_torus100_full_size(form):
+    """The 100 x 100 +-1 torus (N = 10000, 4 classes) at full size: 4096
+    replicas x 10^4 sweeps, 4 replicas and 1024 threads per workgroup, in the
+    register-owner layout the autotuner keeps for FP32 (4 register rows per
+    thread, the twist fused into the last class) and in the pair layout;
+    replicas from every XCD block against the oracle."""
+    inst = ci.torus(100, seed=3)
+    colour, C, prob = make(inst, cosm.COLOR_TORUS, [100, 100])
+    p = cosm.Params(sweeps_per_trial=10000, dwt_ratio=0.5, dwt_period=3, lds_form=form,
+                    replicas_per_wg=4, threads_per_wg=1024, residency=cosm.RES_LDS)
+    info = check_trial(inst, colour, C, prob, p, seed=2, R=4096, sweeps=10000,
+                       sample=xcd_sample(4096, 4, per_block=2))
+    assert info["lds_form"] == form and info["replicas_per_wg"] == 4
+    if form == cosm.LDS_FORM_REGISTER:
+        assert info["register_rows"] == 4 and info["twist_fused"] == 1
