@@ -115,6 +115,116 @@ void greedy_independent(int32_t n, const std::vector<std::vector<Adj>> &adj,
   }
 }
 
+// Enlarges an independent set by 2-improvements (the local search of Andrade,
+// Resende and Werneck, 2012): a set vertex x leaves when two of its
+// neighbours that have x as their only set neighbour, and are not adjacent to
+// each other, can enter instead.  Repeated until no vertex offers such a pair;
+// every step keeps the set independent and grows it by one.
+void improve_independent(int32_t n, const std::vector<std::vector<Adj>> &adj,
+                         std::vector<uint8_t> *in_set) {
+  std::vector<uint8_t> &I = *in_set;
+  std::vector<int32_t> tight((size_t)n, 0);  // set neighbours of a vertex
+  for (int32_t v = 0; v < n; v++)
+    if (I[(size_t)v])
+      for (const Adj &a : adj[(size_t)v]) tight[(size_t)a.other]++;
+  auto adjacent = [&](int32_t a, int32_t b) {
+    for (const Adj &e : adj[(size_t)a])
+      if (e.other == b) return true;
+    return false;
+  };
+  std::vector<int32_t> queue;
+  std::vector<uint8_t> queued((size_t)n, 0);
+  for (int32_t v = 0; v < n; v++)
+    if (I[(size_t)v]) {
+      queue.push_back(v);
+      queued[(size_t)v] = 1;
+    }
+  std::vector<int32_t> one;
+  for (size_t h = 0; h < queue.size(); h++) {
+    const int32_t x = queue[h];
+    queued[(size_t)x] = 0;
+    if (!I[(size_t)x]) continue;
+    one.clear();
+    for (const Adj &a : adj[(size_t)x])
+      if (!I[(size_t)a.other] && tight[(size_t)a.other] == 1) one.push_back(a.other);
+    int32_t w1 = -1, w2 = -1;
+    for (size_t i = 0; i < one.size() && w1 < 0; i++)
+      for (size_t j = i + 1; j < one.size(); j++)
+        if (one[i] != one[j] && !adjacent(one[i], one[j])) {
+          w1 = one[i];
+          w2 = one[j];
+          break;
+        }
+    if (w1 < 0) continue;
+    // x leaves, w1 and w2 enter
+    I[(size_t)x] = 0;
+    for (const Adj &a : adj[(size_t)x]) tight[(size_t)a.other]--;
+    for (int32_t w : {w1, w2}) {
+      I[(size_t)w] = 1;
+      for (const Adj &a : adj[(size_t)w]) tight[(size_t)a.other]++;
+    }
+    // the set vertices near the change may now offer a pair
+    for (int32_t w : {x, w1, w2})
+      for (const Adj &a : adj[(size_t)w])
+        for (const Adj &b : adj[(size_t)a.other])
+          if (I[(size_t)b.other] && !queued[(size_t)b.other]) {
+            queued[(size_t)b.other] = 1;
+            queue.push_back(b.other);
+          }
+    for (int32_t w : {w1, w2})
+      if (!queued[(size_t)w]) {
+        queued[(size_t)w] = 1;
+        queue.push_back(w);
+      }
+  }
+}
+
+// An independent set for a graph that is not bipartite: the larger of (a) the
+// minimum-degree greedy set and (b) a side of the breadth-first parity
+// colouring with the vertices that have a neighbour on their own side dropped
+// (first come, first kept) and the set then made maximal -- nearly half of a
+// graph that is bipartite but for a few odd cycles, as an odd torus is --
+// each enlarged by 2-improvements.
+void large_independent(int32_t n, const std::vector<std::vector<Adj>> &adj,
+                       std::vector<uint8_t> *in_set) {
+  greedy_independent(n, adj, in_set);
+  improve_independent(n, adj, in_set);
+  int64_t best = 0;
+  for (uint8_t b : *in_set) best += b;
+  std::vector<int32_t> depth((size_t)n, -1), queue;
+  for (int32_t s0 = 0; s0 < n; s0++) {
+    if (depth[(size_t)s0] >= 0 || adj[(size_t)s0].empty()) continue;
+    depth[(size_t)s0] = 0;
+    queue.assign(1, s0);
+    for (size_t h = 0; h < queue.size(); h++)
+      for (const Adj &a : adj[(size_t)queue[h]])
+        if (depth[(size_t)a.other] < 0) {
+          depth[(size_t)a.other] = depth[(size_t)queue[h]] + 1;
+          queue.push_back(a.other);
+        }
+  }
+  for (int32_t side : {0, 1}) {
+    std::vector<uint8_t> S((size_t)n, 0);
+    for (int32_t v = 0; v < n; v++) S[(size_t)v] = depth[(size_t)v] >= 0 && depth[(size_t)v] % 2 == side;
+    auto has_set_neighbour = [&](int32_t v) {
+      for (const Adj &a : adj[(size_t)v])
+        if (S[(size_t)a.other]) return true;
+      return false;
+    };
+    for (int32_t v = 0; v < n; v++)
+      if (S[(size_t)v] && has_set_neighbour(v)) S[(size_t)v] = 0;
+    for (int32_t v = 0; v < n; v++)
+      if (!S[(size_t)v] && depth[(size_t)v] >= 0 && !has_set_neighbour(v)) S[(size_t)v] = 1;
+    improve_independent(n, adj, &S);
+    int64_t size = 0;
+    for (uint8_t b : S) size += b;
+    if (size > best) {
+      best = size;
+      *in_set = std::move(S);
+    }
+  }
+}
+
 inline uint64_t bit(int32_t r) { return 1ull << r; }
 
 // Options of one attempt.  pre: every LDS vertex takes residue (its rank among
@@ -162,8 +272,6 @@ int build_reg_impl(const cosm_state &s, const RegOptions &o, LdsSchedule *out) {
     for (int64_t k = 0; k < m; k++)
       if (s.h_J[(size_t)k] >= 8192 || s.h_J[(size_t)k] < -8192)
         return set_error(COSM_ERANGE, "the streamed register form needs |J| < 2^13");
-    if ((size_t)(n + kRegRowsSlack) * 4 * W > ((size_t)1 << 18))
-      return set_error(COSM_ERANGE, "the streamed register form needs rows below 2^18 bytes");
   }
   const int32_t G = W == 1 ? 32 : 64 / W;  // lanes and residues of a read group
   const int32_t H = 32 / W;                // lanes and residues of a write half
@@ -177,7 +285,7 @@ int build_reg_impl(const cosm_state &s, const RegOptions &o, LdsSchedule *out) {
 
   // 1. the register set
   std::vector<uint8_t> inI;
-  if (!bipartite_side(n, adj, &inI)) greedy_independent(n, adj, &inI);
+  if (!bipartite_side(n, adj, &inI)) large_independent(n, adj, &inI);
   std::vector<int32_t> cand;
   for (int32_t v = 0; v < n; v++)
     if (inI[(size_t)v]) cand.push_back(v);
@@ -430,6 +538,9 @@ int build_reg_impl(const cosm_state &s, const RegOptions &o, LdsSchedule *out) {
   const int64_t n_rows = ((int64_t)G * per + 63) / 64 * 64;
   if (n_rows + kDummyRows > 65535 || n_rows > (int64_t)n + kRegRowsSlack - kDummyRows)
     return set_error(COSM_ERANGE, "too many rows for the register form");
+  // the streamed form's pair words hold row offsets in 18 bits
+  if (o.rstream && (size_t)(n_rows + kDummyRows) * 4 * W > ((size_t)1 << 18))
+    return set_error(COSM_ERANGE, "the streamed register form needs rows below 2^18 bytes");
   std::vector<int32_t> row((size_t)n, -1), fill((size_t)G, 0);
   LdsSchedule L;
   L.G = G;
@@ -646,7 +757,7 @@ int build_rstream_schedule(const cosm_state &s, int32_t W, int32_t nth_request,
     adj[(size_t)s.h_ev[(size_t)k]].push_back({s.h_eu[(size_t)k], (int32_t)k, 0});
   }
   std::vector<uint8_t> inI;
-  if (!bipartite_side(s.n, adj, &inI)) greedy_independent(s.n, adj, &inI);
+  if (!bipartite_side(s.n, adj, &inI)) large_independent(s.n, adj, &inI);
   int64_t set = 0;
   for (uint8_t b : inI) set += b;
   int32_t K = kRStreamKMax;
@@ -674,7 +785,10 @@ int build_rstream_schedule(const cosm_state &s, int32_t W, int32_t nth_request,
 }
 
 size_t rstream_lds_bytes(const LdsSchedule &L, int W, int32_t C) {
-  return lds_sweep_bytes(L.n_rows, W, C) + (size_t)C * (L.nth / 64) * 4;
+  // rows and dummy rows, the twist angles of kThetaChunk twists (FP32: W
+  // replicas per row), the slot masks
+  return (size_t)(L.n_rows + kDummyRows) * W * 4 + (size_t)kThetaChunk * W * 4 +
+         (size_t)C * (L.nth / 64) * 4;
 }
 
 }  // namespace cosm

@@ -128,8 +128,10 @@ __global__ void __launch_bounds__(1024) k_sweep_rstream(const RStreamArgs a) {
     F::template pack<W>(x, w);
     lds_store<W>(lds, s, w);
   }
+  // the twist angles of kThetaChunk twists (no bias fields: no direction
+  // table), then the slot masks
   float *theta_buf = reinterpret_cast<float *>(lds + (size_t)(a.n_rows + kDummyRows) * W);
-  uint32_t *act = reinterpret_cast<uint32_t *>(theta_buf + 2 * kThetaFloats);  // [C][nw]
+  uint32_t *act = reinterpret_cast<uint32_t *>(theta_buf + kThetaChunk * RW);  // [C][nw]
   for (int i = tid; i < a.C * nw; i += nth) act[i] = a.act[i];
   // HBM -> register rows
   uint32_t own[K][W];

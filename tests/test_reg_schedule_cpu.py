@@ -132,7 +132,24 @@ def test_rstream_schedule_complete(checker, case):
 
 
 def test_rstream_row_offsets_bounded(checker):
-    """Row offsets must stay below 2^18 bytes: 16-byte rows of a 19881-vertex
-    graph are refused."""
-    r = run(checker, ci.torus(141, seed=4), cosm.COLOR_TORUS, [141, 141], 4, 0)
-    assert r.returncode == 2 and "ERANGE" in r.stdout
+    """Row offsets must stay below 2^18 bytes: 3000 disjoint 6-cliques (18000
+    vertices, 7 classes, at most one register vertex per clique) leave about
+    15000 LDS rows, too many for 16-byte rows and for 8-byte ones."""
+    edges = [(6 * q + a, 6 * q + b) for q in range(3000) for a in range(6) for b in range(a + 1, 6)]
+    colour = {}
+    for q in range(3000):  # greedy edge colouring of each clique
+        used = {}
+        for a in range(6):
+            for b in range(a + 1, 6):
+                c = 0
+                while c in used.get(a, set()) or c in used.get(b, set()):
+                    c += 1
+                used.setdefault(a, set()).add(c)
+                used.setdefault(b, set()).add(c)
+                colour[(6 * q + a, 6 * q + b)] = c
+    C = max(colour.values()) + 1
+    txt = f"18000 {len(edges)} {C}\n" + "\n".join(f"{u} {v} 1 {colour[(u, v)]}" for u, v in edges)
+    for W in (4, 2):
+        r = subprocess.run([checker, str(W), "0"], input=txt, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 2 and "ERANGE" in r.stdout, (W, r.stdout)
