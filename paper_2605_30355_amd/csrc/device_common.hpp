@@ -75,6 +75,26 @@ __device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb) {
 
 __device__ __forceinline__ float fract1(float v) { return __builtin_amdgcn_fractf(v); }
 
+// The FP32 rounding mode of the calling wave (MODE.FP_ROUND bits 1:0; each wave
+// has its own MODE and starts in round-to-nearest-even).  Toward minus
+// infinity, fma(d, 2, 1.5 * 2^23) is 1.5 * 2^23 + floor(2d) exactly for
+// |2d| < 2^22, an integer whose lowest mantissa bit is the parity of floor(2d);
+// exact sums and products do not depend on the mode.
+constexpr int kHwRegModeRoundF32 = (1 << 11) | 1;  // hwreg(HW_REG_MODE, offset 0, size 2)
+__device__ __forceinline__ void f32_round_down() { __builtin_amdgcn_s_setreg(kHwRegModeRoundF32, 2); }
+__device__ __forceinline__ void f32_round_nearest() {
+  __builtin_amdgcn_s_setreg(kHwRegModeRoundF32, 0);
+}
+
+// Eq. (4)-(6)'s step sign on exact grid values, under f32_round_down: fract(d)
+// < 1/2 exactly when floor(2d) is even, so the step is aJ with its sign bit
+// flipped by that parity (one fma and one v_lshl_add instead of fract, compare
+// and select).
+__device__ __forceinline__ float step_by_parity(float d, float aJ) {
+  const float r = __builtin_fmaf(d, 2.0f, 12582912.0f);
+  return __uint_as_float((__float_as_uint(r) << 31) + __float_as_uint(aJ));
+}
+
 // ---------------------------------------------------------------------------
 // Storage formats.  "value" is x in [0,1) for FP32 and y = x - 1/2 otherwise.
 // ---------------------------------------------------------------------------

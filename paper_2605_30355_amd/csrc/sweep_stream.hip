@@ -79,7 +79,9 @@ __device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&
   F::template unpack<W>(wv, xv);
 #pragma unroll
   for (int k = 0; k < RW; k++) {
-    const float dl = (fract1(xu[k] - xv[k]) < 0.5f) ? aJ : -aJ;
+    // FP32: every value exact, the classes run toward minus infinity
+    const float dl = ST == COSM_STORE_FP32 ? step_by_parity(xu[k] - xv[k], aJ)
+                     : (fract1(xu[k] - xv[k]) < 0.5f) ? aJ : -aJ;
     xu[k] -= dl;
     xv[k] += dl;
   }
@@ -263,6 +265,8 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       }
     };
 
+    constexpr bool kRoundDown = LAZY && ST == COSM_STORE_FP32;
+    if constexpr (kRoundDown) f32_round_down();
     for (int c = 0; c < a.C; c++) {
       // this class's slot count and last lanes, read one class ahead
       const int K = __builtin_amdgcn_readfirstlane(k_next);
@@ -275,6 +279,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       run_class(K, act_final);
       __syncthreads();
     }
+    if constexpr (kRoundDown) f32_round_nearest();
     jsw -= (uint32_t)a.total_slots;  // the next sweep's first words are in flight
 
     // Dual window twist every `period` sweeps, after the last class: whole
