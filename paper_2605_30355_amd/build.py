@@ -9,6 +9,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -28,21 +29,34 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
+def _jobs() -> int:
+    try:
+        cap = int(os.environ.get("MAX_JOBS", "0"))
+    except ValueError:
+        cap = 0
+    n = os.cpu_count() or 1
+    return max(1, min(8, n, cap if cap > 0 else n))
+
+
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for name in sorted(os.listdir(CSRC)):
         src = os.path.join(CSRC, name)
         obj = os.path.join(BUILD, name + ".o")
         if name.endswith(".hip"):
-            _run(["hipcc", "-c", *COMMON, *DEVICE, "-x", "hip", src, "-o", obj])
+            cmds.append(["hipcc", "-c", *COMMON, *DEVICE, "-x", "hip", src, "-o", obj])
         elif name.endswith(".cpp"):
             # host-only code: plain g++ against the HIP runtime headers
-            _run(["g++", "-c", *COMMON, "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include",
-                  src, "-o", obj])
+            cmds.append(["g++", "-c", *COMMON, "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include",
+                         src, "-o", obj])
         else:
             continue
         objs.append(obj)
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        for f in [ex.submit(_run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
           "-Wl,-rpath,/opt/rocm/lib"])

@@ -316,8 +316,11 @@ __device__ __forceinline__ float round_h(float v) { return (float)(_Float16)v; }
 // exact.  FP32 steps on FP16 operands give these results: an FP32 result of
 // one operation rounded again to FP16 equals its direct FP16 rounding
 // (24 >= 2 x 11 + 2 bits).
-template <int ST, bool LAZY = false>
+// RD (FP32 on the grid schedule, under f32_round_down): every operand and
+// result is exact, and the step's sign comes from step_by_parity.
+template <int ST, bool LAZY = false, bool RD = false>
 __device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ) {
+  static_assert(!RD || ST == COSM_STORE_FP32, "the parity step is an FP32 grid form");
   if constexpr (ST == COSM_STORE_FP16_PK) {
     const float e = round_h(xu - xv);
     const float t = round_h(__builtin_fmaf(2.0f, e, -0.5f));
@@ -330,8 +333,7 @@ __device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ) {
       xv -= __builtin_rintf(xv);
     }
   } else {
-    const float f = fract1(xu - xv);
-    const float dl = (f < 0.5f) ? aJ : -aJ;
+    const float dl = RD ? step_by_parity(xu - xv, aJ) : (fract1(xu - xv) < 0.5f) ? aJ : -aJ;
     xu = LAZY ? xu - dl : Fmt<ST>::wrap(xu - dl);
     xv = LAZY ? xv + dl : Fmt<ST>::wrap(xv + dl);
   }
@@ -518,7 +520,7 @@ __device__ __forceinline__ void row_store(uint32_t addr, const uint32_t (&w)[W])
 // its lowest bit is the parity of round(2e - 1/2); shifted to the sign bit it
 // flips the step's sign.  The wrap subtracts (y + 1536) - 1536 = rint(y).
 // Other formats: unpack, the FP32 update, pack.
-template <int ST, int W, bool LAZY = false>
+template <int ST, int W, bool LAZY = false, bool RD = false>
 __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
   if constexpr (ST == COSM_STORE_FP16_PK) {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
@@ -572,7 +574,7 @@ __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W
     F::template unpack<W>(wu, xu);
     F::template unpack<W>(wv, xv);
 #pragma unroll
-    for (int k = 0; k < RW; k++) pair_update<ST, LAZY>(xu[k], xv[k], aJ);
+    for (int k = 0; k < RW; k++) pair_update<ST, LAZY, RD>(xu[k], xv[k], aJ);
     F::template pack<W>(xu, wu);
     F::template pack<W>(xv, wv);
   }
@@ -634,12 +636,12 @@ __device__ __forceinline__ void update_reg_words(uint32_t (&r)[W], uint32_t (&w)
 }
 
 // Eq. (6) on every replica of one edge: rows at byte offsets bu, bv.
-template <int ST, int W, bool LAZY = false>
+template <int ST, int W, bool LAZY = false, bool RD = false>
 __device__ __forceinline__ void edge_rows(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ) {
   uint32_t wu[W], wv[W];
   lds_load_at<W>(lds, bu, wu);
   lds_load_at<W>(lds, bv, wv);
-  update_words<ST, W, LAZY>(wu, wv, aJ);
+  update_words<ST, W, LAZY, RD>(wu, wv, aJ);
   lds_store_at<W>(lds, bu, wu);
   lds_store_at<W>(lds, bv, wv);
 }
@@ -780,13 +782,13 @@ __device__ __forceinline__ void twist_words(uint32_t (&w)[W],
 // twist of both endpoints: their phases are final for the sweep once the
 // update is done, so the twist needs no pass of its own for them.  The twist
 // sees the stored (rounded) phases, as a pass of its own would.
-template <int ST, int W, bool LAZY = false>
+template <int ST, int W, bool LAZY = false, bool RD = false>
 __device__ __forceinline__ void edge_rows_twist(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ,
                                                 const TwistOps<ST, W> &op) {
   uint32_t wu[W], wv[W];
   lds_load_at<W>(lds, bu, wu);
   lds_load_at<W>(lds, bv, wv);
-  update_words<ST, W, LAZY>(wu, wv, aJ);
+  update_words<ST, W, LAZY, RD>(wu, wv, aJ);
   twist_row<ST, W, LAZY>(op, wu);
   twist_row<ST, W, LAZY>(op, wv);
   lds_store_at<W>(lds, bu, wu);
@@ -828,7 +830,7 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *scratch /* >= 1
 // The sets are disjoint, so the rows of four sets are read before any is
 // written back, which lets the LDS latency of one set overlap the arithmetic
 // of the others.
-template <int ST, int W, bool LAZY = false>
+template <int ST, int W, bool LAZY = false, bool RD = false>
 __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint32_t bv,
                                                uint32_t set_bytes, int nsets, float aJ) {
   int k = 0;
@@ -840,7 +842,7 @@ __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint3
       lds_load_at<W>(lds, bv + (uint32_t)(k + q) * set_bytes, wv[q]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; q++) update_words<ST, W, LAZY>(wu[q], wv[q], aJ);
+    for (int q = 0; q < 4; q++) update_words<ST, W, LAZY, RD>(wu[q], wv[q], aJ);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       lds_store_at<W>(lds, bu + (uint32_t)(k + q) * set_bytes, wu[q]);
@@ -848,7 +850,8 @@ __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint3
     }
   }
   for (; k < nsets; k++)
-    edge_rows<ST, W, LAZY>(lds, bu + (uint32_t)k * set_bytes, bv + (uint32_t)k * set_bytes, aJ);
+    edge_rows<ST, W, LAZY, RD>(lds, bu + (uint32_t)k * set_bytes, bv + (uint32_t)k * set_bytes,
+                               aJ);
 }
 
 // One workgroup's pass over the classes of one sweep with the lane schedule

@@ -284,6 +284,12 @@ bool lds_twist_fused(const cosm_state &s);
 // wrapped range between two twists (sweep_stream.hip, kernels.hip).
 bool lds_lazy_wrap(const cosm_state &s);
 bool lazy16(const cosm_state &s);
+// Whether every phase operation of the sweeps of s is exact in FP32 (FP32
+// storage on the grid schedule: phases on the 2^-23 turn grid, steps and twists
+// on the 2^-22 grid, |alpha J| below a turn): the LDS kernels then take the
+// step's sign from the parity of floor(2(x_u - x_v)) under round-toward-minus-
+// infinity (step_by_parity, kernels.hip, sweep_stream.hip, batch.hip).
+bool exact_grid_fp32(const cosm_state &s);
 // That drift bound in turns: the largest twist plus period x the largest step
 // x the largest sum of |J| and |h| at one vertex.
 double wrap_drift_turns(const cosm_state &s);

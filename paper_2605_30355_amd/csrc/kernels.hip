@@ -71,9 +71,10 @@ __global__ void __launch_bounds__(256) k_init(void *phases, int32_t n, int32_t R
 // EXACT: one slot per class (EMAX of them), no bounds checks.  FUSE (EXACT or
 // streamed, no bias fields): the twist runs inside the last class's sub-sweep.
 // ---------------------------------------------------------------------------
-template <int ST, int W, int EMAX, bool EXACT, bool FUSE, bool LAZY>
+template <int ST, int W, int EMAX, bool EXACT, bool FUSE, bool LAZY, bool RD>
 __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   static_assert(!LAZY || lazy_storage(ST), "the lazy wrap is a floating-point form");
+  static_assert(!RD || ST == COSM_STORE_FP32, "the parity step is an FP32 grid form");
   static_assert(!FUSE || EXACT || EMAX == 0,
                 "the fused twist runs in the one-slot-per-class and the streamed forms");
   extern __shared__ uint32_t lds[];
@@ -155,6 +156,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   const uint32_t nsw = (uint32_t)a.nsw;
   uint32_t t = (uint32_t)a.t0;
   ScheduleChunk chunk;
+  // RD: the grid schedule, on which every operation of the sweeps is exact
+  // (the ramp, the twist angles and offsets, the updates and wraps), so the
+  // rounding mode matters only to the step's parity fma
+  if constexpr (RD) f32_round_down();
   for (uint32_t it = 0; it < nsw; it++) {
     t++;
     if ((it & 63u) == 0u) chunk.fill(sc, t);
@@ -185,36 +190,36 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       }
 #pragma unroll
       for (int j = 0; j < EMAX - 1; j++) {
-        edge_rows<ST, W, LAZY>(lds, ua[j], va[j], alpha_s * jr[j]);
+        edge_rows<ST, W, LAZY, RD>(lds, ua[j], va[j], alpha_s * jr[j]);
         __syncthreads();
       }
       if (fuse_now) {
-        edge_rows_twist<ST, W, LAZY>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1], op);
+        edge_rows_twist<ST, W, LAZY, RD>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1], op);
 #pragma unroll
         for (int q = 0; q < kFuseRowsMax; q++)
           if (q < a.fuse_k && fr[q] != kEmptySlot) row_twist<ST, W, LAZY>(lds, fr[q], op);
       } else {
-        edge_rows<ST, W, LAZY>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1]);
+        edge_rows<ST, W, LAZY, RD>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1]);
       }
       __syncthreads();
     } else if constexpr (EXACT) {
       // EMAX slots, one class each
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
-        edge_rows<ST, W, LAZY>(lds, ua[j], va[j], alpha_s * jr[j]);
+        edge_rows<ST, W, LAZY, RD>(lds, ua[j], va[j], alpha_s * jr[j]);
         __syncthreads();
       }
     } else if constexpr (EMAX > 0) {
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
         if (j < a.total_slots) {
-          edge_rows<ST, W, LAZY>(lds, ua[j], va[j], alpha_s * jr[j]);
+          edge_rows<ST, W, LAZY, RD>(lds, ua[j], va[j], alpha_s * jr[j]);
           if ((a.bar_mask >> j) & 1u) __syncthreads();
         }
       }
     } else if (a.total_slots > 0) {
       auto edge = [&](const EdgeDesc &d) {
-        edge_rows<ST, W, LAZY>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha_s * d.J);
+        edge_rows<ST, W, LAZY, RD>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha_s * d.J);
       };
       if constexpr (FUSE) {
         // streamed form: on a twist sweep the last class twists the rows it
@@ -242,7 +247,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         stream_classes(
             a.desc, Ks, a.C, a.total_slots, dA, dB, jslot, edge,
             [&](const EdgeDesc &d) {
-              edge_rows_twist<ST, W, LAZY>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
+              edge_rows_twist<ST, W, LAZY, RD>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
                                      alpha_s * d.J, op);
             },
             [&] {
@@ -321,6 +326,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       __syncthreads();
     }
   }
+  if constexpr (RD) f32_round_nearest();
 
   // LDS rows -> HBM
   for (int s = tid; s < a.n_rows; s += nth) {
@@ -824,22 +830,26 @@ float host_twist(const Schedule &sc, int64_t t) {
   return sc.dwt_ratio * host_alpha(sc, t);
 }
 
-template <int ST, int W, int EMAX, bool EXACT, bool FUSE, bool LAZY>
+template <int ST, int W, int EMAX, bool EXACT, bool FUSE, bool LAZY, bool RD = false>
 int launch_lds_k(cosm_state *s, const LdsArgs &a) {
   const size_t lds = s->shape.lds_bytes;
-  (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, W, EMAX, EXACT, FUSE, LAZY>,
+  (void)hipFuncSetAttribute((const void *)k_sweep_lds<ST, W, EMAX, EXACT, FUSE, LAZY, RD>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_sweep_lds<ST, W, EMAX, EXACT, FUSE, LAZY>), dim3(s->shape.blocks),
+  hipLaunchKernelGGL((k_sweep_lds<ST, W, EMAX, EXACT, FUSE, LAZY, RD>), dim3(s->shape.blocks),
                      dim3(s->shape.threads), lds, s->stream, a);
   return launch_check("k_sweep_lds");
 }
 
 // 16-bit float phases are wrapped at the twists only when the drift bound
-// holds (lazy16); the other formats here wrap at every update.
+// holds (lazy16); the other formats here wrap at every update.  FP32 on the
+// grid schedule takes the step's sign from the parity form (exact_grid_fp32).
 template <int ST, int W, int EMAX, bool EXACT, bool FUSE = false>
 int launch_lds(cosm_state *s, const LdsArgs &a) {
   if constexpr (ST == COSM_STORE_FP16 || ST == COSM_STORE_BF16 || ST == COSM_STORE_FP16_PK) {
     if (lazy16(*s)) return launch_lds_k<ST, W, EMAX, EXACT, FUSE, true>(s, a);
+  }
+  if constexpr (ST == COSM_STORE_FP32) {
+    if (exact_grid_fp32(*s)) return launch_lds_k<ST, W, EMAX, EXACT, FUSE, false, true>(s, a);
   }
   return launch_lds_k<ST, W, EMAX, EXACT, FUSE, false>(s, a);
 }
@@ -1156,6 +1166,10 @@ double wrap_drift_turns(const cosm_state &s) {
   const double twist_max = sc.grid ? (double)sc.twist_num2 * (double)sc.a0_units * (double)sc.tunit
                                    : (double)sc.dwt_ratio * alpha_max;
   return twist_max + (double)sc.dwt_period * alpha_max * (double)s.wdeg_max;
+}
+
+bool exact_grid_fp32(const cosm_state &s) {
+  return s.p.storage == COSM_STORE_FP32 && s.sched.grid && s.p.update == COSM_UPDATE_SCS;
 }
 
 bool lazy16(const cosm_state &s) {

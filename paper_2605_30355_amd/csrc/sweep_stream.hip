@@ -97,9 +97,11 @@ struct Slot {
   float aJ;
 };
 
-template <int ST, int W, bool JU, bool LAZY>
+template <int ST, int W, bool JU, bool LAZY, bool RD>
 __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
   static_assert(!LAZY || lazy_storage(ST), "the lazy wrap is a floating-point form");
+  static_assert(!RD || ST == COSM_STORE_FP32, "the parity step is an FP32 grid form");
+  static_assert(!LAZY || ST != COSM_STORE_FP32 || RD, "the lazy FP32 form runs on the grid");
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
@@ -216,7 +218,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       if constexpr (LAZY) {
         update_words_lazy<ST, W>(x.u, x.v, x.aJ);
       } else {
-        update_words<ST, W>(x.u, x.v, x.aJ);
+        update_words<ST, W, false, RD>(x.u, x.v, x.aJ);
       }
       row_store<W>(x.au, x.u);
       row_store<W>(x.av, x.v);
@@ -265,8 +267,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       }
     };
 
-    constexpr bool kRoundDown = LAZY && ST == COSM_STORE_FP32;
-    if constexpr (kRoundDown) f32_round_down();
+    if constexpr (RD) f32_round_down();
     for (int c = 0; c < a.C; c++) {
       // this class's slot count and last lanes, read one class ahead
       const int K = __builtin_amdgcn_readfirstlane(k_next);
@@ -279,7 +280,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       run_class(K, act_final);
       __syncthreads();
     }
-    if constexpr (kRoundDown) f32_round_nearest();
+    if constexpr (RD) f32_round_nearest();
     jsw -= (uint32_t)a.total_slots;  // the next sweep's first words are in flight
 
     // Dual window twist every `period` sweeps, after the last class: whole
@@ -328,12 +329,12 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
   }
 }
 
-template <int ST, int W, bool JU, bool LAZY>
+template <int ST, int W, bool JU, bool LAZY, bool RD>
 int launch_stream_k(cosm_state *s, const StreamArgs &a) {
   const size_t lds = s->shape.lds_bytes;
-  (void)hipFuncSetAttribute((const void *)k_sweep_stream<ST, W, JU, LAZY>,
+  (void)hipFuncSetAttribute((const void *)k_sweep_stream<ST, W, JU, LAZY, RD>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_sweep_stream<ST, W, JU, LAZY>), dim3(s->shape.blocks),
+  hipLaunchKernelGGL((k_sweep_stream<ST, W, JU, LAZY, RD>), dim3(s->shape.blocks),
                      dim3(s->shape.threads), lds, s->stream, a);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess)
@@ -341,16 +342,22 @@ int launch_stream_k(cosm_state *s, const StreamArgs &a) {
   return COSM_OK;
 }
 
-template <int ST, int W, bool LAZY>
+template <int ST, int W, bool LAZY, bool RD = false>
 int launch_stream_l(cosm_state *s, const StreamArgs &a) {
-  if (s->lds.junit) return launch_stream_k<ST, W, true, LAZY>(s, a);
-  return launch_stream_k<ST, W, false, LAZY>(s, a);
+  if (s->lds.junit) return launch_stream_k<ST, W, true, LAZY, RD>(s, a);
+  return launch_stream_k<ST, W, false, LAZY, RD>(s, a);
 }
 
+// FP32: the lazy form (grid schedule, drift bound) or, on the grid schedule,
+// the eager form with the parity step; both under round-toward-minus-infinity
 template <int ST, int W>
 int launch_stream_w(cosm_state *s, const StreamArgs &a) {
+  constexpr bool kFp32 = ST == COSM_STORE_FP32;
   if constexpr (lazy_storage(ST)) {
-    if (lds_lazy_wrap(*s)) return launch_stream_l<ST, W, true>(s, a);
+    if (lds_lazy_wrap(*s)) return launch_stream_l<ST, W, true, kFp32>(s, a);
+  }
+  if constexpr (kFp32) {
+    if (exact_grid_fp32(*s)) return launch_stream_l<ST, W, false, true>(s, a);
   }
   return launch_stream_l<ST, W, false>(s, a);
 }
