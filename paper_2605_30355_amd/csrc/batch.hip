@@ -92,10 +92,14 @@ __global__ void __launch_bounds__(256) k_batch_init(const GraphDev *graphs, cons
 }
 
 // All sweeps of one work item: nsets sets of RW replicas, set k in the LDS rows
-// [k * n, (k + 1) * n).  Lane schedule streamed one slot ahead.
-template <int ST, int W>
+// [k * n, (k + 1) * n).  Lane schedule streamed one slot ahead.  RD: every
+// graph of the run is FP32 on the grid schedule, so every operation of the
+// sweeps is exact and the step's sign comes from the parity form under
+// round-toward-minus-infinity.
+template <int ST, int W, bool RD>
 __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
   using F = Fmt<ST>;
+  static_assert(!RD || ST == COSM_STORE_FP32, "the parity step is an FP32 grid form");
   // FP16 / BF16 / FP16_PK: wrapped at the twists only when the graph's drift bound holds
   // (g.lazy, set by the host).  (FP32 on the grid could be too, exactly, but a
   // second FP32 sweep path in this kernel made the mixed stream 5 % slower.)
@@ -139,6 +143,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
 
   const uint32_t S = (uint32_t)g.S;  // at most 2^31 sweeps
   ScheduleChunk chunk;
+  if constexpr (RD) f32_round_down();
   for (uint32_t t = 1; t - 1 < S; t++) {
     if (((t - 1) & 63u) == 0u) chunk.fill(sc, t);
     float alpha, twist;
@@ -152,8 +157,9 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
         });
       } else {
         stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
-          edge_rows_sets<ST, W>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, set_bytes,
-                                nsets, alpha_s * d.J);
+          edge_rows_sets<ST, W, false, RD>(lds, (d.slots & 0xffffu) * ROWB,
+                                           (d.slots >> 16) * ROWB, set_bytes, nsets,
+                                           alpha_s * d.J);
         });
       }
     }
@@ -196,6 +202,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
       __syncthreads();
     }
   }
+  if constexpr (RD) f32_round_nearest();
 
   for (int s = tid; s < g.n * nsets; s += nth) {
     const int k = s / g.n, slot = s - k * g.n;
@@ -212,7 +219,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
   }
 }
 
-template <int ST>
+template <int ST, bool RD>
 __global__ void __launch_bounds__(kBatchThreads) k_batch_sweeps(const GraphDev *__restrict__ graphs,
                                                                 const Item *__restrict__ items,
                                                                 RunDesc *rd) {
@@ -229,9 +236,9 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_sweeps(const GraphDev *
     if (k >= n_items) break;  // every wave of the workgroup leaves together
     const Item it = items[k];
     const GraphDev g = graphs[it.graph];  // by value: its fields stay in registers
-    if (g.W == 4) item_sweeps<ST, 4>(lds, g, it);
-    else if (g.W == 2) item_sweeps<ST, 2>(lds, g, it);
-    else item_sweeps<ST, 1>(lds, g, it);
+    if (g.W == 4) item_sweeps<ST, 4, RD>(lds, g, it);
+    else if (g.W == 2) item_sweeps<ST, 2, RD>(lds, g, it);
+    else item_sweeps<ST, 1, RD>(lds, g, it);
     __syncthreads();
   }
 }
@@ -289,8 +296,10 @@ struct cosm_batch {
   RunDesc *d_run = nullptr;
   int32_t *d_run_graphs = nullptr, *d_rep_prefix = nullptr;
   int64_t *d_phase_prefix = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // the captured run, one per sweep variant (1: every graph FP32 on the grid)
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  int32_t run_rd = 0;       // the variant of the prepared run
   hipEvent_t e0 = nullptr, e1 = nullptr;
   bool graphs_dirty = true;
 };
@@ -302,16 +311,28 @@ void enqueue_run(cosm_batch *b) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->d_run);
   hipLaunchKernelGGL((k_batch_init<ST>), dim3(2048), dim3(256), 0, b->stream, b->d_graphs,
                      b->d_run, b->d_run_graphs, b->d_phase_prefix);
-  hipLaunchKernelGGL((k_batch_sweeps<ST>), dim3(b->cus), dim3(kBatchThreads), (size_t)kLdsBudget,
-                     b->stream, b->d_graphs, b->d_items, b->d_run);
+  if constexpr (ST == COSM_STORE_FP32) {
+    if (b->run_rd)
+      hipLaunchKernelGGL((k_batch_sweeps<ST, true>), dim3(b->cus), dim3(kBatchThreads),
+                         (size_t)kLdsBudget, b->stream, b->d_graphs, b->d_items, b->d_run);
+    else
+      hipLaunchKernelGGL((k_batch_sweeps<ST, false>), dim3(b->cus), dim3(kBatchThreads),
+                         (size_t)kLdsBudget, b->stream, b->d_graphs, b->d_items, b->d_run);
+  } else {
+    hipLaunchKernelGGL((k_batch_sweeps<ST, false>), dim3(b->cus), dim3(kBatchThreads),
+                       (size_t)kLdsBudget, b->stream, b->d_graphs, b->d_items, b->d_run);
+  }
   hipLaunchKernelGGL((k_batch_readout<ST>), dim3(4096), dim3(256), b->readout_lds, b->stream,
                      b->d_graphs, b->d_run, b->d_run_graphs, b->d_rep_prefix);
 }
 
 template <int ST>
 void set_attrs(cosm_batch *b) {
-  (void)hipFuncSetAttribute((const void *)k_batch_sweeps<ST>,
+  (void)hipFuncSetAttribute((const void *)k_batch_sweeps<ST, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+  if constexpr (ST == COSM_STORE_FP32)
+    (void)hipFuncSetAttribute((const void *)k_batch_sweeps<ST, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
   (void)hipFuncSetAttribute((const void *)k_batch_readout<ST>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->readout_lds);
 }
@@ -320,6 +341,10 @@ void set_attrs(cosm_batch *b) {
 // the device and synchronised, for the graphs ids (valid ids of b->graphs).
 int prepare_run(cosm_batch *b, const std::vector<int32_t> &ids, bool fill = true) {
   const int32_t count = (int32_t)ids.size();
+  // the sweep variant: the parity form when every graph is FP32 on the grid
+  b->run_rd = b->storage == COSM_STORE_FP32 ? 1 : 0;
+  for (int32_t id : ids)
+    if (!b->graphs[(size_t)id]->dev.grid) b->run_rd = 0;
   // work items: split every graph's replicas into items of up to sets_max sets,
   // shrinking the sets (fill) while the run would leave CUs without an item
   std::vector<int32_t> sets(ids.size());
@@ -364,10 +389,12 @@ int prepare_run(cosm_batch *b, const std::vector<int32_t> &ids, bool fill = true
     (void)hipFree(b->d_items);
     b->d_items = fresh;
     b->max_items = cap;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+    for (int v = 0; v < 2; v++) {
+      if (b->exec[v]) (void)hipGraphExecDestroy(b->exec[v]);
+      if (b->graph[v]) (void)hipGraphDestroy(b->graph[v]);
+      b->exec[v] = nullptr;
+      b->graph[v] = nullptr;
+    }
   }
   // largest items first (longest-processing-time order)
   std::vector<size_t> order(items.size());
@@ -583,8 +610,10 @@ int cosm_batch_destroy(cosm_batch *b) {
   clear_error();
   if (b == nullptr) return COSM_OK;
   (void)hipStreamSynchronize(b->stream);
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (int v = 0; v < 2; v++) {
+    if (b->exec[v]) (void)hipGraphExecDestroy(b->exec[v]);
+    if (b->graph[v]) (void)hipGraphDestroy(b->graph[v]);
+  }
   for (BatchGraphHost *g : b->graphs) {
     if (g->mem) (void)hipFree(g->mem);
     delete g;
@@ -803,7 +832,8 @@ int cosm_batch_run(cosm_batch *b, const int32_t *graph_ids, int32_t count) {
   for (int32_t id : ids)
     if (id < 0 || id >= (int32_t)b->graphs.size()) return set_error(COSM_EINVAL, "bad graph id");
   if (int rc = prepare_run(b, ids)) return rc;
-  if (b->exec == nullptr) {
+  const int v = b->run_rd;
+  if (b->exec[v] == nullptr) {
     COSM_HIP_CHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     switch (b->storage) {
       case COSM_STORE_FP32: enqueue_run<COSM_STORE_FP32>(b); break;
@@ -813,11 +843,11 @@ int cosm_batch_run(cosm_batch *b, const int32_t *graph_ids, int32_t count) {
       case COSM_STORE_FIX16: enqueue_run<COSM_STORE_FIX16>(b); break;
       default: enqueue_run<COSM_STORE_FIX32>(b); break;
     }
-    COSM_HIP_CHECK(hipStreamEndCapture(b->stream, &b->graph));
-    COSM_HIP_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    COSM_HIP_CHECK(hipStreamEndCapture(b->stream, &b->graph[v]));
+    COSM_HIP_CHECK(hipGraphInstantiate(&b->exec[v], b->graph[v], nullptr, nullptr, 0));
   }
   COSM_HIP_CHECK(hipEventRecord(b->e0, b->stream));
-  COSM_HIP_CHECK(hipGraphLaunch(b->exec, b->stream));
+  COSM_HIP_CHECK(hipGraphLaunch(b->exec[v], b->stream));
   COSM_HIP_CHECK(hipEventRecord(b->e1, b->stream));
   return check_launch("cosm_batch_run");
 }

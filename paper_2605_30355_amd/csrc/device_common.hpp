@@ -589,8 +589,11 @@ __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W
 // +step: for r = u that is the sign of u - v; for r = v, u - v = -(r - w) has
 // the sign bit clear exactly when r - w is not in [1, 1/2 turn].
 // FP32 arithmetic: the pair update on (w, r) when flipped, with -(r - w)
-// standing for w - r (IEEE subtraction is antisymmetric).
-template <int ST, int W>
+// standing for w - r (IEEE subtraction is antisymmetric).  RD (the grid
+// schedule, under f32_round_down): the flip folded into the parity fma's
+// factor (-2) and into the step's sign, so that D = step_by_parity on
+// (r - w) x (-1)^flip with aJ x (-1)^flip.
+template <int ST, int W, bool RD = false>
 __device__ __forceinline__ void update_reg_words(uint32_t (&r)[W], uint32_t (&w)[W], float aJ,
                                                  uint32_t flip) {
   if constexpr (ST == COSM_STORE_FIX32) {
@@ -624,9 +627,15 @@ __device__ __forceinline__ void update_reg_words(uint32_t (&r)[W], uint32_t (&w)
 #pragma unroll
     for (int k = 0; k < RW; k++) {
       const float e = xr[k] - xw[k];
-      const float f = fract1(flip ? -e : e);
-      const float dl = (f < 0.5f) ? aJ : -aJ;
-      const float D = flip ? -dl : dl;
+      float D;
+      if constexpr (RD) {
+        const float p = __builtin_fmaf(e, flip ? -2.0f : 2.0f, 12582912.0f);
+        D = __uint_as_float((__float_as_uint(p) << 31) + (__float_as_uint(aJ) ^ (flip << 31)));
+      } else {
+        const float f = fract1(flip ? -e : e);
+        const float dl = (f < 0.5f) ? aJ : -aJ;
+        D = flip ? -dl : dl;
+      }
       xr[k] = F::wrap(xr[k] - D);
       xw[k] = F::wrap(xw[k] + D);
     }

@@ -351,9 +351,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
 // in registers; lanes without an edge use dummy rows with J = 0.  The twist visits the LDS rows (all threads) and the
 // register rows (their owner), after the last class.
 // ---------------------------------------------------------------------------
-template <int ST, int W, int K, int CM, int CLASSES, bool FUSE>
+template <int ST, int W, int K, int CM, int CLASSES, bool FUSE, bool RD>
 __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
   static_assert(!FUSE || CLASSES == CM, "the fused twist needs the exact class count");
+  static_assert(!RD || ST == COSM_STORE_FP32, "the parity step is an FP32 grid form");
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
   constexpr int RW = W * F::kPerWord;
@@ -415,6 +416,8 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
   uint32_t t = (uint32_t)a.t0;
   uint32_t tw = 0;
   ScheduleChunk chunk;
+  // RD: every operation of the sweeps is exact (the grid schedule)
+  if constexpr (RD) f32_round_down();
   for (uint32_t it = 0; it < nsw; it++) {
     t++;
     if ((it & 63u) == 0u) chunk.fill(sc, t);
@@ -459,12 +462,12 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
         }
 #pragma unroll
         for (int k = 0; k < K; k++) {
-          update_reg_words<ST, W>(reg[k], w[k], alpha_s * jr[c][k], row[c][k] & 1u);
+          update_reg_words<ST, W, RD>(reg[k], w[k], alpha_s * jr[c][k], row[c][k] & 1u);
           if (last_twist) tops.apply(w[k]);
           lds_store_at<W>(lds, row[c][k] & ~1u, w[k]);
         }
         if (fon) {
-          update_words<ST, W>(pu, pv, alpha_s * jf[c]);
+          update_words<ST, W, false, RD>(pu, pv, alpha_s * jf[c]);
           if (last_twist) {
             tops.apply(pu);
             tops.apply(pv);
@@ -514,6 +517,7 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
       __syncthreads();
     }
   }
+  if constexpr (RD) f32_round_nearest();
 
   // register rows and LDS rows -> HBM
 #pragma unroll
@@ -854,14 +858,23 @@ int launch_lds(cosm_state *s, const LdsArgs &a) {
   return launch_lds_k<ST, W, EMAX, EXACT, FUSE, false>(s, a);
 }
 
-template <int ST, int W, int K, int CM, int CLASSES = 0, bool FUSE = false>
-int launch_reg(cosm_state *s, const LdsArgs &a) {
+template <int ST, int W, int K, int CM, int CLASSES, bool FUSE, bool RD>
+int launch_reg_k(cosm_state *s, const LdsArgs &a) {
   const size_t lds = s->shape.lds_bytes;
-  (void)hipFuncSetAttribute((const void *)k_sweep_reg<ST, W, K, CM, CLASSES, FUSE>,
+  (void)hipFuncSetAttribute((const void *)k_sweep_reg<ST, W, K, CM, CLASSES, FUSE, RD>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_sweep_reg<ST, W, K, CM, CLASSES, FUSE>), dim3(s->shape.blocks),
+  hipLaunchKernelGGL((k_sweep_reg<ST, W, K, CM, CLASSES, FUSE, RD>), dim3(s->shape.blocks),
                      dim3(s->shape.threads), lds, s->stream, a);
   return launch_check("k_sweep_reg");
+}
+
+// FP32 on the grid schedule: the parity step
+template <int ST, int W, int K, int CM, int CLASSES = 0, bool FUSE = false>
+int launch_reg(cosm_state *s, const LdsArgs &a) {
+  if constexpr (ST == COSM_STORE_FP32) {
+    if (exact_grid_fp32(*s)) return launch_reg_k<ST, W, K, CM, CLASSES, FUSE, true>(s, a);
+  }
+  return launch_reg_k<ST, W, K, CM, CLASSES, FUSE, false>(s, a);
 }
 
 // The register-owner form exists for the formats whose update is exact for

@@ -56,18 +56,30 @@ struct RStreamArgs {
 // difference is taken as x_u - x_v, i.e. (x_r - x_w) with its sign bit
 // flipped when r is v (IEEE subtraction is antisymmetric); the register row
 // moves by -D and the LDS row by +D, D = +-aJf.  LAZY: no wrap (FP32 phases
-// wrapped at the twists only, as in the streamed pair form).
+// wrapped at the twists only, as in the streamed pair form; the grid schedule,
+// so the sweeps run under f32_round_down and the sign comes from the parity of
+// floor(2e), the flip folded into the fma's factor -2).
 template <int ST, int W, bool LAZY>
 __device__ __forceinline__ void update_owner(uint32_t (&r)[W], uint32_t (&w)[W], float aJf,
                                              uint32_t fm) {
-  if constexpr (ST == COSM_STORE_FP32) {
+  if constexpr (ST == COSM_STORE_FP32 && LAZY) {
+    const float two = __uint_as_float(0x40000000u ^ fm);  // +-2
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      const float xr = __uint_as_float(r[k]), xw = __uint_as_float(w[k]);
+      const float p = __builtin_fmaf(xr - xw, two, 12582912.0f);
+      const float D = __uint_as_float((__float_as_uint(p) << 31) + __float_as_uint(aJf));
+      r[k] = __float_as_uint(xr - D);
+      w[k] = __float_as_uint(xw + D);
+    }
+  } else if constexpr (ST == COSM_STORE_FP32) {
 #pragma unroll
     for (int k = 0; k < W; k++) {
       const float xr = __uint_as_float(r[k]), xw = __uint_as_float(w[k]);
       const float e = __uint_as_float(__float_as_uint(xr - xw) ^ fm);
       const float D = (fract1(e) < 0.5f) ? aJf : -aJf;
-      r[k] = __float_as_uint(LAZY ? xr - D : fract1(xr - D));
-      w[k] = __float_as_uint(LAZY ? xw + D : fract1(xw + D));
+      r[k] = __float_as_uint(fract1(xr - D));
+      w[k] = __float_as_uint(fract1(xw + D));
     }
   } else {
     static_assert(!LAZY, "the lazy wrap is an FP32 form");
@@ -81,7 +93,7 @@ __device__ __forceinline__ void update_pair(uint32_t (&u)[W], uint32_t (&v)[W], 
 #pragma unroll
     for (int k = 0; k < W; k++) {
       const float xu = __uint_as_float(u[k]), xv = __uint_as_float(v[k]);
-      const float dl = (fract1(xu - xv) < 0.5f) ? aJ : -aJ;
+      const float dl = step_by_parity(xu - xv, aJ);
       u[k] = __float_as_uint(xu - dl);
       v[k] = __float_as_uint(xv + dl);
     }
@@ -184,6 +196,8 @@ __global__ void __launch_bounds__(1024) k_sweep_rstream(const RStreamArgs a) {
   uint32_t tw = 0;
   uint32_t j = 0;  // the register class whose words are in the ring
   ScheduleChunk chunk;
+  // LAZY (the grid schedule): every operation of the sweeps is exact
+  if constexpr (LAZY) f32_round_down();
   for (uint32_t it = 0; it < nsw; it++) {
     t++;
     if ((it & 63u) == 0u) chunk.fill(sc, t);
@@ -277,6 +291,7 @@ __global__ void __launch_bounds__(1024) k_sweep_rstream(const RStreamArgs a) {
       __syncthreads();
     }
   }
+  if constexpr (LAZY) f32_round_nearest();
 
   // register rows and LDS rows -> HBM
 #pragma unroll
