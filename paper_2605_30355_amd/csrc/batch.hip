@@ -143,7 +143,8 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
 
   const uint32_t S = (uint32_t)g.S;  // at most 2^31 sweeps
   ScheduleChunk chunk;
-  if constexpr (RD) f32_round_down();
+  float pm = 0.0f;  // RD: 1.5 * 2^23 from the switch, the parity fma's addend
+  if constexpr (RD) pm = f32_round_down();
   for (uint32_t t = 1; t - 1 < S; t++) {
     if (((t - 1) & 63u) == 0u) chunk.fill(sc, t);
     float alpha, twist;
@@ -159,7 +160,7 @@ __device__ void item_sweeps(uint32_t *lds, const GraphDev &g, const Item &it) {
         stream_classes(g.desc, Ks, g.C, g.total_slots, dA, dB, jslot, [&](const EdgeDesc &d) {
           edge_rows_sets<ST, W, false, RD>(lds, (d.slots & 0xffffu) * ROWB,
                                            (d.slots >> 16) * ROWB, set_bytes, nsets,
-                                           alpha_s * d.J);
+                                           alpha_s * d.J, pm);
         });
       }
     }

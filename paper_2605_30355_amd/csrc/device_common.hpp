@@ -80,18 +80,32 @@ __device__ __forceinline__ float fract1(float v) { return __builtin_amdgcn_fract
 // infinity, fma(d, 2, 1.5 * 2^23) is 1.5 * 2^23 + floor(2d) exactly for
 // |2d| < 2^22, an integer whose lowest mantissa bit is the parity of floor(2d);
 // exact sums and products do not depend on the mode.
-constexpr int kHwRegModeRoundF32 = (1 << 11) | 1;  // hwreg(HW_REG_MODE, offset 0, size 2)
-__device__ __forceinline__ void f32_round_down() { __builtin_amdgcn_s_setreg(kHwRegModeRoundF32, 2); }
+// The compiler orders no instruction against a write of MODE (neither the
+// arithmetic nor the memory accesses around s_setreg), so the switch is an asm
+// statement that also yields the constant 1.5 * 2^23: every parity fma takes
+// it as an operand and so cannot run before the switch.  The switch back is a
+// volatile asm with a memory clobber, after the loops whose stores consume the
+// parity results.  s_nop 1 gives the mode write its wait states before the
+// next vector instruction.
+__device__ __forceinline__ float f32_round_down() {
+  float m;
+  asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 0, 2), 2\n\ts_nop 1\n\t"
+               "s_mov_b32 %0, 0x4b400000"
+               : "=s"(m)
+               :
+               : "memory");
+  return m;
+}
 __device__ __forceinline__ void f32_round_nearest() {
-  __builtin_amdgcn_s_setreg(kHwRegModeRoundF32, 0);
+  asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 0, 2), 0\n\ts_nop 1" ::: "memory");
 }
 
-// Eq. (4)-(6)'s step sign on exact grid values, under f32_round_down: fract(d)
-// < 1/2 exactly when floor(2d) is even, so the step is aJ with its sign bit
-// flipped by that parity (one fma and one v_lshl_add instead of fract, compare
-// and select).
-__device__ __forceinline__ float step_by_parity(float d, float aJ) {
-  const float r = __builtin_fmaf(d, 2.0f, 12582912.0f);
+// Eq. (4)-(6)'s step sign on exact grid values, under f32_round_down (pm its
+// 1.5 * 2^23): fract(d) < 1/2 exactly when floor(2d) is even, so the step is aJ
+// with its sign bit flipped by that parity (one fma and one v_lshl_add instead
+// of fract, compare and select).
+__device__ __forceinline__ float step_by_parity(float d, float aJ, float pm) {
+  const float r = __builtin_fmaf(d, 2.0f, pm);
   return __uint_as_float((__float_as_uint(r) << 31) + __float_as_uint(aJ));
 }
 
@@ -319,7 +333,7 @@ __device__ __forceinline__ float round_h(float v) { return (float)(_Float16)v; }
 // RD (FP32 on the grid schedule, under f32_round_down): every operand and
 // result is exact, and the step's sign comes from step_by_parity.
 template <int ST, bool LAZY = false, bool RD = false>
-__device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ) {
+__device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ, float pm = 0.0f) {
   static_assert(!RD || ST == COSM_STORE_FP32, "the parity step is an FP32 grid form");
   if constexpr (ST == COSM_STORE_FP16_PK) {
     const float e = round_h(xu - xv);
@@ -333,7 +347,7 @@ __device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ) {
       xv -= __builtin_rintf(xv);
     }
   } else {
-    const float dl = RD ? step_by_parity(xu - xv, aJ) : (fract1(xu - xv) < 0.5f) ? aJ : -aJ;
+    const float dl = RD ? step_by_parity(xu - xv, aJ, pm) : (fract1(xu - xv) < 0.5f) ? aJ : -aJ;
     xu = LAZY ? xu - dl : Fmt<ST>::wrap(xu - dl);
     xv = LAZY ? xv + dl : Fmt<ST>::wrap(xv + dl);
   }
@@ -521,7 +535,8 @@ __device__ __forceinline__ void row_store(uint32_t addr, const uint32_t (&w)[W])
 // flips the step's sign.  The wrap subtracts (y + 1536) - 1536 = rint(y).
 // Other formats: unpack, the FP32 update, pack.
 template <int ST, int W, bool LAZY = false, bool RD = false>
-__device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
+__device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ,
+                                             float pm = 0.0f) {
   if constexpr (ST == COSM_STORE_FP16_PK) {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     const uint32_t sb = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)aJ);
@@ -574,7 +589,7 @@ __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W
     F::template unpack<W>(wu, xu);
     F::template unpack<W>(wv, xv);
 #pragma unroll
-    for (int k = 0; k < RW; k++) pair_update<ST, LAZY, RD>(xu[k], xv[k], aJ);
+    for (int k = 0; k < RW; k++) pair_update<ST, LAZY, RD>(xu[k], xv[k], aJ, pm);
     F::template pack<W>(xu, wu);
     F::template pack<W>(xv, wv);
   }
@@ -595,7 +610,7 @@ __device__ __forceinline__ void update_words(uint32_t (&wu)[W], uint32_t (&wv)[W
 // (r - w) x (-1)^flip with aJ x (-1)^flip.
 template <int ST, int W, bool RD = false>
 __device__ __forceinline__ void update_reg_words(uint32_t (&r)[W], uint32_t (&w)[W], float aJ,
-                                                 uint32_t flip) {
+                                                 uint32_t flip, float pm = 0.0f) {
   if constexpr (ST == COSM_STORE_FIX32) {
     const uint32_t st = (uint32_t)(int32_t)aJ, nst = 0u - st;
 #pragma unroll
@@ -629,7 +644,7 @@ __device__ __forceinline__ void update_reg_words(uint32_t (&r)[W], uint32_t (&w)
       const float e = xr[k] - xw[k];
       float D;
       if constexpr (RD) {
-        const float p = __builtin_fmaf(e, flip ? -2.0f : 2.0f, 12582912.0f);
+        const float p = __builtin_fmaf(e, flip ? -2.0f : 2.0f, pm);
         D = __uint_as_float((__float_as_uint(p) << 31) + (__float_as_uint(aJ) ^ (flip << 31)));
       } else {
         const float f = fract1(flip ? -e : e);
@@ -646,11 +661,12 @@ __device__ __forceinline__ void update_reg_words(uint32_t (&r)[W], uint32_t (&w)
 
 // Eq. (6) on every replica of one edge: rows at byte offsets bu, bv.
 template <int ST, int W, bool LAZY = false, bool RD = false>
-__device__ __forceinline__ void edge_rows(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ) {
+__device__ __forceinline__ void edge_rows(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ,
+                                          float pm = 0.0f) {
   uint32_t wu[W], wv[W];
   lds_load_at<W>(lds, bu, wu);
   lds_load_at<W>(lds, bv, wv);
-  update_words<ST, W, LAZY, RD>(wu, wv, aJ);
+  update_words<ST, W, LAZY, RD>(wu, wv, aJ, pm);
   lds_store_at<W>(lds, bu, wu);
   lds_store_at<W>(lds, bv, wv);
 }
@@ -793,11 +809,11 @@ __device__ __forceinline__ void twist_words(uint32_t (&w)[W],
 // sees the stored (rounded) phases, as a pass of its own would.
 template <int ST, int W, bool LAZY = false, bool RD = false>
 __device__ __forceinline__ void edge_rows_twist(uint32_t *lds, uint32_t bu, uint32_t bv, float aJ,
-                                                const TwistOps<ST, W> &op) {
+                                                const TwistOps<ST, W> &op, float pm = 0.0f) {
   uint32_t wu[W], wv[W];
   lds_load_at<W>(lds, bu, wu);
   lds_load_at<W>(lds, bv, wv);
-  update_words<ST, W, LAZY, RD>(wu, wv, aJ);
+  update_words<ST, W, LAZY, RD>(wu, wv, aJ, pm);
   twist_row<ST, W, LAZY>(op, wu);
   twist_row<ST, W, LAZY>(op, wv);
   lds_store_at<W>(lds, bu, wu);
@@ -841,7 +857,8 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *scratch /* >= 1
 // of the others.
 template <int ST, int W, bool LAZY = false, bool RD = false>
 __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint32_t bv,
-                                               uint32_t set_bytes, int nsets, float aJ) {
+                                               uint32_t set_bytes, int nsets, float aJ,
+                                               float pm = 0.0f) {
   int k = 0;
   for (; k + 4 <= nsets; k += 4) {
     uint32_t wu[4][W], wv[4][W];
@@ -851,7 +868,7 @@ __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint3
       lds_load_at<W>(lds, bv + (uint32_t)(k + q) * set_bytes, wv[q]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; q++) update_words<ST, W, LAZY, RD>(wu[q], wv[q], aJ);
+    for (int q = 0; q < 4; q++) update_words<ST, W, LAZY, RD>(wu[q], wv[q], aJ, pm);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       lds_store_at<W>(lds, bu + (uint32_t)(k + q) * set_bytes, wu[q]);
@@ -860,7 +877,7 @@ __device__ __forceinline__ void edge_rows_sets(uint32_t *lds, uint32_t bu, uint3
   }
   for (; k < nsets; k++)
     edge_rows<ST, W, LAZY, RD>(lds, bu + (uint32_t)k * set_bytes, bv + (uint32_t)k * set_bytes,
-                               aJ);
+                               aJ, pm);
 }
 
 // One workgroup's pass over the classes of one sweep with the lane schedule

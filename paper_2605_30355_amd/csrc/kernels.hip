@@ -159,7 +159,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   // RD: the grid schedule, on which every operation of the sweeps is exact
   // (the ramp, the twist angles and offsets, the updates and wraps), so the
   // rounding mode matters only to the step's parity fma
-  if constexpr (RD) f32_round_down();
+  float pm = 0.0f;  // RD: 1.5 * 2^23 from the switch, the parity fma's addend
+  if constexpr (RD) pm = f32_round_down();
   for (uint32_t it = 0; it < nsw; it++) {
     t++;
     if ((it & 63u) == 0u) chunk.fill(sc, t);
@@ -190,36 +191,38 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
       }
 #pragma unroll
       for (int j = 0; j < EMAX - 1; j++) {
-        edge_rows<ST, W, LAZY, RD>(lds, ua[j], va[j], alpha_s * jr[j]);
+        edge_rows<ST, W, LAZY, RD>(lds, ua[j], va[j], alpha_s * jr[j], pm);
         __syncthreads();
       }
       if (fuse_now) {
-        edge_rows_twist<ST, W, LAZY, RD>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1], op);
+        edge_rows_twist<ST, W, LAZY, RD>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1],
+                                         op, pm);
 #pragma unroll
         for (int q = 0; q < kFuseRowsMax; q++)
           if (q < a.fuse_k && fr[q] != kEmptySlot) row_twist<ST, W, LAZY>(lds, fr[q], op);
       } else {
-        edge_rows<ST, W, LAZY, RD>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1]);
+        edge_rows<ST, W, LAZY, RD>(lds, ua[EMAX - 1], va[EMAX - 1], alpha_s * jr[EMAX - 1], pm);
       }
       __syncthreads();
     } else if constexpr (EXACT) {
       // EMAX slots, one class each
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
-        edge_rows<ST, W, LAZY, RD>(lds, ua[j], va[j], alpha_s * jr[j]);
+        edge_rows<ST, W, LAZY, RD>(lds, ua[j], va[j], alpha_s * jr[j], pm);
         __syncthreads();
       }
     } else if constexpr (EMAX > 0) {
 #pragma unroll
       for (int j = 0; j < EMAX; j++) {
         if (j < a.total_slots) {
-          edge_rows<ST, W, LAZY, RD>(lds, ua[j], va[j], alpha_s * jr[j]);
+          edge_rows<ST, W, LAZY, RD>(lds, ua[j], va[j], alpha_s * jr[j], pm);
           if ((a.bar_mask >> j) & 1u) __syncthreads();
         }
       }
     } else if (a.total_slots > 0) {
       auto edge = [&](const EdgeDesc &d) {
-        edge_rows<ST, W, LAZY, RD>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB, alpha_s * d.J);
+        edge_rows<ST, W, LAZY, RD>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
+                                   alpha_s * d.J, pm);
       };
       if constexpr (FUSE) {
         // streamed form: on a twist sweep the last class twists the rows it
@@ -247,8 +250,8 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
         stream_classes(
             a.desc, Ks, a.C, a.total_slots, dA, dB, jslot, edge,
             [&](const EdgeDesc &d) {
-              edge_rows_twist<ST, W, LAZY, RD>(lds, (d.slots & 0xffffu) * ROWB, (d.slots >> 16) * ROWB,
-                                     alpha_s * d.J, op);
+              edge_rows_twist<ST, W, LAZY, RD>(lds, (d.slots & 0xffffu) * ROWB,
+                                               (d.slots >> 16) * ROWB, alpha_s * d.J, op, pm);
             },
             [&] {
               for (int q = 0; q < a.fuse_k; q++) {
@@ -417,7 +420,8 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
   uint32_t tw = 0;
   ScheduleChunk chunk;
   // RD: every operation of the sweeps is exact (the grid schedule)
-  if constexpr (RD) f32_round_down();
+  float pm = 0.0f;
+  if constexpr (RD) pm = f32_round_down();
   for (uint32_t it = 0; it < nsw; it++) {
     t++;
     if ((it & 63u) == 0u) chunk.fill(sc, t);
@@ -462,12 +466,12 @@ __global__ void __launch_bounds__(1024) k_sweep_reg(const LdsArgs a) {
         }
 #pragma unroll
         for (int k = 0; k < K; k++) {
-          update_reg_words<ST, W, RD>(reg[k], w[k], alpha_s * jr[c][k], row[c][k] & 1u);
+          update_reg_words<ST, W, RD>(reg[k], w[k], alpha_s * jr[c][k], row[c][k] & 1u, pm);
           if (last_twist) tops.apply(w[k]);
           lds_store_at<W>(lds, row[c][k] & ~1u, w[k]);
         }
         if (fon) {
-          update_words<ST, W, false, RD>(pu, pv, alpha_s * jf[c]);
+          update_words<ST, W, false, RD>(pu, pv, alpha_s * jf[c], pm);
           if (last_twist) {
             tops.apply(pu);
             tops.apply(pv);

@@ -61,13 +61,13 @@ struct RStreamArgs {
 // floor(2e), the flip folded into the fma's factor -2).
 template <int ST, int W, bool LAZY>
 __device__ __forceinline__ void update_owner(uint32_t (&r)[W], uint32_t (&w)[W], float aJf,
-                                             uint32_t fm) {
+                                             uint32_t fm, float pm) {
   if constexpr (ST == COSM_STORE_FP32 && LAZY) {
     const float two = __uint_as_float(0x40000000u ^ fm);  // +-2
 #pragma unroll
     for (int k = 0; k < W; k++) {
       const float xr = __uint_as_float(r[k]), xw = __uint_as_float(w[k]);
-      const float p = __builtin_fmaf(xr - xw, two, 12582912.0f);
+      const float p = __builtin_fmaf(xr - xw, two, pm);
       const float D = __uint_as_float((__float_as_uint(p) << 31) + __float_as_uint(aJf));
       r[k] = __float_as_uint(xr - D);
       w[k] = __float_as_uint(xw + D);
@@ -88,12 +88,13 @@ __device__ __forceinline__ void update_owner(uint32_t (&r)[W], uint32_t (&w)[W],
 }
 
 template <int ST, int W, bool LAZY>
-__device__ __forceinline__ void update_pair(uint32_t (&u)[W], uint32_t (&v)[W], float aJ) {
+__device__ __forceinline__ void update_pair(uint32_t (&u)[W], uint32_t (&v)[W], float aJ,
+                                            float pm) {
   if constexpr (LAZY) {
 #pragma unroll
     for (int k = 0; k < W; k++) {
       const float xu = __uint_as_float(u[k]), xv = __uint_as_float(v[k]);
-      const float dl = step_by_parity(xu - xv, aJ);
+      const float dl = step_by_parity(xu - xv, aJ, pm);
       u[k] = __float_as_uint(xu - dl);
       v[k] = __float_as_uint(xv + dl);
     }
@@ -197,7 +198,8 @@ __global__ void __launch_bounds__(1024) k_sweep_rstream(const RStreamArgs a) {
   uint32_t j = 0;  // the register class whose words are in the ring
   ScheduleChunk chunk;
   // LAZY (the grid schedule): every operation of the sweeps is exact
-  if constexpr (LAZY) f32_round_down();
+  float pm = 0.0f;  // LAZY: 1.5 * 2^23 from the switch, the parity fma's addend
+  if constexpr (LAZY) pm = f32_round_down();
   for (uint32_t it = 0; it < nsw; it++) {
     t++;
     if ((it & 63u) == 0u) chunk.fill(sc, t);
@@ -225,7 +227,7 @@ __global__ void __launch_bounds__(1024) k_sweep_rstream(const RStreamArgs a) {
         };
         auto rfinish = [&](int k) {
           RSlot<W> &x = rs[k & 1];
-          update_owner<ST, W, LAZY>(own[k], x.w, x.aJ, x.fm);
+          update_owner<ST, W, LAZY>(own[k], x.w, x.aJ, x.fm, pm);
           row_store<W>(x.off, x.w);
         };
         rread(0);
@@ -246,7 +248,7 @@ __global__ void __launch_bounds__(1024) k_sweep_rstream(const RStreamArgs a) {
           x.aJ = amag * (float)((int32_t)wp[p].x >> kPairJShift);
           row_load<W>(x.ou, x.u);
           row_load<W>(x.ov, x.v);
-          update_pair<ST, W, LAZY>(x.u, x.v, x.aJ);
+          update_pair<ST, W, LAZY>(x.u, x.v, x.aJ, pm);
           row_store<W>(x.ou, x.u);
           row_store<W>(x.ov, x.v);
         }

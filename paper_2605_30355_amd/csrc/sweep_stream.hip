@@ -67,7 +67,8 @@ struct StreamArgs {
 // value that has drifted to |y| in [1/2, 1) is stored with one bit less of
 // fraction (2^-11 turn for FP16, 2^-8 for BF16) until the next twist wraps it.
 template <int ST, int W>
-__device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ) {
+__device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ,
+                                                  float pm) {
   if constexpr (ST == COSM_STORE_FP16_PK) {  // packed FP16 arithmetic
     update_words<ST, W, true>(wu, wv, aJ);
     return;
@@ -80,7 +81,7 @@ __device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&
 #pragma unroll
   for (int k = 0; k < RW; k++) {
     // FP32: every value exact, the classes run toward minus infinity
-    const float dl = ST == COSM_STORE_FP32 ? step_by_parity(xu[k] - xv[k], aJ)
+    const float dl = ST == COSM_STORE_FP32 ? step_by_parity(xu[k] - xv[k], aJ, pm)
                      : (fract1(xu[k] - xv[k]) < 0.5f) ? aJ : -aJ;
     xu[k] -= dl;
     xv[k] += dl;
@@ -164,6 +165,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
 
   int32_t k_next = cls[0], last_next = cls[a.C];
   SweepSchedule sc = a.sch;
+  float pm = 0.0f;  // RD: 1.5 * 2^23 from the switch, the parity fma's addend
   const uint32_t nsw = (uint32_t)a.nsw;
   uint32_t t = (uint32_t)a.t0;
   uint32_t tw = 0;
@@ -216,9 +218,9 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
     auto finish = [&](int p) {
       Slot<W> &x = sl[p];
       if constexpr (LAZY) {
-        update_words_lazy<ST, W>(x.u, x.v, x.aJ);
+        update_words_lazy<ST, W>(x.u, x.v, x.aJ, pm);
       } else {
-        update_words<ST, W, false, RD>(x.u, x.v, x.aJ);
+        update_words<ST, W, false, RD>(x.u, x.v, x.aJ, pm);
       }
       row_store<W>(x.au, x.u);
       row_store<W>(x.av, x.v);
@@ -267,7 +269,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
       }
     };
 
-    if constexpr (RD) f32_round_down();
+    if constexpr (RD) pm = f32_round_down();
     for (int c = 0; c < a.C; c++) {
       // this class's slot count and last lanes, read one class ahead
       const int K = __builtin_amdgcn_readfirstlane(k_next);
