@@ -37,14 +37,11 @@ def functions(asm):
     return out
 
 
-@pytest.fixture(scope="module")
-def assembly(tmp_path_factory):
-    if shutil.which("hipcc") is None:
-        pytest.skip("hipcc not available")
-    d = tmp_path_factory.mktemp("asm")
+def compile_all(tmp_path):
+    """Device assembly of every source, compiled side by side."""
     procs = {}
     for src in SOURCES:
-        out = str(d / (src + ".s"))
+        out = str(tmp_path / (src + ".s"))
         procs[src] = (out, subprocess.Popen(["hipcc", *FLAGS, os.path.join(CSRC, src), "-o", out],
                                             stdout=subprocess.PIPE, stderr=subprocess.PIPE))
     result = {}
@@ -56,30 +53,32 @@ def assembly(tmp_path_factory):
     return result
 
 
-@pytest.mark.parametrize("src", SOURCES)
-def test_parity_fmas_inside_the_round_down_window(assembly, src):
+def test_parity_fmas_inside_the_round_down_window(tmp_path):
+    if shutil.which("hipcc") is None:
+        pytest.skip("hipcc not available")
     down_re = re.compile(r"s_setreg_imm32_b32 hwreg\(HW_REG_MODE, 0, 2\), 2")
     up_re = re.compile(r"s_setreg_imm32_b32 hwreg\(HW_REG_MODE, 0, 2\), 0")
     magic_re = re.compile(r"s_mov_b32 (s\d+), 0x4b400000")
-    switching = 0
-    for name, body in functions(assembly[src]):
-        if not any(down_re.search(l) for l in body):
-            assert not any(up_re.search(l) for l in body), name
-            continue
-        switching += 1
-        assert not any(l.startswith(("v_fmaak_f32", "v_fmamk_f32")) and "0x4b400000" in l
-                       for l in body), f"{name}: the addend as a literal"
-        state, sreg, n_fma = None, None, 0
-        for line in body:
-            if down_re.search(line):
-                state = "down"
-            elif up_re.search(line):
-                state = "nearest"
-            m = magic_re.search(line)
-            if m:
-                sreg = m.group(1)
-            if sreg and line.startswith("v_fma_f32") and line.endswith(", " + sreg):
-                n_fma += 1
-                assert state == "down", f"{name}: {line} outside the round-down window"
-        assert n_fma > 0, f"{name}: switches the mode but has no parity fma"
-    assert switching > 0, f"{src}: no kernel switches the rounding mode"
+    for src, asm in compile_all(tmp_path).items():
+        switching = 0
+        for name, body in functions(asm):
+            if not any(down_re.search(l) for l in body):
+                assert not any(up_re.search(l) for l in body), name
+                continue
+            switching += 1
+            assert not any(l.startswith(("v_fmaak_f32", "v_fmamk_f32")) and "0x4b400000" in l
+                           for l in body), f"{name}: the addend as a literal"
+            state, sreg, n_fma = None, None, 0
+            for line in body:
+                if down_re.search(line):
+                    state = "down"
+                elif up_re.search(line):
+                    state = "nearest"
+                m = magic_re.search(line)
+                if m:
+                    sreg = m.group(1)
+                if sreg and line.startswith("v_fma_f32") and line.endswith(", " + sreg):
+                    n_fma += 1
+                    assert state == "down", f"{name}: {line} outside the round-down window"
+            assert n_fma > 0, f"{name}: switches the mode but has no parity fma"
+        assert switching > 0, f"{src}: no kernel switches the rounding mode"
