@@ -75,6 +75,12 @@ __device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb) {
 
 __device__ __forceinline__ float fract1(float v) { return __builtin_amdgcn_fractf(v); }
 
+// The formats whose sweeps can take the parity step on the grid schedule
+// (step_by_parity): the float formats with FP32 arithmetic.
+constexpr bool parity_storage(int st) {
+  return st == COSM_STORE_FP32 || st == COSM_STORE_FP16 || st == COSM_STORE_BF16;
+}
+
 // The FP32 rounding mode of the calling wave (MODE.FP_ROUND bits 1:0; each wave
 // has its own MODE and starts in round-to-nearest-even).  Toward minus
 // infinity, fma(d, 2, 1.5 * 2^23) is 1.5 * 2^23 + floor(2d) exactly for
@@ -330,11 +336,15 @@ __device__ __forceinline__ float round_h(float v) { return (float)(_Float16)v; }
 // exact.  FP32 steps on FP16 operands give these results: an FP32 result of
 // one operation rounded again to FP16 equals its direct FP16 rounding
 // (24 >= 2 x 11 + 2 bits).
-// RD (FP32 on the grid schedule, under f32_round_down): every operand and
-// result is exact, and the step's sign comes from step_by_parity.
+// RD (the grid schedule, under f32_round_down): every FP32 operand and result
+// is exact (phases and steps are multiples of 2^-23 turn below 2 in
+// magnitude), and the step's sign comes from step_by_parity.  FP16 and BF16
+// storage take it too: their values are on the same grid, and the packed
+// conversions that round them on store follow the 16-bit rounding field of
+// MODE, not the FP32 one, so they still round to nearest even.
 template <int ST, bool LAZY = false, bool RD = false>
 __device__ __forceinline__ void pair_update(float &xu, float &xv, float aJ, float pm = 0.0f) {
-  static_assert(!RD || ST == COSM_STORE_FP32, "the parity step is an FP32 grid form");
+  static_assert(!RD || parity_storage(ST), "the parity step is a grid form of the float formats");
   if constexpr (ST == COSM_STORE_FP16_PK) {
     const float e = round_h(xu - xv);
     const float t = round_h(__builtin_fmaf(2.0f, e, -0.5f));

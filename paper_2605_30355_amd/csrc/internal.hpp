@@ -290,6 +290,10 @@ bool lazy16(const cosm_state &s);
 // step's sign from the parity of floor(2(x_u - x_v)) under round-toward-minus-
 // infinity (step_by_parity, kernels.hip, sweep_stream.hip, batch.hip).
 bool exact_grid_fp32(const cosm_state &s);
+// The same for the streamed pair form, which also takes the parity step for
+// FP16 and BF16 storage on the grid (their values are on the same grid; the
+// conversions that round them on store keep rounding to nearest even).
+bool grid_parity_step(const cosm_state &s);
 // That drift bound in turns: the largest twist plus period x the largest step
 // x the largest sum of |J| and |h| at one vertex.
 double wrap_drift_turns(const cosm_state &s);

@@ -331,7 +331,10 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
   }
   if constexpr (RD) f32_round_nearest();
 
-  // LDS rows -> HBM
+  // LDS rows -> HBM.  16-bit float phases wrapped at the twists only go back
+  // as they are (|y| < 1, within the drift bound): wrapping them here would
+  // change how later steps round them, and with it the trajectory whenever a
+  // trial is split over several calls
   for (int s = tid; s < a.n_rows; s += nth) {
     const size_t base = (size_t)a.slot_vertex[s] * a.R + r0;
     uint32_t w[W];
@@ -340,7 +343,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lds(const LdsArgs a) {
     F::template unpack<W>(w, v);
 #pragma unroll
     for (int k = 0; k < RW; k++)
-      if (k < nvalid) F::store_elem(a.phases, base + k, LAZY ? F::wrap(v[k]) : v[k]);
+      if (k < nvalid) F::store_elem(a.phases, base + k, v[k]);
   }
 }
 
@@ -1187,6 +1190,12 @@ double wrap_drift_turns(const cosm_state &s) {
 
 bool exact_grid_fp32(const cosm_state &s) {
   return s.p.storage == COSM_STORE_FP32 && s.sched.grid && s.p.update == COSM_UPDATE_SCS;
+}
+
+bool grid_parity_step(const cosm_state &s) {
+  const int32_t st = s.p.storage;
+  return (st == COSM_STORE_FP32 || st == COSM_STORE_FP16 || st == COSM_STORE_BF16) &&
+         s.sched.grid && s.p.update == COSM_UPDATE_SCS;
 }
 
 bool lazy16(const cosm_state &s) {

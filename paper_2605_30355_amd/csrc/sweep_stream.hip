@@ -66,7 +66,7 @@ struct StreamArgs {
 // wraps y - rint(y) of every update: no exactness is claimed there, and a
 // value that has drifted to |y| in [1/2, 1) is stored with one bit less of
 // fraction (2^-11 turn for FP16, 2^-8 for BF16) until the next twist wraps it.
-template <int ST, int W>
+template <int ST, int W, bool RD>
 __device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&wv)[W], float aJ,
                                                   float pm) {
   if constexpr (ST == COSM_STORE_FP16_PK) {  // packed FP16 arithmetic
@@ -80,9 +80,10 @@ __device__ __forceinline__ void update_words_lazy(uint32_t (&wu)[W], uint32_t (&
   F::template unpack<W>(wv, xv);
 #pragma unroll
   for (int k = 0; k < RW; k++) {
-    // FP32: every value exact, the classes run toward minus infinity
-    const float dl = ST == COSM_STORE_FP32 ? step_by_parity(xu[k] - xv[k], aJ, pm)
-                     : (fract1(xu[k] - xv[k]) < 0.5f) ? aJ : -aJ;
+    // RD (the grid schedule): every value exact, the classes run toward
+    // minus infinity
+    const float dl = RD ? step_by_parity(xu[k] - xv[k], aJ, pm)
+                        : (fract1(xu[k] - xv[k]) < 0.5f) ? aJ : -aJ;
     xu[k] -= dl;
     xv[k] += dl;
   }
@@ -101,7 +102,7 @@ struct Slot {
 template <int ST, int W, bool JU, bool LAZY, bool RD>
 __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
   static_assert(!LAZY || lazy_storage(ST), "the lazy wrap is a floating-point form");
-  static_assert(!RD || ST == COSM_STORE_FP32, "the parity step is an FP32 grid form");
+  static_assert(!RD || parity_storage(ST), "the parity step is a grid form of the float formats");
   static_assert(!LAZY || ST != COSM_STORE_FP32 || RD, "the lazy FP32 form runs on the grid");
   extern __shared__ uint32_t lds[];
   using F = Fmt<ST>;
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
     auto finish = [&](int p) {
       Slot<W> &x = sl[p];
       if constexpr (LAZY) {
-        update_words_lazy<ST, W>(x.u, x.v, x.aJ, pm);
+        update_words_lazy<ST, W, RD>(x.u, x.v, x.aJ, pm);
       } else {
         update_words<ST, W, false, RD>(x.u, x.v, x.aJ, pm);
       }
@@ -327,7 +328,8 @@ __global__ void __launch_bounds__(1024) k_sweep_stream(const StreamArgs a) {
     F::template unpack<W>(w, v);
 #pragma unroll
     for (int k = 0; k < RW; k++)
-      if (k < nvalid) F::store_elem(a.phases, base + k, LAZY ? F::wrap(v[k]) : v[k]);
+      if (k < nvalid)  // FP32 wraps exactly; 16-bit values go back as they are
+        F::store_elem(a.phases, base + k, LAZY && ST == COSM_STORE_FP32 ? F::wrap(v[k]) : v[k]);
   }
 }
 
@@ -350,16 +352,19 @@ int launch_stream_l(cosm_state *s, const StreamArgs &a) {
   return launch_stream_k<ST, W, false, LAZY, RD>(s, a);
 }
 
-// FP32: the lazy form (grid schedule, drift bound) or, on the grid schedule,
-// the eager form with the parity step; both under round-toward-minus-infinity
+// On the grid schedule FP32, FP16 and BF16 take the parity step (under
+// round-toward-minus-infinity), wrapped at the twists where the drift bound
+// holds (FP32 wraps lazily only on the grid), else after every update
 template <int ST, int W>
 int launch_stream_w(cosm_state *s, const StreamArgs &a) {
-  constexpr bool kFp32 = ST == COSM_STORE_FP32;
-  if constexpr (lazy_storage(ST)) {
-    if (lds_lazy_wrap(*s)) return launch_stream_l<ST, W, true, kFp32>(s, a);
+  if constexpr (parity_storage(ST)) {
+    if (grid_parity_step(*s)) {
+      if (lds_lazy_wrap(*s)) return launch_stream_l<ST, W, true, true>(s, a);
+      return launch_stream_l<ST, W, false, true>(s, a);
+    }
   }
-  if constexpr (kFp32) {
-    if (exact_grid_fp32(*s)) return launch_stream_l<ST, W, false, true>(s, a);
+  if constexpr (lazy_storage(ST) && ST != COSM_STORE_FP32) {
+    if (lds_lazy_wrap(*s)) return launch_stream_l<ST, W, true>(s, a);
   }
   return launch_stream_l<ST, W, false>(s, a);
 }

@@ -5,7 +5,10 @@ On the grid the FP32 kernels take the step's sign from the parity of
 floor(2(x_u - x_v)) under round-toward-minus-infinity; the oracle takes it from
 fract(x_u - x_v) < 1/2 in FP64.  Both must agree bit for bit on every phase
 after a few sweeps (twists included), also where the lazy wrap lets a phase
-leave [0, 1) and where the register-owner layouts flip the edge's roles."""
+leave [0, 1) and where the register-owner layouts flip the edge's roles.  FP16
+and BF16 storage (FP32 arithmetic, rounded to 16 bits on store) take the same
+step in the streamed form; there the device-memory form, which does not,
+is the reference."""
 import numpy as np
 import pytest
 
@@ -95,3 +98,34 @@ def test_streamed_pair_torus141(alpha0, lazy):
                     residency=cosm.RES_LDS, replicas_per_wg=2, threads_per_wg=1024)
     run(inst, colour, C, prob, p, 4, 7, 34,
         {"lds_form": cosm.LDS_FORM_PAIR, "streamed": 1, "lazy_wrap": lazy})
+
+
+@pytest.mark.parametrize("storage", [cosm.STORE_FP16, cosm.STORE_BF16])
+@pytest.mark.parametrize("alpha0,lazy", [(14.0, 1), (40.0, 0)], ids=["lazy", "eager"])
+def test_streamed_pair_sixteen_bit_against_device_memory_form(storage, alpha0, lazy):
+    """FP16 and BF16 storage on the grid: the streamed form takes the parity
+    step, the device-memory form compares fract(x_u - x_v) with 1/2; from the
+    same tie-laden phases both give the same phases bit for bit."""
+    inst = ci.torus(141, seed=4)
+    colour, C, _ = make(inst, cosm.COLOR_TORUS, [141, 141])
+    R, S = 8, 7
+    x0 = tie_phases(inst.n, R, 35)
+    out = {}
+    for res in (cosm.RES_LDS, cosm.RES_HBM):
+        p = cosm.Params(alpha0_deg=alpha0, sweeps_per_trial=60, dwt_ratio=0.5, dwt_period=3,
+                        storage=storage, residency=res,
+                        **({"replicas_per_wg": 4, "threads_per_wg": 1024}
+                           if res == cosm.RES_LDS else {}))
+        with cosm.State(inst.n, inst.eu, inst.ev, inst.J, colour, C, p, seed=35,
+                        replicas=R) as st:
+            st.set_phases(x0, cosm.UNIT_TURNS, 0)
+            st.sweep(1)
+            x1 = st.get_phases(cosm.UNIT_TURNS)
+            st.sweep(S - 1)
+            out[res] = (x1, st.get_phases(cosm.UNIT_TURNS), st.info())
+        say(f"[gpu] storage={storage} residency={res} lazy={out[res][2]['lazy_wrap']} "
+            f"streamed={out[res][2]['streamed']}")
+        assert out[res][2]["lazy_wrap"] == lazy
+    assert out[cosm.RES_LDS][2]["streamed"] == 1
+    assert np.array_equal(out[cosm.RES_LDS][0], out[cosm.RES_HBM][0]), "after the first sweep"
+    assert np.array_equal(out[cosm.RES_LDS][1], out[cosm.RES_HBM][1]), f"after {S} sweeps"
