@@ -38,8 +38,8 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-ops per second, non-packed FP32
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the counter
 # reads for a 256 MiB device copy (FETCH_SIZE 131087 KiB -> x2.0; WRITE_SIZE
 # 262144 KiB -> x1.0).  Valid only for the kernel sources they were taken on.
-TRAFFIC = dict(fetch_kib=1039372.3, write_kib=1286307.5, fetch_factor=2.0, write_factor=1.0,
-               sources_sha256="8c6b84bb8b0d9d4f8e231113bd6598aa5099da5c99ce335e26c98af191bb043c")
+TRAFFIC = dict(fetch_kib=1002863.8, write_kib=1295563.3, fetch_factor=2.0, write_factor=1.0,
+               sources_sha256="2fae1109e931794c28948c2b1b0b357f98e857ff7afc6988202b2461ab46c449")
 TRAFFIC_SOURCES = ('paper_2605_30355_amd/csrc/sweep_stream.hip', 'paper_2605_30355_amd/csrc/device_common.hpp', 'paper_2605_30355_amd/csrc/schedule.cpp', 'paper_2605_30355_amd/csrc/internal.hpp')
 
 
