@@ -25,10 +25,13 @@ namespace cosm {
 
 namespace {
 
-// Instance signature: sizes, storage, layout request, bias fields, and an
-// FNV-1a hash of the edge list and its colouring (the schedules are built from
-// exactly these, so two instances with the same key accept the same shapes).
-using Key = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t, uint64_t>;
+// Instance signature: sizes, storage, layout request, bias fields, the kernel
+// variant the parameters select (grid schedule: the parity step; drift bound:
+// the wrap at the twists), and an FNV-1a hash of the edge list and its
+// colouring (the schedules are built from exactly these, so two instances with
+// the same key accept the same shapes and run the same kernels).
+using Key = std::tuple<int32_t, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t,
+                       uint64_t>;
 // (W, threads, register rows (kShapeRStream: the streamed register-owner form,
 // 0: the pair form), 1 = the classic streamed schedule instead of the streamed
 // word form)
@@ -46,7 +49,9 @@ Key make_key(const cosm_state &s) {
     mix((uint32_t)s.h_ev[(size_t)k]);
     mix((uint32_t)s.h_colour[(size_t)k]);
   }
-  return Key{s.n, s.m, s.C, s.R, s.p.storage, s.p.lds_form, s.has_h ? 1 : 0, h};
+  const int32_t variant = (s.sched.grid ? 1 : 0) |
+                          (s.sched.dwt_period > 0 && wrap_drift_turns(s) < 0.5 ? 2 : 0);
+  return Key{s.n, s.m, s.C, s.R, s.p.storage, s.p.lds_form, s.has_h ? 1 : 0, variant, h};
 }
 
 
