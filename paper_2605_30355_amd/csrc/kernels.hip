@@ -17,6 +17,9 @@
 // minimum angular difference:  f = fract(x_u - x_v); s = +1 iff f < 1/2;
 // delta = alpha_t * J * s; x_u <- wrap(x_u - delta); x_v <- wrap(x_v + delta).
 // (fract(d) < 1/2 is exactly "the difference wrapped to [-1/2, 1/2) is >= 0".)
+// On the grid schedule the FP32 sweeps (RD instantiations) take s from the
+// parity of floor(2(x_u - x_v)) under round-toward-minus-infinity instead
+// (step_by_parity): the same decision for every input, in fewer instructions.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
