@@ -19,7 +19,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2605_30355_amd", "csrc")
-SOURCES = ["sweep_stream.hip", "kernels.hip", "sweep_rstream.hip", "batch.hip"]
+SOURCES = ["sweep_stream.hip", "kernels.hip", "sweep_reg.hip", "sweep_rstream.hip", "batch.hip"]
 FLAGS = ["-O3", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
          "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics", "--cuda-device-only", "-S", "-x", "hip"]
